@@ -1,0 +1,264 @@
+"""Pins of the oracle's Wald initial data and field solver (Sec. 3.3, 3.4, 4.2)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2511_17701_amd.workloads import WORKLOADS
+
+
+def c1_params(O, n, **kw):
+    w = WORKLOADS["c1_64"].scaled(n, n)
+    prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, n, n, 0.0, **kw)
+    prm.dt = O.courant_dt(prm, 0.5)
+    return prm
+
+
+# ------------------------------------------------------------- Wald solution
+
+def test_wald_discrete_divergence_free(O):
+    """B from the discrete Stokes curl of A (eq. EB-set) is divergence free to
+    round-off in every cell: Delta_i(sqrt(h) B^1) + Delta_j(sqrt(h) B^2) = 0."""
+    prm = c1_params(O, 32)
+    F = O.fields_init_wald(prm, 1.0)
+    g, n = prm.ng, 32
+    sh1 = np.zeros(prm.shape()); sh2 = np.zeros(prm.shape())
+    for i in range(-1, n + 1):
+        for j in range(0, n):
+            sh1[i + g, j + g] = O.metric_at(prm, i, j + 0.5, clamp=False)["sqrt_h"]
+        for j in range(0, n + 1):
+            sh2[i + g, j + g] = O.metric_at(prm, i + 0.5, j, clamp=False)["sqrt_h"]
+    B1, B2 = F[3], F[4]
+    div = np.zeros((n, n)); scale = 0.0
+    for i in range(0, n - 1):
+        for j in range(1, n - 1):
+            a = sh1[i + 1 + g, j + g] * B1[i + 1 + g, j + g] - sh1[i + g, j + g] * B1[i + g, j + g]
+            b = sh2[i + g, j + 1 + g] * B2[i + g, j + 1 + g] - sh2[i + g, j + g] * B2[i + g, j + g]
+            div[i, j] = a + b
+            scale = max(scale, abs(a), abs(b))
+    assert np.abs(div).max() <= 1e-13 * scale
+
+
+def test_wald_fields_are_curl_of_potential(O):
+    """Analytic B^i = eps^ijk d_j A_k / sqrt(h) (eq. EB-set) agrees with central
+    differences of the Wald potential (eq. Wald)."""
+    prm = c1_params(O, 64)
+    h = 1e-4
+    g = np.random.default_rng(8)
+    for _ in range(20):
+        x1, x2 = g.uniform(1, 63), g.uniform(2, 62)
+        D, B = O.wald_fields(prm, x1, x2, 1.7)
+        m = O.metric_at(prm, x1, x2, clamp=False)
+        dA1 = (O.wald_potential(prm, x1 + h, x2, 1.7) - O.wald_potential(prm, x1 - h, x2, 1.7)) / (2 * h)
+        dA2 = (O.wald_potential(prm, x1, x2 + h, 1.7) - O.wald_potential(prm, x1, x2 - h, 1.7)) / (2 * h)
+        ref = np.array([dA2[2], -dA1[2], -dA2[1]]) / m["sqrt_h"]
+        np.testing.assert_allclose(B, ref, rtol=1e-7, atol=1e-8 * np.abs(ref).max())
+
+
+def _aux(m, D, B):
+    """eq. aux, pointwise: E_i = alpha h_ij D^j + e_ijk beta^j B^k,
+    H_i = alpha h_ij B^j - e_ijk beta^j D^k, with beta = (beta^1, 0, 0)."""
+    al, sh, b1 = m["alpha"], m["sqrt_h"], m["beta1"]
+    hl = np.array([[m["hl11"], 0, m["hl13"]], [0, m["hl22"], 0], [m["hl13"], 0, m["hl33"]]])
+    E = al * hl @ D + sh * b1 * np.array([0.0, -B[2], B[1]])
+    H = al * hl @ B - sh * b1 * np.array([0.0, -D[2], D[1]])
+    return E, H
+
+
+def test_wald_is_stationary_vacuum(O):
+    """The Wald initial data solve the stationary vacuum Maxwell equations
+    (eq. fields with J = 0): div D = 0, curl E = 0 and curl H = 0 (checked by
+    central differences at interior points; phi components are algebraic,
+    E_3 = H_3 = 0)."""
+    prm = c1_params(O, 64)
+    g = np.random.default_rng(9)
+    h = 1e-4
+    for _ in range(20):
+        x1, x2 = g.uniform(4, 60), g.uniform(4, 60)
+
+        def at(y1, y2):
+            m = O.metric_at(prm, y1, y2, clamp=False)
+            D, B = O.wald_fields(prm, y1, y2, 1.0)
+            E, H = _aux(m, D, B)
+            return m, D, B, E, H
+
+        m, D, B, E, H = at(x1, x2)
+        sc = max(np.abs(m["sqrt_h"] * D).max(), 1e-30)
+        assert abs(E[2]) <= 1e-12 * np.abs(E).max() + 1e-14
+        assert abs(H[2]) <= 1e-11 * (abs(m["alpha"] * m["hl33"] * B[2]) +
+                                     abs(m["sqrt_h"] * m["beta1"] * D[1])) + 1e-14
+        mp, Dp, Bp, Ep, Hp = at(x1 + h, x2)
+        mm, Dm, Bm, Em, Hm = at(x1 - h, x2)
+        mq, Dq, Bq, Eq, Hq = at(x1, x2 + h)
+        mn, Dn, Bn, En, Hn = at(x1, x2 - h)
+        divD = ((mp["sqrt_h"] * Dp[0] - mm["sqrt_h"] * Dm[0]) +
+                (mq["sqrt_h"] * Dq[1] - mn["sqrt_h"] * Dn[1])) / (2 * h)
+        assert abs(divD) <= 1e-6 * sc
+        curlH3 = ((Hp[1] - Hm[1]) - (Hq[0] - Hn[0])) / (2 * h)
+        curlE3 = ((Ep[1] - Em[1]) - (Eq[0] - En[0])) / (2 * h)
+        assert abs(curlH3) <= 1e-6 * np.abs(H).max()
+        assert abs(curlE3) <= 1e-6 * np.abs(E).max() + 1e-12
+
+
+def test_wald_vacuum_stationary_second_order(O):
+    """Vacuum evolution of the Wald data by the PIC-loop field stages (Sec. 3.4):
+    away from the boundary layers (r in [6, 12] at t = 4) every component stays
+    at its initial value up to truncation error, which falls about 4x per
+    doubling of the resolution (Sec. 4.2)."""
+    devs = []
+    for n in (32, 64):
+        prm = c1_params(O, n)
+        F = O.fields_init_wald(prm, 1.0)
+        F0 = F.copy()
+        for _ in range(int(round(4.0 / prm.dt))):
+            O.field_advance(prm, F, 0)
+            O.field_advance(prm, F, 1)
+        g = prm.ng
+        dxi = math.log(prm.r_max / prm.r_min) / n
+        r = prm.r_min * np.exp((np.arange(n + 2 * g) - g) * dxi)
+        sel = (r > 6.0) & (r < 12.0)
+        devs.append([np.abs(F[c] - F0[c])[sel][:, g:g + n + 1].max() /
+                     np.abs(F0[c][sel][:, g:g + n]).max() for c in range(6)])
+    devs = np.array(devs)
+    assert devs[1].max() < 2e-2
+    assert np.all(devs[0] / devs[1] > 3.3), devs
+
+
+# ------------------------------------------------------------ Gauss's law
+
+def _run_with_particles(O, prm, steps, seed, n_pairs=1500, T=1.0):
+    F = O.fields_init_wald(prm, 1.0)
+    P = O.particles_init(prm, n_pairs, 0, T, 0, seed)
+    res0, _, _ = O.gauss_residual(prm, F, P)
+    for _ in range(steps):
+        O.step(prm, F, P)
+    res1, _, scale = O.gauss_residual(prm, F, P)
+    return F, P, res0, res1, scale
+
+
+def test_gauss_law_preserved(O):
+    """With charge deposited (kappa != 0) and no filtering, the full PIC step
+    keeps div D - 4 pi rho fixed to round-off at every interior node (Sec. 3.2:
+    the final Ampere substep uses J^{n+1/2}, and the discrete curl has zero
+    divergence)."""
+    prm = c1_params(O, 32, charge_scale=0.02)
+    F, P, res0, res1, scale = _run_with_particles(O, prm, 25, 1)
+    assert (P["tag"] == 0).sum() > 0   # some particles crossed the inner boundary
+    assert np.abs(res1 - res0).max() <= 2e-14 * scale
+
+
+def test_gauss_law_preserved_with_filter(O):
+    """With n_f = 2 filter passes (R15) the discrete divergence of the filtered
+    current equals minus the rate of the identically filtered charge, so the
+    residual stays fixed at interior nodes away from the radial boundary
+    layers and the axis rows touched by the filter's axis ghosts."""
+    prm = c1_params(O, 32, charge_scale=0.02, n_filter=2)
+    F, P, res0, res1, scale = _run_with_particles(O, prm, 20, 2)
+    d = np.abs(res1 - res0)
+    g = prm.ng
+    inner = d[g + 6:g + 32 - 6, g + 3:g + 32 - 2]
+    assert inner.max() <= 2e-14 * scale
+
+
+def test_axis_cap_charge_conservation(O):
+    """Charge balance at the axis nodes (R29): the polar-cap form of Gauss's law,
+    A_{i+1/2} D^1(i+1/2, 0) - A_{i-1/2} D^1(i-1/2, 0) + sqrt(h) D^2(i, 1/2) - 4 pi Q(i, 0)
+    (and its mirror at theta = pi), is conserved to round-off by the axis
+    D^1 update with the one-sided deposit."""
+    prm = c1_params(O, 24, charge_scale=0.05)
+    F = O.fields_init_wald(prm, 1.0)
+    # particles concentrated next to both axes
+    P = O.particles_init(prm, 800, 0, 1.0, 0, 4)
+    x2 = (P["i2"] + P["dx2"]) * 0.08
+    x2 = np.where(np.arange(len(x2)) % 4 < 2, x2, 24 - x2)
+    for s in ("", "p"):
+        P["i2" + s][:] = np.floor(x2).astype(np.int32)
+        P["dx2" + s][:] = x2 - np.floor(x2)
+    n, g = 24, prm.ng
+
+    def caps():
+        rho = O.charge(prm, P)
+        dxi = math.log(prm.r_max / prm.r_min) / n
+        dth = math.pi / n
+        out = []
+        for i in range(3, n - 2):
+            A = []
+            for ii in (i - 1, i):
+                r = prm.r_min * math.exp((ii + 0.5) * dxi)
+                ra = r * r + prm.a ** 2
+                A.append(dxi * r * ra * math.sqrt(1 + 2 * r / ra) * (1 - math.cos(0.5 * dth)))
+            s_lo = O.metric_at(prm, i, 0.5, clamp=False)["sqrt_h"]
+            s_hi = O.metric_at(prm, i, n - 0.5, clamp=False)["sqrt_h"]
+            D1, D2 = F[0], F[1]
+            lo = (A[1] * D1[i + g, g] - A[0] * D1[i - 1 + g, g] + s_lo * D2[i + g, g] -
+                  4 * math.pi * rho[i + g, g])
+            hi = (A[1] * D1[i + g, n + g] - A[0] * D1[i - 1 + g, n + g] -
+                  s_hi * D2[i + g, n - 1 + g] - 4 * math.pi * rho[i + g, n + g])
+            out.append((lo, hi))
+        return np.array(out)
+
+    c0 = caps()
+    for _ in range(15):
+        O.step(prm, F, P)
+    c1 = caps()
+    scale = np.abs(F[0:2]).max() * 1e-3 + np.abs(c0).max()
+    assert np.abs(c1 - c0).max() <= 1e-12 * scale, np.abs(c1 - c0).max() / scale
+
+
+# ------------------------------------------------------- mirror symmetry
+
+def _mirror(O, prm, F, P):
+    """Equatorial reflection theta -> pi - theta: D^1, J^1 even, D^2, J^2 odd,
+    D^3, J^3 even (true vectors); B^1, B^3 odd, B^2 even (pseudovector);
+    E_i as D, H_i as B.  Particles: x2 -> N - x2, u_2 -> -u_2."""
+    n, g = prm.n_th, prm.ng
+    Fm = np.zeros_like(F)
+    half = {0: 0, 1: 1, 2: 0}   # D/J/E components: theta-staggered?
+    halfB = {0: 1, 1: 0, 2: 1}
+    for base, kind in [(0, "D"), (3, "B"), (6, "D"), (9, "B"), (12, "D"), (15, "B"),
+                       (18, "D"), (21, "D"), (24, "D"), (27, "B"), (30, "D")]:
+        for c in range(3):
+            sgn = [1, -1, 1][c] * (-1 if kind == "B" else 1)
+            hf = (halfB if kind == "B" else half)[c]
+            src = F[base + c]
+            dst = Fm[base + c]
+            if hf:
+                dst[:, :] = sgn * src[:, ::-1][:, :]     # j -> n - 1 - j (bijective on [-g, n+g))
+            else:
+                for j in range(-1, n + 2):
+                    dst[:, j + g] = sgn * src[:, (n - j) + g]
+                dst[:, 0] = 0.0   # the j = -2 ghost of a node component is never read
+    Pm = {k: v.copy() for k, v in P.items()}
+    for s in ("", "p"):
+        x2 = n - (P["i2" + s] + P["dx2" + s])
+        f = np.floor(x2)
+        Pm["i2" + s][:] = f.astype(np.int32)
+        Pm["dx2" + s][:] = x2 - f
+    Pm["u2"][:] = -P["u2"]
+    return Fm, Pm
+
+
+def test_equatorial_mirror_symmetry(O):
+    """Kerr is symmetric under theta -> pi - theta, so the PIC step commutes with
+    the equatorial reflection (pins the orientation of the theta = pi axis update,
+    R29, and the axis parities)."""
+    prm = c1_params(O, 20, charge_scale=0.03)
+    F = O.fields_init_wald(prm, 1.0)
+    g = np.random.default_rng(12)
+    F[:12] *= 1 + 0.05 * g.normal(size=F[:12].shape)
+    P = O.particles_init(prm, 300, 0, 1.0, 0, 6)
+    Fm, Pm = _mirror(O, prm, F, P)
+    for _ in range(8):
+        O.step(prm, F, P)
+        O.step(prm, Fm, Pm)
+    Fb, Pb = _mirror(O, prm, Fm, Pm)
+    gg = prm.ng
+    for c in list(range(0, 12)) + [18, 19, 20]:
+        a = F[c][:, gg:gg + 21]
+        b = Fb[c][:, gg:gg + 21]
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * np.abs(a).max() + 1e-300)
+    alive = P["tag"] != 0
+    np.testing.assert_array_equal(P["tag"], Pb["tag"])
+    for k in ("u1", "u2", "u3"):
+        np.testing.assert_allclose(P[k][alive], Pb[k][alive], rtol=1e-10,
+                                   atol=1e-12 * np.abs(P[k]).max())
