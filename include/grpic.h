@@ -1,0 +1,179 @@
+/*
+ * grpic.h -- C ABI of libgrpic.so, the MI355X (gfx950) implementation of the
+ * data-parallel hot path of a general-relativistic particle-in-cell step
+ * (Galishnikova, Hakobyan, Philippov, Crinquand, "Entity II: General
+ * Relativistic Module").
+ *
+ * Problem (Sec. 3): particles and fields on an axisymmetric (r, theta) grid,
+ * uniform in the code coordinates x1 = ln(r / r_min) / dxi, x2 = theta / dth
+ * (App. A, quasi-spherical Kerr-Schild map with r0 = h0 = 0), in the 3+1 split
+ * of the Kerr metric of mass M and spin a (Sec. 2.1, App. A).
+ *
+ * Conventions shared by every call
+ *  - Every pointer inside grpic_fields / grpic_particles is a device pointer,
+ *    owned by the caller (the library never allocates or frees caller memory).
+ *    The library owns only what grpic_create allocates (per-context tables and
+ *    scratch), released by grpic_destroy.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work on
+ *    it and return without waiting, except where stated.
+ *  - Return value: GRPIC_OK (0) or a negative grpic_status.  Argument errors
+ *    are detected on the host before anything is enqueued; a failed kernel
+ *    launch returns GRPIC_EHIP.  grpic_last_error() gives a message for the
+ *    last failure on the calling thread.  No call throws.
+ *  - Real-valued arrays are double when the context precision is GRPIC_FP64
+ *    and float when it is GRPIC_FP32 (the precision form: int32 cell index plus
+ *    single-precision offset, momenta, fields and currents).
+ *
+ * Field storage (Sec. 3.3.1 Yee staggering, Sec. 3.4 time levels): every
+ * component is one plane of (n_r + 2 n_ghost) x (n_th + 2 n_ghost) reals,
+ * element (i, j) at (i + n_ghost) * (n_th + 2 n_ghost) + (j + n_ghost); a
+ * component staggered to i+1/2 or j+1/2 is stored at index i or j.
+ * D^1 (i+1/2, j), D^2 (i, j+1/2), D^3 (i, j); B^1 (i, j+1/2), B^2 (i+1/2, j),
+ * B^3 (i+1/2, j+1/2); E_i as D^i, H_i as B^i, J^i (conformal sqrt(h) J^i) as D^i.
+ *
+ * Particle storage (Sec. 3, code units): structure of arrays; position = cell
+ * index (i1, i2) plus offset (dx1, dx2) in [0, 1); covariant code components
+ * u_1 = u_r dr/dx1, u_2 = u_theta dth/dx2, u_3 = u_phi; previous position
+ * (i1p, i2p, dx1p, dx2p) written by the push for the deposit (Sec. 3.2).
+ * tag: 0 = empty slot, 1 = positron (q/m = +1), 2 = electron (q/m = -1),
+ * 3 = neutral test particle (q = 0); bit 0x80 = left the domain this step
+ * (deposited once more, emptied by the next push).
+ */
+#ifndef GRPIC_H
+#define GRPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GRPIC_OK = 0,
+  GRPIC_EINVAL = -1,    /* invalid argument (null pointer, size, layout) */
+  GRPIC_EHIP = -2,      /* HIP runtime error (allocation, launch)        */
+  GRPIC_ENOMEM = -3,    /* device allocation of context tables failed    */
+  GRPIC_ESTATE = -4,    /* call not valid for this context               */
+  GRPIC_ECAPACITY = -5  /* particle arrays too small for the request     */
+} grpic_status;
+
+typedef enum { GRPIC_FP64 = 0, GRPIC_FP32 = 1 } grpic_precision;
+
+typedef enum {
+  GRPIC_FIELDS_PRE_PUSH = 0,     /* Sec. 3.4 step 2: B^n for the push          */
+  GRPIC_FIELDS_POST_DEPOSIT = 1  /* Sec. 3.4 steps 5-8: B^{n+1/2}, D^{n+1}     */
+} grpic_field_stage;
+
+/* Run parameters (code units, G = c = 1). */
+typedef struct {
+  double a;             /* black-hole spin, |a| < M                          */
+  double M;             /* mass; M = 0 with a = 0 is flat space (App. A)     */
+  double r_min, r_max;  /* radial extent; r_min inside the horizon           */
+  double dt;            /* time step; <= 0: set from cfl by grpic_create     */
+  double cfl;           /* Courant number used when dt <= 0                  */
+  double small_angle;   /* theta clamp for metric evaluation (Sec. 3.3.2)   */
+  double charge_scale;  /* deposited charge per unit particle weight          */
+  int32_t n_r, n_th;    /* cells in r and theta, >= 8 each                   */
+  int32_t n_ghost;      /* ghost cells per side; must be 2                   */
+  int32_t n_iter;       /* implicit-midpoint iterations (Sec. 3.1), >= 1    */
+  int32_t n_filter;     /* current filter passes n_f (Sec. 3.3.3)            */
+  int32_t n_absorb;     /* outer absorbing-layer width in cells, >= 0        */
+  int32_t precision;    /* grpic_precision                                   */
+  int32_t reserved;     /* must be 0                                         */
+} grpic_params;
+
+/* Device pointers to the 33 field planes (Sec. 3.4 storage):
+ * D, B   = em   (D^n, B^{n-1/2});
+ * D0, B0 = em0  (D^{n-1}, B^{n-3/2} at a step boundary; B0 holds B^n after
+ *          the pre-push stage, which is what the push interpolates);
+ * E, H   = aux; J = cur (J^{n+1/2}, accumulated by the deposit);
+ * J0     = cur0 (J^{n-1/2}); Dinit, Binit = targets of the absorbing layer;
+ * T      = scratch. */
+typedef struct {
+  void *D[3], *B[3], *D0[3], *B0[3], *E[3], *H[3], *J[3], *J0[3];
+  void *Dinit[3], *Binit[3], *T[3];
+} grpic_fields;
+
+typedef struct {
+  int64_t n;            /* number of slots                                   */
+  int32_t *i1, *i2;
+  void *dx1, *dx2, *u1, *u2, *u3, *w, *phi;
+  int32_t *i1p, *i2p;
+  void *dx1p, *dx2p;
+  uint8_t *tag;
+} grpic_particles;
+
+/* Summary filled by grpic_diagnostics. */
+typedef struct {
+  int64_t n_alive[4];   /* by species tag 0..3 (index 0 unused)              */
+  int64_t n_leaving;    /* slots with the leaving bit                       */
+  int64_t n_empty;      /* tag == 0                                          */
+  int64_t n_nonfinite;  /* live slots with a non-finite offset or momentum   */
+  double sum_E[4], sum_L[4];  /* sums of E and L by species (Sec. 2.3)      */
+  double gauss_max;     /* max |div D - 4 pi rho| over the checked nodes     */
+  double gauss_scale;   /* largest single term of that residual              */
+} grpic_diag;
+
+typedef struct grpic_ctx grpic_ctx;
+
+/* Message for the last non-OK status on the calling thread. */
+const char* grpic_last_error(void);
+
+/* Creates a context for the current HIP device: validates *params, fixes dt
+ * (Courant rule when params->dt <= 0: dt = cfl / max over cell centres of the
+ * coordinate light speed sqrt((alpha sqrt(h^11) + |beta^1|)^2 + (alpha sqrt(h^22))^2)),
+ * builds the 1-D coordinate tables on the device.  Synchronous. */
+grpic_status grpic_create(const grpic_params* params, grpic_ctx** out);
+grpic_status grpic_destroy(grpic_ctx* ctx);
+/* Copies the parameters in use (dt filled in) to *out. */
+grpic_status grpic_get_params(const grpic_ctx* ctx, grpic_params* out);
+
+/* Particle loading (Sec. 4 problem setup; particles uniform in the code cell,
+ * isotropic Maxwell-Juttner momenta at temperature T in the local tetrad
+ * frame, u_i = e_i^hat u_hat, App. A tetrad).  Pairs k = 0 .. n_pairs-1 go to
+ * slots 2k (e+) and 2k+1 (e-) at one position; with ppc > 0 (even) pair k sits
+ * in cell k / (ppc/2) (cell = i1 * n_th + i2) and n_pairs = n_r n_th ppc / 2;
+ * with ppc == 0 the cell is drawn uniformly.  Then n_geo neutral bound test
+ * particles.  Random numbers: Philox4x32-10 keyed by seed.  P->n must equal
+ * 2 n_pairs + n_geo (GRPIC_ECAPACITY otherwise). */
+grpic_status grpic_particles_init(grpic_ctx* ctx, const grpic_particles* P, int64_t n_pairs,
+                                  int32_t ppc, double T, int64_t n_geo, uint64_t seed,
+                                  void* stream);
+
+/* Wald vacuum field of amplitude B0 (Sec. 4.1.2, eq. Wald): B from the
+ * discrete curl of A_mu (eq. EB-set), D from the analytic solution; fills D, B,
+ * D0, B0, Dinit, Binit, zeroes E, H, J, J0, T. */
+grpic_status grpic_fields_init_wald(grpic_ctx* ctx, const grpic_fields* F, double B0,
+                                    void* stream);
+
+/* Particle update of Sec. 3.1 (steps 1-11) for every slot: interpolate D (plane
+ * D) and B (plane B0) to x^n, EM half push in the tetrad frame, implicit
+ * geodesic momentum update, EM half push, implicit coordinate update, phi
+ * update, axis reflection and removal at the radial boundaries (Sec. 3.3.3). */
+grpic_status grpic_push(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,
+                        void* stream);
+
+/* Charge-conserving conformal current deposit (Sec. 3.2) from the previous to
+ * the current positions, added into J (the caller zeroes J; the post-deposit
+ * field stage does). */
+grpic_status grpic_deposit(grpic_ctx* ctx, const grpic_particles* P, const grpic_fields* F,
+                           void* stream);
+
+/* Field stages of the PIC loop (Sec. 3.4): stage GRPIC_FIELDS_PRE_PUSH or
+ * GRPIC_FIELDS_POST_DEPOSIT (grpic_field_stage). */
+grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t stage,
+                                 void* stream);
+
+/* Diagnostics (Sec. 2.3 conserved E, L at the time-centred position; Gauss's
+ * law Sec. 3.2).  E_out, L_out: optional device arrays of P->n reals (NaN for
+ * empty slots); gauss_res: optional device plane for the residual.  Waits for
+ * the stream; fills *out. */
+grpic_status grpic_diagnostics(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,
+                               double B0, grpic_diag* out, void* E_out, void* L_out,
+                               void* gauss_res, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRPIC_H */

@@ -116,6 +116,7 @@ def lib():
         L.orc_gauss_residual.restype = c_double
         L.orc_courant_dt.argtypes = [P, c_double]
         L.orc_courant_dt.restype = c_double
+        L.orc_num_threads.restype = c_int
         _lib = L
     return _lib
 
@@ -250,6 +251,10 @@ def gauss_residual(prm: Params, F: np.ndarray, P: dict):
     mx = lib().orc_gauss_residual(ctypes.byref(prm), _dp(F), ctypes.byref(s), _dp(res),
                                   _dp(tmp), ctypes.byref(scale))
     return res, mx, scale.value
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
 
 
 def courant_dt(prm: Params, cfl: float) -> float:

@@ -38,6 +38,9 @@
  *   particles    : structure of arrays, see orc_particles.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -87,6 +90,16 @@ static int64_t IX(const orc_params* p, int i, int j)
 }
 
 int64_t orc_plane_size(const orc_params* p) { return g_plane(p); }
+
+/* OpenMP threads the particle loop of orc_push uses */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* charge-to-mass ratio per species tag (R12): e+ = +1, e- = -1, neutral = 0 */
 static double tag_qm(uint8_t t)
@@ -632,10 +645,9 @@ static void axis_bc(const orc_params* p, double* X, int kind)
           C[IX(p, i, 0)] = 0.0;
           C[IX(p, i, nth)] = 0.0;
         }
-        for (int g = 1; g <= ng; ++g) {
-          C[IX(p, i, -g)] = par[comp] * C[IX(p, i, g)];
-          C[IX(p, i, nth + g)] = par[comp] * C[IX(p, i, nth - g)];
-        }
+        /* node rows run 0..nth: ng ghost rows below, ng - 1 above */
+        for (int g = 1; g <= ng; ++g) C[IX(p, i, -g)] = par[comp] * C[IX(p, i, g)];
+        for (int g = 1; g < ng; ++g) C[IX(p, i, nth + g)] = par[comp] * C[IX(p, i, nth - g)];
       } else {
         for (int g = 1; g <= ng; ++g) {
           C[IX(p, i, -g)] = par[comp] * C[IX(p, i, g - 1)];
@@ -906,11 +918,10 @@ static void filter_scalar(const orc_params* p, double* C, double* T)
   const int64_t pl = g_plane(p);
   const int ng = p->ng, nth = p->n_th;
   for (int pass = 0; pass < p->n_filter; ++pass) {
-    for (int i = -ng; i < p->n_r + ng; ++i)
-      for (int g = 1; g <= ng; ++g) {
-        C[IX(p, i, -g)] = C[IX(p, i, g)];
-        C[IX(p, i, nth + g)] = C[IX(p, i, nth - g)];
-      }
+    for (int i = -ng; i < p->n_r + ng; ++i) {
+      for (int g = 1; g <= ng; ++g) C[IX(p, i, -g)] = C[IX(p, i, g)];
+      for (int g = 1; g < ng; ++g) C[IX(p, i, nth + g)] = C[IX(p, i, nth - g)];
+    }
     memcpy(T, C, sizeof(double) * pl);
     for (int i = 1 - ng; i <= p->n_r + ng - 2; ++i)
       for (int j = 0; j <= nth; ++j) {

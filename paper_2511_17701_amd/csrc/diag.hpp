@@ -1,0 +1,142 @@
+// diag.hpp -- diagnostics kernels: conserved energy / angular momentum per
+// particle (Sec. 2.3), slot counts, and the Gauss-law residual (Sec. 3.2).
+#pragma once
+
+#include "init.hpp"
+
+namespace grpic {
+
+// Device accumulators: counts[0..3] alive by species, [4] leaving, [5] empty,
+// [6] non-finite; sums[0..3] E by species, [4..7] L by species; the two maxima
+// are non-negative doubles compared through their bit patterns.
+struct DiagAcc {
+  unsigned long long counts[8];
+  double sums[8];
+  unsigned long long gmax_bits, gscale_bits;
+};
+
+constexpr int kDiagBlock = 256;
+
+__global__ void __launch_bounds__(kDiagBlock)
+diag_particles_kernel(Grid g, ParticleArrays P, double B0, double* __restrict__ Eout,
+                      double* __restrict__ Lout, DiagAcc* acc) {
+  __shared__ unsigned long long sc[8][kDiagBlock / 64];
+  __shared__ double ss[8][kDiagBlock / 64];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (k < P.n) {
+    const uint8_t t = P.tag[k];
+    double E = __builtin_nan(""), L = __builtin_nan("");
+    if (t == 0) {
+      cnt[5] = 1;
+    } else if (t & kInvalid) {
+      cnt[6] = 1;
+    } else {
+      const int sp = t & kSpecies;
+      if (t & kLeaving) cnt[4] = 1; else cnt[sp] = 1;
+      const double u1 = P.u1[k], u2 = P.u2[k], u3 = P.u3[k];
+      const double d1 = P.dx1[k], d2 = P.dx2[k];
+      if (!(isfinite(u1) && isfinite(u2) && isfinite(u3) && isfinite(d1) && isfinite(d2)))
+        cnt[6] = 1;
+      const double x1 = 0.5 * (((double)P.i1p[k] + P.dx1p[k]) + ((double)P.i1[k] + d1));
+      const double x2 = 0.5 * (((double)P.i2p[k] + P.dx2p[k]) + ((double)P.i2[k] + d2));
+      const Coeffs m = coeffs_at(g, x1, x2);
+      const double th = clamp_theta(g, x2 * g.dth);
+      double s, c;
+      sincos(th, &s, &c);
+      const WaldPot w = wald_pot(g, exp(g.xi_min + x1 * g.dxi), s, c, B0);
+      const double qm = species_sign(t);
+      E = m.alpha * gamma_of(m, u1, u2, u3) - m.beta1 * u1 - qm * w.A0;
+      L = u3 + qm * w.A3;
+      if (!(t & kLeaving)) {
+        sum[sp] = E;
+        sum[4 + sp] = L;
+      }
+    }
+    if (Eout) Eout[k] = E;
+    if (Lout) Lout[k] = L;
+  }
+  // wavefront reduction, then one atomic per block and counter
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    for (int off = 32; off > 0; off >>= 1) {
+      cnt[q] += __shfl_down(cnt[q], off, 64);
+      sum[q] += __shfl_down(sum[q], off, 64);
+    }
+    if (lane == 0) {
+      sc[q][wv] = cnt[q];
+      ss[q][wv] = sum[q];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int q = threadIdx.x;
+    unsigned long long c = 0;
+    double s = 0.0;
+    for (int w = 0; w < kDiagBlock / 64; ++w) {
+      c += sc[q][w];
+      s += ss[q][w];
+    }
+    if (c) atomicAdd(&acc->counts[q], c);
+    if (s != 0.0) atomicAdd(&acc->sums[q], s);
+  }
+}
+
+// first-order charge sqrt(h) rho = sum q S at the nodes around the current positions
+__global__ void charge_kernel(Grid g, ParticleArrays P, double* __restrict__ Q) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P.n) return;
+  const uint8_t t = P.tag[k];
+  if (!is_live(t)) return;
+  const double sg = species_sign(t);
+  if (sg == 0.0) return;
+  const double q = sg * g.charge_scale * P.w[k];
+  const double w1 = P.dx1[k], w2 = P.dx2[k];
+  if (!in_deposit_range(g, P.i1[k], w1, P.i2[k], w2)) return;
+  double* p = Q + ix(g, P.i1[k], P.i2[k]);
+  atomic_add(p, q * (1.0 - w1) * (1.0 - w2));
+  atomic_add(p + 1, q * (1.0 - w1) * w2);
+  atomic_add(p + g.ld, q * w1 * (1.0 - w2));
+  atomic_add(p + g.ld + 1, q * w1 * w2);
+}
+
+// residual div D - 4 pi rho at nodes i in [n_f + 2, n_r - n_absorb), j in [1, n_th)
+__global__ void gauss_kernel(Grid g, Tables t, const double* __restrict__ D1,
+                             const double* __restrict__ D2, const double* __restrict__ Q,
+                             double* __restrict__ res, DiagAcc* acc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y + g.n_filter + 2;
+  double rmax = 0.0, smax = 0.0;
+  if (j < g.n_th && i < g.n_r - g.n_absorb) {
+    const int64_t o = ix(g, i, j);
+    const double t1 = cell_tab(g, t, i, 1, j, 0).sqrt_h * D1[o];
+    const double t2 = cell_tab(g, t, i - 1, 1, j, 0).sqrt_h * D1[o - g.ld];
+    const double t3 = cell_tab(g, t, i, 0, j, 1).sqrt_h * D2[o];
+    const double t4 = cell_tab(g, t, i, 0, j - 1, 1).sqrt_h * D2[o - 1];
+    const double t5 = 4.0 * kPi * Q[o];
+    const double r = (t1 - t2) + (t3 - t4) - t5;
+    if (res) res[o] = r;
+    rmax = fabs(r);
+    smax = fmax(fmax(fabs(t1), fabs(t2)), fmax(fmax(fabs(t3), fabs(t4)), fabs(t5)));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    rmax = fmax(rmax, __shfl_down(rmax, off, 64));
+    smax = fmax(smax, __shfl_down(smax, off, 64));
+  }
+  if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0) {
+    atomicMax(&acc->gmax_bits, (unsigned long long)__double_as_longlong(rmax));
+    atomicMax(&acc->gscale_bits, (unsigned long long)__double_as_longlong(smax));
+  }
+}
+
+// even-parity theta ghosts of a node-located scalar plane
+__global__ void scalar_axis_kernel(Grid g, double* __restrict__ C) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
+  if (i >= g.n_r + g.ng) return;
+  for (int k = 1; k <= g.ng; ++k) C[ix(g, i, -k)] = C[ix(g, i, k)];
+  for (int k = 1; k < g.ng; ++k) C[ix(g, i, g.n_th + k)] = C[ix(g, i, g.n_th - k)];
+}
+
+}  // namespace grpic

@@ -1,0 +1,190 @@
+// geometry.hpp -- grid description and Kerr-Schild 3+1 geometry in code
+// coordinates, evaluated on the device (and on the host for dt and tables).
+//
+// Code coordinates (App. A, quasi-spherical Kerr-Schild with r0 = h0 = 0):
+//   r = exp(xi_min + x1 dxi), theta = x2 dth, phi with dphi = 1.
+// Kerr-Schild 3+1 split (Sec. 2.1, App. A), with S2 = Sigma + 2 M r:
+//   Sigma = r^2 + a^2 cos^2, Delta = r^2 - 2 M r + a^2,
+//   A = (r^2 + a^2)^2 - a^2 Delta sin^2, alpha^2 = Sigma / S2,
+//   beta^r = 2 M r / S2, h^rr = A / (Sigma S2), h^rphi = a / Sigma,
+//   h^thth = 1 / Sigma, h^phiphi = 1 / (Sigma sin^2),
+//   h_rr = S2 / Sigma, h_rphi = -a (S2 / Sigma) sin^2, h_thth = Sigma,
+//   h_phiphi = A sin^2 / Sigma, sqrt(h) = Sigma sin / alpha.
+// A covariant index 1 carries a factor R = dr/dx1 = dxi r, index 2 a factor
+// dth; contravariant indices the inverse factors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace grpic {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Everything a kernel needs to know about the grid and the run, by value.
+struct Grid {
+  double a, M;
+  double xi_min, dxi, dth, inv_dth2;
+  double dt;
+  double small_angle;
+  double charge_scale;
+  int n_r, n_th, ng, ld;  // ld = n_th + 2 ng (row length of a plane)
+  int n_iter, n_filter, n_absorb;
+  int64_t plane;          // reals per plane
+};
+
+__host__ __device__ inline int64_t ix(const Grid& g, int i, int j) {
+  return (int64_t)(i + g.ng) * g.ld + (j + g.ng);
+}
+
+// Pusher coefficients at a point: lapse, shift and inverse spatial metric.
+struct Coeffs {
+  double alpha, beta1, hu11, hu22, hu33, hu13;
+};
+
+// Coefficients plus the tetrad factors of App. A at a point:
+// s11 = sqrt(h^11), s22 = sqrt(h_22), s33 = sqrt(h_33), k13 = h_13 / h_33.
+struct Frame {
+  Coeffs c;
+  double s11, s22, s33, k13;
+};
+
+// d/dx1 ([0]) and d/dx2 ([1]) of the pusher coefficients.
+struct Grad {
+  double alpha[2], beta1[2], hu11[2], hu22[2], hu33[2], hu13[2];
+};
+
+__host__ __device__ inline double clamp_theta(const Grid& g, double th) {
+  return fmin(fmax(th, g.small_angle), kPi - g.small_angle);
+}
+
+__host__ __device__ inline void sin_cos(double th, double* s, double* c) {
+#ifdef __HIP_DEVICE_COMPILE__
+  sincos(th, s, c);
+#else
+  *s = std::sin(th);
+  *c = std::cos(th);
+#endif
+}
+
+// Inverse metric, lapse and shift at code position (x1, x2), theta clamped.
+__host__ __device__ inline Coeffs coeffs_at(const Grid& g, double x1, double x2) {
+  const double r = exp(g.xi_min + x1 * g.dxi);
+  double s, c;
+  sin_cos(clamp_theta(g, x2 * g.dth), &s, &c);
+  const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r;
+  const double Sig = r2 + a2 * c * c;
+  const double S2 = Sig + tMr;
+  const double ra = r2 + a2;
+  const double A = ra * ra - a2 * (ra - tMr) * s * s;
+  const double iSig = 1.0 / Sig, iS2 = 1.0 / S2, iR = 1.0 / (g.dxi * r);
+  Coeffs m;
+  m.alpha = sqrt(Sig * iS2);
+  m.beta1 = tMr * iS2 * iR;
+  m.hu11 = A * iSig * iS2 * iR * iR;
+  m.hu13 = g.a * iSig * iR;
+  m.hu22 = iSig * g.inv_dth2;
+  m.hu33 = iSig / (s * s);
+  return m;
+}
+
+// Coefficients, tetrad factors and first derivatives at (x1, x2), theta clamped.
+__host__ __device__ inline void frame_at(const Grid& g, double x1, double x2, Frame* f, Grad* d) {
+  const double r = exp(g.xi_min + x1 * g.dxi);
+  double s, c;
+  sin_cos(clamp_theta(g, x2 * g.dth), &s, &c);
+  const double a = g.a, M = g.M;
+  const double a2 = a * a, r2 = r * r, tMr = 2.0 * M * r;
+  const double Sig = r2 + a2 * c * c;
+  const double S2 = Sig + tMr;
+  const double ra = r2 + a2;
+  const double Del = ra - tMr;
+  const double s2 = s * s;
+  const double A = ra * ra - a2 * Del * s2;
+  const double iSig = 1.0 / Sig, iS2 = 1.0 / S2;
+  const double R = g.dxi * r, iR = 1.0 / R;
+  const double alpha = sqrt(Sig * iS2);
+  const double ialpha = 1.0 / alpha;
+
+  f->c.alpha = alpha;
+  f->c.beta1 = tMr * iS2 * iR;
+  const double hrr = A * iSig * iS2;
+  f->c.hu11 = hrr * iR * iR;
+  f->c.hu13 = a * iSig * iR;
+  f->c.hu22 = iSig * g.inv_dth2;
+  const double is2 = 1.0 / s2;
+  f->c.hu33 = iSig * is2;
+  f->s11 = sqrt(hrr) * iR;
+  f->s22 = sqrt(Sig) * g.dth;
+  f->s33 = sqrt(A * iSig) * s;
+  f->k13 = -a * R * S2 / A;
+
+  // radial and polar derivatives of Sigma, A (S2 shares dSigma/dtheta)
+  const double dSig_r = 2.0 * r, dSig_t = -2.0 * a2 * s * c;
+  const double dA_r = 4.0 * r * ra - a2 * s2 * (2.0 * r - 2.0 * M);
+  const double dA_t = -2.0 * a2 * Del * s * c;
+  const double iS22 = iS2 * iS2, iSig2 = iSig * iSig;
+
+  // alpha
+  d->alpha[0] = R * M * (2.0 * r2 - Sig) * ialpha * iS22;
+  d->alpha[1] = g.dth * M * r * dSig_t * ialpha * iS22;
+  // beta^1 = beta^r / R
+  const double dbr_r = 2.0 * M * (Sig - 2.0 * r2) * iS22;
+  const double dbr_t = -tMr * dSig_t * iS22;
+  d->beta1[0] = dbr_r - g.dxi * f->c.beta1;
+  d->beta1[1] = g.dth * dbr_t * iR;
+  // h^11 = h^rr / R^2
+  const double dhrr_r = (dA_r - hrr * (dSig_r * S2 + Sig * (dSig_r + 2.0 * M))) * iSig * iS2;
+  const double dhrr_t = (dA_t - hrr * 2.0 * dSig_t * (Sig + M * r)) * iSig * iS2;
+  d->hu11[0] = dhrr_r * iR - 2.0 * g.dxi * f->c.hu11;
+  d->hu11[1] = g.dth * dhrr_t * iR * iR;
+  // h^13 = a / (Sigma R)
+  d->hu13[0] = -a * dSig_r * iSig2 - g.dxi * f->c.hu13;
+  d->hu13[1] = -g.dth * a * dSig_t * iSig2 * iR;
+  // h^22 = 1 / (Sigma dth^2)
+  d->hu22[0] = -R * dSig_r * iSig2 * g.inv_dth2;
+  d->hu22[1] = -dSig_t * iSig2 / g.dth;
+  // h^33 = 1 / (Sigma sin^2)
+  d->hu33[0] = -R * dSig_r * iSig2 * is2;
+  d->hu33[1] = -g.dth * (dSig_t + 2.0 * Sig * c / s) * iSig2 * is2;
+}
+
+// Geometry at a grid location for the field solver (theta not clamped).
+struct Cell {
+  double alpha, beta1, hl11, hl22, hl33, hl13;
+  double sqrt_h, sqrt_ht;  // sqrt(h) and sqrt(h) / sin(theta)
+};
+
+__host__ __device__ inline Cell cell_at(const Grid& g, double x1, double x2) {
+  const double r = exp(g.xi_min + x1 * g.dxi);
+  double s, c;
+  sin_cos(x2 * g.dth, &s, &c);
+  const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r;
+  const double Sig = r2 + a2 * c * c;
+  const double S2 = Sig + tMr;
+  const double ra = r2 + a2;
+  const double A = ra * ra - a2 * (ra - tMr) * s * s;
+  const double R = g.dxi * r;
+  const double iSig = 1.0 / Sig;
+  const double opz = S2 * iSig;  // 1 + z
+  Cell e;
+  e.alpha = sqrt(Sig / S2);
+  e.beta1 = tMr / (S2 * R);
+  e.hl11 = opz * R * R;
+  e.hl22 = Sig * g.dth * g.dth;
+  e.hl33 = A * s * s * iSig;
+  e.hl13 = -g.a * opz * s * s * R;
+  e.sqrt_ht = R * g.dth * Sig / e.alpha;
+  e.sqrt_h = e.sqrt_ht * s;
+  return e;
+}
+
+// gamma = sqrt(1 + h^ij u_i u_j) (Sec. 2.3, massive particles)
+__host__ __device__ inline double gamma_of(const Coeffs& m, double u1, double u2, double u3) {
+  return sqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+              2.0 * m.hu13 * u1 * u3);
+}
+
+}  // namespace grpic

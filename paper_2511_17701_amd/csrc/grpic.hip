@@ -1,0 +1,457 @@
+// grpic.hip -- C ABI of libgrpic.so (declared in include/grpic.h): argument
+// checks, per-context tables, and the launch sequences of the PIC-loop stages.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "grpic.h"
+#include "diag.hpp"
+
+using namespace grpic;
+
+struct grpic_ctx {
+  grpic_params prm;
+  Grid g;
+  int device;
+  double* tables;  // r[2], s[2], c[2], each of length n + 2 ng
+  Tables tab;
+  DiagAcc* acc;    // device accumulators for diagnostics
+  double polar_k;  // 1 - cos(dth / 2)
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+grpic_status fail(grpic_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+grpic_status fail(grpic_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(GRPIC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK(name)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = hipGetLastError();                                                      \
+    if (e_ != hipSuccess) return fail(GRPIC_EHIP, "launch %s: %s", name, hipGetErrorString(e_)); \
+  } while (0)
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+grpic_status check_ctx(const grpic_ctx* c) {
+  if (!c) return fail(GRPIC_EINVAL, "null context");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != c->device) return fail(GRPIC_ESTATE, "context made on device %d, current is %d", c->device, dev);
+  return GRPIC_OK;
+}
+
+grpic_status check_fields(const grpic_fields* F) {
+  if (!F) return fail(GRPIC_EINVAL, "null field set");
+  void* const* p = &F->D[0];
+  for (int k = 0; k < 33; ++k)
+    if (!p[k]) return fail(GRPIC_EINVAL, "field plane %d is null", k);
+  return GRPIC_OK;
+}
+
+grpic_status check_particles(const grpic_particles* P) {
+  if (!P) return fail(GRPIC_EINVAL, "null particle set");
+  if (P->n < 0) return fail(GRPIC_EINVAL, "negative particle count");
+  if (P->n == 0) return GRPIC_OK;
+  if (!P->i1 || !P->i2 || !P->dx1 || !P->dx2 || !P->u1 || !P->u2 || !P->u3 || !P->w || !P->phi ||
+      !P->i1p || !P->i2p || !P->dx1p || !P->dx2p || !P->tag)
+    return fail(GRPIC_EINVAL, "particle array pointer is null");
+  return GRPIC_OK;
+}
+
+ParticleArrays arrays(const grpic_particles* P) {
+  ParticleArrays a;
+  a.i1 = P->i1;
+  a.i2 = P->i2;
+  a.dx1 = (double*)P->dx1;
+  a.dx2 = (double*)P->dx2;
+  a.u1 = (double*)P->u1;
+  a.u2 = (double*)P->u2;
+  a.u3 = (double*)P->u3;
+  a.w = (double*)P->w;
+  a.phi = (double*)P->phi;
+  a.i1p = P->i1p;
+  a.i2p = P->i2p;
+  a.dx1p = (double*)P->dx1p;
+  a.dx2p = (double*)P->dx2p;
+  a.tag = P->tag;
+  a.n = P->n;
+  return a;
+}
+
+Tri tri(void* const p[3]) { return Tri{{(double*)p[0], (double*)p[1], (double*)p[2]}}; }
+CTri ctri(void* const p[3]) { return CTri{{(const double*)p[0], (const double*)p[1], (const double*)p[2]}}; }
+
+constexpr int kB = 256;
+inline unsigned blocks(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+// 2-D launch over an (ni x nj) range, threads along j
+inline dim3 grid2(int ni, int nj) { return dim3((nj + 63) / 64, (ni + 3) / 4); }
+const dim3 kBlock2(64, 4);
+
+const int3 kStagD1 = {1, 0, 0}, kStagD2 = {0, 1, 0};  // x1 / x2 staggering of D^i, J^i
+const int3 kStagB1 = {0, 1, 1}, kStagB2 = {1, 0, 1};  // x1 / x2 staggering of B^i
+
+// boundaries of an updated triple: horizon layer + absorbing layer, then axis
+grpic_status field_bc(grpic_ctx* c, Tri X, CTri X0, bool is_B, hipStream_t s) {
+  const Grid& g = c->g;
+  hipLaunchKernelGGL(bc_radial_kernel, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, X,
+                     X0, is_B ? kStagB1 : kStagD1);
+  LAUNCH_CHECK("bc_radial");
+  hipLaunchKernelGGL(bc_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, X,
+                     is_B ? kStagB2 : kStagD2, is_B ? 1 : 2);
+  LAUNCH_CHECK("bc_axis");
+  return GRPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* grpic_last_error(void) { return g_err.c_str(); }
+
+grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
+  if (!p || !out) return fail(GRPIC_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->precision != GRPIC_FP64)
+    return fail(GRPIC_EINVAL, "precision %d is not available in this library", p->precision);
+  if (p->n_r < 8 || p->n_th < 8) return fail(GRPIC_EINVAL, "grid %d x %d too small", p->n_r, p->n_th);
+  if (p->n_ghost != 2) return fail(GRPIC_EINVAL, "n_ghost must be 2 (got %d)", p->n_ghost);
+  if (p->n_iter < 1) return fail(GRPIC_EINVAL, "n_iter must be >= 1");
+  if (p->n_filter < 0 || p->n_absorb < 0) return fail(GRPIC_EINVAL, "negative n_filter or n_absorb");
+  if (p->n_filter + 2 >= p->n_r - p->n_absorb)
+    return fail(GRPIC_EINVAL, "boundary layers overlap (n_filter %d, n_absorb %d, n_r %d)", p->n_filter,
+                p->n_absorb, p->n_r);
+  if (!(p->r_min > 0.0) || !(p->r_max > p->r_min)) return fail(GRPIC_EINVAL, "need 0 < r_min < r_max");
+  if (!((p->M > 0.0 && std::fabs(p->a) < p->M) || (p->M == 0.0 && p->a == 0.0)))
+    return fail(GRPIC_EINVAL, "need |a| < M (or M = a = 0)");
+  if (!(p->small_angle > 0.0 && p->small_angle < 0.1)) return fail(GRPIC_EINVAL, "small_angle out of range");
+  if (p->reserved != 0) return fail(GRPIC_EINVAL, "reserved must be 0");
+  if ((int64_t)(p->n_r + 2 * p->n_ghost) * (p->n_th + 2 * p->n_ghost) > (int64_t)1 << 31)
+    return fail(GRPIC_EINVAL, "grid too large");
+
+  grpic_ctx* c = new grpic_ctx();
+  c->prm = *p;
+  Grid& g = c->g;
+  g.a = p->a;
+  g.M = p->M;
+  g.xi_min = std::log(p->r_min);
+  g.dxi = std::log(p->r_max / p->r_min) / p->n_r;
+  g.dth = kPi / p->n_th;
+  g.inv_dth2 = 1.0 / (g.dth * g.dth);
+  g.small_angle = p->small_angle;
+  g.charge_scale = p->charge_scale;
+  g.n_r = p->n_r;
+  g.n_th = p->n_th;
+  g.ng = p->n_ghost;
+  g.ld = p->n_th + 2 * p->n_ghost;
+  g.n_iter = p->n_iter;
+  g.n_filter = p->n_filter;
+  g.n_absorb = p->n_absorb;
+  g.plane = (int64_t)(p->n_r + 2 * p->n_ghost) * g.ld;
+  if (p->dt > 0.0) {
+    g.dt = p->dt;
+  } else {
+    if (!(p->cfl > 0.0)) {
+      delete c;
+      return fail(GRPIC_EINVAL, "dt <= 0 needs cfl > 0");
+    }
+    // Courant rule over the cell centres (host evaluation)
+    double vmax = 0.0;
+    for (int i = 0; i < p->n_r; ++i)
+      for (int j = 0; j < p->n_th; ++j) {
+        const Coeffs m = coeffs_at(g, i + 0.5, j + 0.5);
+        const double v1 = m.alpha * std::sqrt(m.hu11) + std::fabs(m.beta1);
+        const double v2 = m.alpha * std::sqrt(m.hu22);
+        vmax = std::fmax(vmax, std::sqrt(v1 * v1 + v2 * v2));
+      }
+    g.dt = p->cfl / vmax;
+  }
+  c->prm.dt = g.dt;
+  c->polar_k = 1.0 - std::cos(0.5 * g.dth);
+
+  hipError_t e = hipGetDevice(&c->device);
+  const int nr = p->n_r + 2 * p->n_ghost, nt = p->n_th + 2 * p->n_ghost;
+  const size_t nt_all = 2 * (size_t)nr + 4 * (size_t)nt;
+  if (e == hipSuccess) e = hipMalloc(&c->tables, nt_all * sizeof(double));
+  if (e != hipSuccess) {
+    delete c;
+    return fail(GRPIC_ENOMEM, "table allocation: %s", hipGetErrorString(e));
+  }
+  e = hipMalloc(&c->acc, sizeof(DiagAcc));
+  if (e != hipSuccess) {
+    (void)hipFree(c->tables);
+    delete c;
+    return fail(GRPIC_ENOMEM, "accumulator allocation: %s", hipGetErrorString(e));
+  }
+  double* h = new double[nt_all];
+  double* pr0 = h;
+  double* pr1 = h + nr;
+  double* ps0 = h + 2 * nr;
+  double* ps1 = ps0 + nt;
+  double* pc0 = ps1 + nt;
+  double* pc1 = pc0 + nt;
+  for (int i = 0; i < nr; ++i) {
+    pr0[i] = std::exp(g.xi_min + (double)(i - g.ng) * g.dxi);
+    pr1[i] = std::exp(g.xi_min + ((double)(i - g.ng) + 0.5) * g.dxi);
+  }
+  for (int j = 0; j < nt; ++j) {
+    const double t0 = (double)(j - g.ng) * g.dth, t1 = ((double)(j - g.ng) + 0.5) * g.dth;
+    ps0[j] = std::sin(t0);
+    pc0[j] = std::cos(t0);
+    ps1[j] = std::sin(t1);
+    pc1[j] = std::cos(t1);
+  }
+  e = hipMemcpy(c->tables, h, nt_all * sizeof(double), hipMemcpyHostToDevice);
+  delete[] h;
+  if (e != hipSuccess) {
+    (void)hipFree(c->tables);
+    (void)hipFree(c->acc);
+    delete c;
+    return fail(GRPIC_EHIP, "table upload: %s", hipGetErrorString(e));
+  }
+  c->tab.r[0] = c->tables;
+  c->tab.r[1] = c->tables + nr;
+  c->tab.s[0] = c->tables + 2 * nr;
+  c->tab.s[1] = c->tab.s[0] + nt;
+  c->tab.c[0] = c->tab.s[1] + nt;
+  c->tab.c[1] = c->tab.c[0] + nt;
+  *out = c;
+  return GRPIC_OK;
+}
+
+grpic_status grpic_destroy(grpic_ctx* c) {
+  if (!c) return GRPIC_OK;
+  (void)hipFree(c->tables);
+  (void)hipFree(c->acc);
+  delete c;
+  return GRPIC_OK;
+}
+
+grpic_status grpic_get_params(const grpic_ctx* c, grpic_params* out) {
+  if (!c || !out) return fail(GRPIC_EINVAL, "null argument");
+  *out = c->prm;
+  return GRPIC_OK;
+}
+
+grpic_status grpic_particles_init(grpic_ctx* c, const grpic_particles* P, int64_t n_pairs,
+                                  int32_t ppc, double T, int64_t n_geo, uint64_t seed, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_particles(P))) return st;
+  const Grid& g = c->g;
+  if (ppc < 0 || (ppc % 2) != 0) return fail(GRPIC_EINVAL, "ppc must be even and >= 0 (got %d)", ppc);
+  if (ppc > 0) n_pairs = (int64_t)g.n_r * g.n_th * (ppc / 2);
+  if (n_pairs < 0 || n_geo < 0) return fail(GRPIC_EINVAL, "negative counts");
+  if (!(T > 0.0)) return fail(GRPIC_EINVAL, "temperature must be > 0");
+  if (2 * n_pairs + n_geo != P->n)
+    return fail(GRPIC_ECAPACITY, "particle set has %lld slots, request needs %lld", (long long)P->n,
+                (long long)(2 * n_pairs + n_geo));
+  if (2 * n_pairs + n_geo > 0xFFFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^32 particles");
+  if (n_geo > 0 && !(std::log(6.0) > g.xi_min && std::log(15.0) < g.xi_min + g.n_r * g.dxi && g.M > 0.0))
+    return fail(GRPIC_EINVAL, "test geodesics need r in [6, 15] inside the grid and M > 0");
+  ParticleArrays a = arrays(P);
+  if (n_pairs > 0) {
+    hipLaunchKernelGGL(load_pairs_kernel, dim3(blocks(n_pairs)), dim3(kB), 0, S(stream), g, a, n_pairs,
+                       ppc, T, seed);
+    LAUNCH_CHECK("load_pairs");
+  }
+  if (n_geo > 0) {
+    hipLaunchKernelGGL(load_geodesics_kernel, dim3(blocks(n_geo)), dim3(kB), 0, S(stream), g, a,
+                       2 * n_pairs, n_geo, seed);
+    LAUNCH_CHECK("load_geodesics");
+  }
+  return GRPIC_OK;
+}
+
+grpic_status grpic_fields_init_wald(grpic_ctx* c, const grpic_fields* F, double B0, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(F))) return st;
+  const Grid& g = c->g;
+  hipStream_t s = S(stream);
+  void* const* pl = &F->D[0];
+  for (int k = 0; k < 33; ++k) {
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (double*)pl[k], 0.0);
+    LAUNCH_CHECK("fill");
+  }
+  hipLaunchKernelGGL(wald_kernel, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, c->tab,
+                     tri(F->D), tri(F->B), B0);
+  LAUNCH_CHECK("wald");
+  hipLaunchKernelGGL(bc_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, tri(F->D),
+                     kStagD2, 2);
+  LAUNCH_CHECK("bc_axis");
+  hipLaunchKernelGGL(bc_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, tri(F->B),
+                     kStagB2, 1);
+  LAUNCH_CHECK("bc_axis");
+  void* const* dst[4] = {F->D0, F->B0, F->Dinit, F->Binit};
+  void* const* src[4] = {F->D, F->B, F->D, F->B};
+  for (int k = 0; k < 4; ++k) {
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(dst[k]),
+                       ctri(src[k]));
+    LAUNCH_CHECK("copy");
+  }
+  return GRPIC_OK;
+}
+
+grpic_status grpic_push(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(F)) || (st = check_particles(P))) return st;
+  if (P->n == 0) return GRPIC_OK;
+  GatherPlanes gp;
+  for (int k = 0; k < 3; ++k) {
+    gp.D[k] = (const double*)F->D[k];
+    gp.B[k] = (const double*)F->B0[k];
+  }
+  hipLaunchKernelGGL(push_kernel, dim3(blocks(P->n)), dim3(kB), 0, S(stream), c->g, gp, arrays(P));
+  LAUNCH_CHECK("push");
+  return GRPIC_OK;
+}
+
+grpic_status grpic_deposit(grpic_ctx* c, const grpic_particles* P, const grpic_fields* F, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(F)) || (st = check_particles(P))) return st;
+  if (P->n == 0) return GRPIC_OK;
+  CurrentPlanes cp{{(double*)F->J[0], (double*)F->J[1], (double*)F->J[2]}};
+  hipLaunchKernelGGL(deposit_kernel, dim3(blocks(P->n)), dim3(kB), 0, S(stream), c->g, arrays(P), cp);
+  LAUNCH_CHECK("deposit");
+  return GRPIC_OK;
+}
+
+grpic_status grpic_field_advance(grpic_ctx* c, const grpic_fields* F, int32_t stage, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(F))) return st;
+  if (stage != GRPIC_FIELDS_PRE_PUSH && stage != GRPIC_FIELDS_POST_DEPOSIT)
+    return fail(GRPIC_EINVAL, "unknown field stage %d", stage);
+  const Grid& g = c->g;
+  hipStream_t s = S(stream);
+  const dim3 gaux = grid2(g.n_r + 2, g.n_th + 1);   // i in [-1, n_r], j in [0, n_th]
+  const dim3 gupd = grid2(g.n_r + 1, g.n_th + 1);   // i in [0, n_r],  j in [0, n_th]
+  if (stage == GRPIC_FIELDS_PRE_PUSH) {
+    hipLaunchKernelGGL(average_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->B0), ctri(F->B));
+    LAUNCH_CHECK("average");
+    hipLaunchKernelGGL(average_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->D0), ctri(F->D));
+    LAUNCH_CHECK("average");
+    hipLaunchKernelGGL(aux_e_kernel, gaux, kBlock2, 0, s, g, c->tab, ctri(F->B), ctri(F->D0), tri(F->E));
+    LAUNCH_CHECK("aux_e");
+    hipLaunchKernelGGL(faraday_kernel, gupd, kBlock2, 0, s, g, c->tab, tri(F->B0), ctri(F->E));
+    LAUNCH_CHECK("faraday");
+    return field_bc(c, tri(F->B0), ctri(F->Binit), true, s);
+  }
+  // current filter (n_f passes) on the freshly deposited J^{n+1/2}
+  for (int pass = 0; pass < g.n_filter; ++pass) {
+    hipLaunchKernelGGL(bc_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, tri(F->J),
+                       kStagD2, -1);
+    LAUNCH_CHECK("bc_axis");
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->T), ctri(F->J));
+    LAUNCH_CHECK("copy");
+    hipLaunchKernelGGL(filter_kernel, grid2(g.n_r + 2 * g.ng - 2, g.n_th + 1), kBlock2, 0, s, g,
+                       tri(F->J), ctri(F->T), kStagD2, 3);
+    LAUNCH_CHECK("filter");
+  }
+  hipLaunchKernelGGL(aux_e_kernel, gaux, kBlock2, 0, s, g, c->tab, ctri(F->B0), ctri(F->D), tri(F->E));
+  LAUNCH_CHECK("aux_e");
+  hipLaunchKernelGGL(aux_h_kernel, gaux, kBlock2, 0, s, g, c->tab, ctri(F->B0), ctri(F->D), tri(F->H));
+  LAUNCH_CHECK("aux_h");
+  hipLaunchKernelGGL(copy_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->B0), ctri(F->B));
+  LAUNCH_CHECK("copy");
+  hipLaunchKernelGGL(faraday_kernel, gupd, kBlock2, 0, s, g, c->tab, tri(F->B), ctri(F->E));
+  LAUNCH_CHECK("faraday");
+  if ((st = field_bc(c, tri(F->B), ctri(F->Binit), true, s))) return st;
+  hipLaunchKernelGGL(ampere_kernel, gupd, kBlock2, 0, s, g, c->tab, tri(F->D0), ctri(F->H), ctri(F->J0),
+                     ctri(F->J), 0.5, 0.5, c->polar_k);
+  LAUNCH_CHECK("ampere");
+  if ((st = field_bc(c, tri(F->D0), ctri(F->Dinit), false, s))) return st;
+  hipLaunchKernelGGL(aux_h_kernel, gaux, kBlock2, 0, s, g, c->tab, ctri(F->B), ctri(F->D0), tri(F->H));
+  LAUNCH_CHECK("aux_h");
+  hipLaunchKernelGGL(copy_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->D0), ctri(F->D));
+  LAUNCH_CHECK("copy");
+  hipLaunchKernelGGL(ampere_kernel, gupd, kBlock2, 0, s, g, c->tab, tri(F->D), ctri(F->H), ctri(F->J),
+                     ctri(F->J), 1.0, 0.0, c->polar_k);
+  LAUNCH_CHECK("ampere");
+  if ((st = field_bc(c, tri(F->D), ctri(F->Dinit), false, s))) return st;
+  hipLaunchKernelGGL(rotate_currents_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->J0),
+                     tri(F->J));
+  LAUNCH_CHECK("rotate_currents");
+  return GRPIC_OK;
+}
+
+grpic_status grpic_diagnostics(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, double B0,
+                               grpic_diag* out, void* E_out, void* L_out, void* gauss_res, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(F)) || (st = check_particles(P))) return st;
+  if (!out) return fail(GRPIC_EINVAL, "null output");
+  const Grid& g = c->g;
+  hipStream_t s = S(stream);
+  HIP_TRY(hipMemsetAsync(c->acc, 0, sizeof(DiagAcc), s));
+  if (P->n > 0) {
+    hipLaunchKernelGGL(diag_particles_kernel, dim3(blocks(P->n)), dim3(kDiagBlock), 0, s, g, arrays(P), B0,
+                       (double*)E_out, (double*)L_out, c->acc);
+    LAUNCH_CHECK("diag_particles");
+  }
+  // Gauss residual: charge into T[0], filtered like the currents (T[1] scratch)
+  double* Q = (double*)F->T[0];
+  double* tmp = (double*)F->T[1];
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, Q, 0.0);
+  LAUNCH_CHECK("fill");
+  if (P->n > 0) {
+    hipLaunchKernelGGL(charge_kernel, dim3(blocks(P->n)), dim3(kB), 0, s, g, arrays(P), Q);
+    LAUNCH_CHECK("charge");
+  }
+  for (int pass = 0; pass < g.n_filter; ++pass) {
+    hipLaunchKernelGGL(scalar_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, Q);
+    LAUNCH_CHECK("scalar_axis");
+    HIP_TRY(hipMemcpyAsync(tmp, Q, g.plane * sizeof(double), hipMemcpyDeviceToDevice, s));
+    Tri X{{Q, nullptr, nullptr}};
+    CTri Sv{{tmp, nullptr, nullptr}};
+    hipLaunchKernelGGL(filter_kernel, grid2(g.n_r + 2 * g.ng - 2, g.n_th + 1), kBlock2, 0, s, g, X, Sv,
+                       int3{0, 0, 0}, 1);
+    LAUNCH_CHECK("filter");
+  }
+  if (gauss_res) {
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (double*)gauss_res, 0.0);
+    LAUNCH_CHECK("fill");
+  }
+  const int ni = g.n_r - g.n_absorb - (g.n_filter + 2), nj = g.n_th - 1;
+  if (ni > 0 && nj > 0) {
+    hipLaunchKernelGGL(gauss_kernel, grid2(ni, nj), kBlock2, 0, s, g, c->tab, (const double*)F->D[0],
+                       (const double*)F->D[1], (const double*)Q, (double*)gauss_res, c->acc);
+    LAUNCH_CHECK("gauss");
+  }
+  DiagAcc h;
+  HIP_TRY(hipMemcpyAsync(&h, c->acc, sizeof(DiagAcc), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < 4; ++k) {
+    out->n_alive[k] = (int64_t)h.counts[k];
+    out->sum_E[k] = h.sums[k];
+    out->sum_L[k] = h.sums[4 + k];
+  }
+  out->n_leaving = (int64_t)h.counts[4];
+  out->n_empty = (int64_t)h.counts[5];
+  out->n_nonfinite = (int64_t)h.counts[6];
+  double gm, gs;
+  std::memcpy(&gm, &h.gmax_bits, sizeof gm);
+  std::memcpy(&gs, &h.gscale_bits, sizeof gs);
+  out->gauss_max = gm;
+  out->gauss_scale = gs;
+  return GRPIC_OK;
+}
+
+}  // extern "C"
