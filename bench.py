@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--workload", default="c2_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--sort-every", type=int, default=10,
+                    help="cell-sort the particles every k steps (0: never)")
     return ap.parse_args()
 
 
@@ -90,11 +92,14 @@ def main():
     ctx.fields_init_wald(F, w.B0)
     P = ctx.new_particles(w.n_particles, dev)
     ctx.particles_init(P, w.n_pairs_total if w.ppc == 0 else 0, w.ppc, w.T, w.n_geo, w.seed)
+    Q = ctx.new_particles(w.n_particles, dev) if ARGS.sort_every > 0 else None
+    state = {"P": P, "Q": Q, "n": 0}
     torch.cuda.synchronize()
     d0 = ctx.diagnostics(F, P, w.B0)
     live0 = sum(d0["n_alive"])
 
     def step(ev=None):
+        P = state["P"]
         if w.full_step:
             ctx.field_advance(F, grpic.PRE_PUSH)
         if ev is not None:
@@ -107,6 +112,10 @@ def main():
             ev[2].record()
         if w.full_step:
             ctx.field_advance(F, grpic.POST_DEPOSIT)
+        state["n"] += 1
+        if ARGS.sort_every > 0 and state["n"] % ARGS.sort_every == 0:
+            ctx.sort(state["P"], state["Q"])
+            state["P"], state["Q"] = state["Q"], state["P"]
 
     for _ in range(ARGS.warmup):
         step()
@@ -123,6 +132,7 @@ def main():
     total_ms = t_start.elapsed_time(t_end)
     push_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / ARGS.steps
     dep_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / ARGS.steps
+    P = state["P"]
     d1 = ctx.diagnostics(F, P, w.B0)
     live1 = sum(d1["n_alive"])
     assert d1["n_nonfinite"] == 0, "non-finite particles after the run"
@@ -146,7 +156,8 @@ def main():
         "config": {"workload": w.name, "grid": f"{w.n_r}x{w.n_th}", "a": w.a,
                    "r_range": [w.r_min, w.r_max], "particles": w.n_particles, "ppc": w.ppc,
                    "test_geodesics": w.n_geo, "T": w.T, "B0": w.B0, "n_iter": w.n_iter,
-                   "dt": ctx.dt, "full_step": w.full_step, "precision": w.precision},
+                   "dt": ctx.dt, "full_step": w.full_step, "precision": w.precision,
+                   "sort_every": ARGS.sort_every},
         "roofline": {"bound": "hbm", "kernel": "push_kernel", "achieved": push_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": push_gbs / HBM_PEAK_GBS,
                      "traffic": None,

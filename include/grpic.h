@@ -37,7 +37,10 @@
  * (i1p, i2p, dx1p, dx2p) written by the push for the deposit (Sec. 3.2).
  * tag: 0 = empty slot, 1 = positron (q/m = +1), 2 = electron (q/m = -1),
  * 3 = neutral test particle (q = 0); bit 0x80 = left the domain this step
- * (deposited once more, emptied by the next push).
+ * (deposited once more, emptied by the next push); tag 0x40 = dropped by a
+ * bounds guard (a position outside the grid or a move of a cell or more,
+ * which the deposit cannot represent), never used again and counted as
+ * non-finite by grpic_diagnostics.
  */
 #ifndef GRPIC_H
 #define GRPIC_H
@@ -163,6 +166,16 @@ grpic_status grpic_deposit(grpic_ctx* ctx, const grpic_particles* P, const grpic
  * GRPIC_FIELDS_POST_DEPOSIT (grpic_field_stage). */
 grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t stage,
                                  void* stream);
+
+/* Cell sort (a layout device, not part of the paper's method): writes the
+ * slots of src into dst ordered by cell c = i1 * n_th + i2; empty slots and
+ * slots with the leaving bit (already deposited) go last, emptied (tag 0).
+ * The order of particles within one cell is unspecified.  src and dst must
+ * have the same n and must not alias.  If n_live is non-null, waits for the
+ * stream and stores the number of live slots (they occupy dst[0 .. n_live)).
+ * Uses scratch owned by the context (n_r n_th + 1 counters). */
+grpic_status grpic_sort(grpic_ctx* ctx, const grpic_particles* src, const grpic_particles* dst,
+                        int64_t* n_live, void* stream);
 
 /* Diagnostics (Sec. 2.3 conserved E, L at the time-centred position; Gauss's
  * law Sec. 3.2).  E_out, L_out: optional device arrays of P->n reals (NaN for

@@ -117,6 +117,8 @@ def lib():
         L.orc_courant_dt.argtypes = [P, c_double]
         L.orc_courant_dt.restype = c_double
         L.orc_num_threads.restype = c_int
+        L.orc_wald_potential_planes.argtypes = [P, c_double, D, D]
+        L.orc_sqrt_h_plane.argtypes = [P, c_int, c_int, D]
         _lib = L
     return _lib
 
@@ -251,6 +253,20 @@ def gauss_residual(prm: Params, F: np.ndarray, P: dict):
     mx = lib().orc_gauss_residual(ctypes.byref(prm), _dp(F), ctypes.byref(s), _dp(res),
                                   _dp(tmp), ctypes.byref(scale))
     return res, mx, scale.value
+
+
+def wald_potential_planes(prm: Params, B0: float):
+    """(A_1 at r-edges, A_3 at nodes) as planes; test error bounds only."""
+    A1 = np.zeros(prm.shape())
+    A3 = np.zeros(prm.shape())
+    lib().orc_wald_potential_planes(ctypes.byref(prm), B0, _dp(A1), _dp(A3))
+    return A1, A3
+
+
+def sqrt_h_plane(prm: Params, o1: int, o2: int) -> np.ndarray:
+    out = np.zeros(prm.shape())
+    lib().orc_sqrt_h_plane(ctypes.byref(prm), o1, o2, _dp(out))
+    return out
 
 
 def num_threads() -> int:

@@ -625,6 +625,31 @@ void orc_wald_fields(const orc_params* p, double x1, double x2, double B0, doubl
   D[2] = (m.hu13 * X1 + m.hu33 * X3) / m.alpha;
 }
 
+/* Wald potential planes for error bounds in tests: A_1 (code) at r-edges
+ * (i+1/2, j) stored at (i, j), A_3 at nodes (i, j); every stored point. */
+void orc_wald_potential_planes(const orc_params* p, double B0, double* A1, double* A3)
+{
+  for (int i = -p->ng; i < p->n_r + p->ng; ++i)
+    for (int j = -p->ng; j < p->n_th + p->ng; ++j) {
+      double a[3];
+      orc_wald_potential(p, i + 0.5, j, B0, a);
+      A1[IX(p, i, j)] = a[1];
+      orc_wald_potential(p, i, j, B0, a);
+      A3[IX(p, i, j)] = a[2];
+    }
+}
+
+/* sqrt(h) at every stored point of a plane staggered by (o1, o2) half cells */
+void orc_sqrt_h_plane(const orc_params* p, int o1, int o2, double* out)
+{
+  for (int i = -p->ng; i < p->n_r + p->ng; ++i)
+    for (int j = -p->ng; j < p->n_th + p->ng; ++j) {
+      orc_metric m;
+      orc_metric_at(p, i + 0.5 * o1, j + 0.5 * o2, 0, &m);
+      out[IX(p, i, j)] = m.sqrt_h;
+    }
+}
+
 /* ------------------------------------------------------ field boundaries */
 
 /* axis reflection (Sec. 3.3.3, figure of the staggering): r-components even,

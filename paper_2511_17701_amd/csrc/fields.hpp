@@ -9,13 +9,6 @@
 
 namespace grpic {
 
-// 1-D coordinate tables, indexed by (index + ng); [0] integer, [1] half-integer.
-struct Tables {
-  const double* __restrict__ r[2];
-  const double* __restrict__ s[2];
-  const double* __restrict__ c[2];
-};
-
 __device__ inline Cell cell_tab(const Grid& g, const Tables& t, int i, int o1, int j, int o2) {
   const double r = t.r[o1][i + g.ng];
   const double s = t.s[o2][j + g.ng], c = t.c[o2][j + g.ng];

@@ -30,14 +30,24 @@ struct Grid {
   double dt;
   double small_angle;
   double charge_scale;
+  // sin, cos of the clamped polar angles small_angle and pi - small_angle
+  double sin_lo, cos_lo, sin_hi, cos_hi;
   int n_r, n_th, ng, ld;  // ld = n_th + 2 ng (row length of a plane)
   int n_iter, n_filter, n_absorb;
+  int fast;               // offsets small enough for the polynomial path
   int64_t plane;          // reals per plane
 };
 
 __host__ __device__ inline int64_t ix(const Grid& g, int i, int j) {
   return (int64_t)(i + g.ng) * g.ld + (j + g.ng);
 }
+
+// 1-D coordinate tables, indexed by (index + ng); [0] integer, [1] half-integer.
+struct Tables {
+  const double* __restrict__ r[2];
+  const double* __restrict__ s[2];
+  const double* __restrict__ c[2];
+};
 
 // Pusher coefficients at a point: lapse, shift and inverse spatial metric.
 struct Coeffs {
@@ -56,6 +66,11 @@ struct Grad {
   double alpha[2], beta1[2], hu11[2], hu22[2], hu33[2], hu13[2];
 };
 
+// r, sin(theta), cos(theta) of a point
+struct RSC {
+  double r, s, c;
+};
+
 __host__ __device__ inline double clamp_theta(const Grid& g, double th) {
   return fmin(fmax(th, g.small_angle), kPi - g.small_angle);
 }
@@ -69,32 +84,73 @@ __host__ __device__ inline void sin_cos(double th, double* s, double* c) {
 #endif
 }
 
-// Inverse metric, lapse and shift at code position (x1, x2), theta clamped.
-__host__ __device__ inline Coeffs coeffs_at(const Grid& g, double x1, double x2) {
-  const double r = exp(g.xi_min + x1 * g.dxi);
-  double s, c;
-  sin_cos(clamp_theta(g, x2 * g.dth), &s, &c);
+// 1/x and 1/sqrt(x) for positive normal x: hardware seeds refined by two
+// Newton steps on the device (error ~1 ulp), plain division on the host.
+__host__ __device__ inline double rcp(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+#else
+  return 1.0 / x;
+#endif
+}
+
+__host__ __device__ inline double rsqrt(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+#else
+  return 1.0 / std::sqrt(x);
+#endif
+}
+
+// r and clamped sin/cos by the library functions
+__host__ __device__ inline RSC rsc_direct(const Grid& g, double x1, double x2) {
+  RSC p;
+  p.r = exp(g.xi_min + x1 * g.dxi);
+  sin_cos(clamp_theta(g, x2 * g.dth), &p.s, &p.c);
+  return p;
+}
+
+// Inverse metric, lapse and shift at a point (R = dxi r).
+__host__ __device__ inline Coeffs coeffs_from(const Grid& g, RSC p) {
+  const double r = p.r, s = p.s, c = p.c;
   const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r;
   const double Sig = r2 + a2 * c * c;
   const double S2 = Sig + tMr;
   const double ra = r2 + a2;
-  const double A = ra * ra - a2 * (ra - tMr) * s * s;
-  const double iSig = 1.0 / Sig, iS2 = 1.0 / S2, iR = 1.0 / (g.dxi * r);
+  const double s2 = s * s;
+  const double A = ra * ra - a2 * (ra - tMr) * s2;
+  const double R = g.dxi * r;
+  // one reciprocal for 1/Sigma, 1/S2, 1/sin^2 and 1/R
+  const double q = rcp(Sig * S2 * s2 * R);
+  const double iSig = S2 * s2 * R * q, iS2 = Sig * s2 * R * q;
+  const double is2 = Sig * S2 * R * q, iR = Sig * S2 * s2 * q;
   Coeffs m;
-  m.alpha = sqrt(Sig * iS2);
+  const double y = Sig * iS2;
+  m.alpha = y * rsqrt(y);
   m.beta1 = tMr * iS2 * iR;
   m.hu11 = A * iSig * iS2 * iR * iR;
   m.hu13 = g.a * iSig * iR;
   m.hu22 = iSig * g.inv_dth2;
-  m.hu33 = iSig / (s * s);
+  m.hu33 = iSig * is2;
   return m;
 }
 
-// Coefficients, tetrad factors and first derivatives at (x1, x2), theta clamped.
-__host__ __device__ inline void frame_at(const Grid& g, double x1, double x2, Frame* f, Grad* d) {
-  const double r = exp(g.xi_min + x1 * g.dxi);
-  double s, c;
-  sin_cos(clamp_theta(g, x2 * g.dth), &s, &c);
+__host__ __device__ inline Coeffs coeffs_at(const Grid& g, double x1, double x2) {
+  return coeffs_from(g, rsc_direct(g, x1, x2));
+}
+
+// Coefficients, tetrad factors and first derivatives at a point.
+__host__ __device__ inline void frame_from(const Grid& g, RSC p, Frame* f, Grad* d) {
+  const double r = p.r, s = p.s, c = p.c;
   const double a = g.a, M = g.M;
   const double a2 = a * a, r2 = r * r, tMr = 2.0 * M * r;
   const double Sig = r2 + a2 * c * c;
@@ -103,10 +159,14 @@ __host__ __device__ inline void frame_at(const Grid& g, double x1, double x2, Fr
   const double Del = ra - tMr;
   const double s2 = s * s;
   const double A = ra * ra - a2 * Del * s2;
-  const double iSig = 1.0 / Sig, iS2 = 1.0 / S2;
-  const double R = g.dxi * r, iR = 1.0 / R;
-  const double alpha = sqrt(Sig * iS2);
-  const double ialpha = 1.0 / alpha;
+  const double R = g.dxi * r;
+  const double q = rcp(Sig * S2 * s2 * R * A);
+  const double iSig = S2 * s2 * R * A * q, iS2 = Sig * s2 * R * A * q;
+  const double is2 = Sig * S2 * R * A * q, iR = Sig * S2 * s2 * A * q;
+  const double iA = Sig * S2 * s2 * R * q;
+  const double y = Sig * iS2;
+  const double ialpha = rsqrt(y);
+  const double alpha = y * ialpha;
 
   f->c.alpha = alpha;
   f->c.beta1 = tMr * iS2 * iR;
@@ -114,12 +174,12 @@ __host__ __device__ inline void frame_at(const Grid& g, double x1, double x2, Fr
   f->c.hu11 = hrr * iR * iR;
   f->c.hu13 = a * iSig * iR;
   f->c.hu22 = iSig * g.inv_dth2;
-  const double is2 = 1.0 / s2;
   f->c.hu33 = iSig * is2;
-  f->s11 = sqrt(hrr) * iR;
-  f->s22 = sqrt(Sig) * g.dth;
-  f->s33 = sqrt(A * iSig) * s;
-  f->k13 = -a * R * S2 / A;
+  f->s11 = hrr * rsqrt(hrr) * iR;
+  f->s22 = Sig * rsqrt(Sig) * g.dth;
+  const double AiS = A * iSig;
+  f->s33 = AiS * rsqrt(AiS) * s;
+  f->k13 = -a * R * S2 * iA;
 
   // radial and polar derivatives of Sigma, A (S2 shares dSigma/dtheta)
   const double dSig_r = 2.0 * r, dSig_t = -2.0 * a2 * s * c;
@@ -145,10 +205,14 @@ __host__ __device__ inline void frame_at(const Grid& g, double x1, double x2, Fr
   d->hu13[1] = -g.dth * a * dSig_t * iSig2 * iR;
   // h^22 = 1 / (Sigma dth^2)
   d->hu22[0] = -R * dSig_r * iSig2 * g.inv_dth2;
-  d->hu22[1] = -dSig_t * iSig2 / g.dth;
+  d->hu22[1] = -dSig_t * iSig2 * (g.dth * g.inv_dth2);
   // h^33 = 1 / (Sigma sin^2)
   d->hu33[0] = -R * dSig_r * iSig2 * is2;
-  d->hu33[1] = -g.dth * (dSig_t + 2.0 * Sig * c / s) * iSig2 * is2;
+  d->hu33[1] = -g.dth * (dSig_t + 2.0 * Sig * c * s * is2) * iSig2 * is2;
+}
+
+__host__ __device__ inline void frame_at(const Grid& g, double x1, double x2, Frame* f, Grad* d) {
+  frame_from(g, rsc_direct(g, x1, x2), f, d);
 }
 
 // Geometry at a grid location for the field solver (theta not clamped).

@@ -2,6 +2,7 @@
 // checks, per-context tables, and the launch sequences of the PIC-loop stages.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -10,6 +11,7 @@
 
 #include "grpic.h"
 #include "diag.hpp"
+#include "sort.hpp"
 
 using namespace grpic;
 
@@ -21,7 +23,18 @@ struct grpic_ctx {
   Tables tab;
   DiagAcc* acc;    // device accumulators for diagnostics
   double polar_k;  // 1 - cos(dth / 2)
+  int* sort_off;   // n_cells + 1 counts / offsets, then block sums, then n_live
+  int* sort_sums;
+  int* sort_live;
 };
+
+namespace grpic {
+__global__ void fill_int_kernel(int64_t n, int* __restrict__ p, int v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+__global__ void copy_int_kernel(const int* __restrict__ src, int* __restrict__ dst) { *dst = *src; }
+}  // namespace grpic
 
 namespace {
 
@@ -188,6 +201,13 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   }
   c->prm.dt = g.dt;
   c->polar_k = 1.0 - std::cos(0.5 * g.dth);
+  g.sin_lo = std::sin(p->small_angle);
+  g.cos_lo = std::cos(p->small_angle);
+  g.sin_hi = std::sin(kPi - p->small_angle);
+  g.cos_hi = std::cos(kPi - p->small_angle);
+  // the push evaluates exp and sincos of in-cell offsets (at most 1.5 cells)
+  // by short series that are exact to rounding for arguments up to 0.11
+  g.fast = 1.5 * std::fmax(g.dxi, g.dth) <= 0.11 ? 1 : 0;
 
   hipError_t e = hipGetDevice(&c->device);
   const int nr = p->n_r + 2 * p->n_ghost, nt = p->n_th + 2 * p->n_ghost;
@@ -202,6 +222,19 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     (void)hipFree(c->tables);
     delete c;
     return fail(GRPIC_ENOMEM, "accumulator allocation: %s", hipGetErrorString(e));
+  }
+  {
+    const int64_t nkeys = (int64_t)p->n_r * p->n_th + 1;
+    const int64_t nb = (nkeys + kScanBlock - 1) / kScanBlock;
+    e = hipMalloc(&c->sort_off, (nkeys + nb + 1) * sizeof(int));
+    if (e != hipSuccess) {
+      (void)hipFree(c->tables);
+      (void)hipFree(c->acc);
+      delete c;
+      return fail(GRPIC_ENOMEM, "sort scratch allocation: %s", hipGetErrorString(e));
+    }
+    c->sort_sums = c->sort_off + nkeys;
+    c->sort_live = c->sort_sums + nb;
   }
   double* h = new double[nt_all];
   double* pr0 = h;
@@ -226,6 +259,7 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   if (e != hipSuccess) {
     (void)hipFree(c->tables);
     (void)hipFree(c->acc);
+    (void)hipFree(c->sort_off);
     delete c;
     return fail(GRPIC_EHIP, "table upload: %s", hipGetErrorString(e));
   }
@@ -243,6 +277,7 @@ grpic_status grpic_destroy(grpic_ctx* c) {
   if (!c) return GRPIC_OK;
   (void)hipFree(c->tables);
   (void)hipFree(c->acc);
+  (void)hipFree(c->sort_off);
   delete c;
   return GRPIC_OK;
 }
@@ -320,7 +355,10 @@ grpic_status grpic_push(grpic_ctx* c, const grpic_fields* F, const grpic_particl
     gp.D[k] = (const double*)F->D[k];
     gp.B[k] = (const double*)F->B0[k];
   }
-  hipLaunchKernelGGL(push_kernel, dim3(blocks(P->n)), dim3(kB), 0, S(stream), c->g, gp, arrays(P));
+  if (c->g.fast)
+    hipLaunchKernelGGL(push_kernel<true>, dim3(blocks(P->n)), dim3(kB), 0, S(stream), c->g, c->tab, gp, arrays(P));
+  else
+    hipLaunchKernelGGL(push_kernel<false>, dim3(blocks(P->n)), dim3(kB), 0, S(stream), c->g, c->tab, gp, arrays(P));
   LAUNCH_CHECK("push");
   return GRPIC_OK;
 }
@@ -330,8 +368,54 @@ grpic_status grpic_deposit(grpic_ctx* c, const grpic_particles* P, const grpic_f
   if ((st = check_ctx(c)) || (st = check_fields(F)) || (st = check_particles(P))) return st;
   if (P->n == 0) return GRPIC_OK;
   CurrentPlanes cp{{(double*)F->J[0], (double*)F->J[1], (double*)F->J[2]}};
-  hipLaunchKernelGGL(deposit_kernel, dim3(blocks(P->n)), dim3(kB), 0, S(stream), c->g, arrays(P), cp);
+  const dim3 grid((unsigned)((P->n + kDepBlock - 1) / kDepBlock));
+  if (c->g.fast)
+    hipLaunchKernelGGL(deposit_kernel<true>, grid, dim3(kDepBlock), 0, S(stream), c->g, c->tab, arrays(P), cp);
+  else
+    hipLaunchKernelGGL(deposit_kernel<false>, grid, dim3(kDepBlock), 0, S(stream), c->g, c->tab, arrays(P), cp);
   LAUNCH_CHECK("deposit");
+  return GRPIC_OK;
+}
+
+grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst,
+                        int64_t* n_live, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_particles(src)) || (st = check_particles(dst))) return st;
+  if (src->n != dst->n) return fail(GRPIC_EINVAL, "source has %lld slots, destination %lld",
+                                    (long long)src->n, (long long)dst->n);
+  if (src->n > 0x7FFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^31 - 1 slots");
+  if (src->n > 0 && (src->tag == dst->tag || src->u1 == dst->u1))
+    return fail(GRPIC_EINVAL, "source and destination must not alias");
+  const Grid& g = c->g;
+  hipStream_t s = S(stream);
+  const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
+  const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, nkeys, c->sort_off, 0);
+  LAUNCH_CHECK("fill_int");
+  if (src->n > 0) {
+    ParticleArrays a = arrays(src), b = arrays(dst);
+    hipLaunchKernelGGL(sort_count_kernel, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, c->sort_off);
+    LAUNCH_CHECK("sort_count");
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, c->sort_off, nkeys, c->sort_sums);
+    LAUNCH_CHECK("scan_blocks");
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, c->sort_sums, nb);
+    LAUNCH_CHECK("scan_sums");
+    hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, c->sort_off, nkeys, c->sort_sums);
+    LAUNCH_CHECK("scan_add");
+    hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, c->sort_off + (nkeys - 1), c->sort_live);
+    LAUNCH_CHECK("copy_int");
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, b, c->sort_off);
+    LAUNCH_CHECK("sort_scatter");
+  } else {
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, (int64_t)1, c->sort_live, 0);
+    LAUNCH_CHECK("fill_int");
+  }
+  if (n_live) {
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, c->sort_live, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_live = h;
+  }
   return GRPIC_OK;
 }
 

@@ -5,6 +5,8 @@
 // deposit Sec. 3.2.
 #pragma once
 
+#include <climits>
+
 #include "geometry.hpp"
 
 namespace grpic {
@@ -117,9 +119,11 @@ __device__ inline void geodesic_u(const Grid& g, const Frame& f, const Grad& d, 
   double t1 = s1, t2 = s2;
   for (int it = 0; it < g.n_iter; ++it) {
     const double b1 = 0.5 * (s1 + t1), b2 = 0.5 * (s2 + t2);
-    const double gb = sqrt(1.0 + m.hu11 * b1 * b1 + m.hu22 * b2 * b2 + m.hu33 * u33 +
-                           2.0 * m.hu13 * b1 * u3);
-    const double h = 0.5 * m.alpha / gb;
+    const double Q = 1.0 + m.hu11 * b1 * b1 + m.hu22 * b2 * b2 + m.hu33 * u33 +
+                     2.0 * m.hu13 * b1 * u3;
+    const double ig = rsqrt(Q);
+    const double gb = Q * ig;
+    const double h = 0.5 * m.alpha * ig;
     double fr[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -127,8 +131,11 @@ __device__ inline void geodesic_u(const Grid& g, const Frame& f, const Grad& d, 
                        2.0 * d.hu13[i] * b1 * u3;
       fr[i] = -gb * d.alpha[i] + b1 * d.beta1[i] - h * q;
     }
-    t1 = s1 + g.dt * fr[0];
-    t2 = s2 + g.dt * fr[1];
+    const double n1 = s1 + g.dt * fr[0], n2 = s2 + g.dt * fr[1];
+    const bool fixed = n1 == t1 && n2 == t2;  // exact repeat: fixed point reached
+    t1 = n1;
+    t2 = n2;
+    if (fixed) break;
   }
   u1 = t1;
   u2 = t2;
@@ -144,7 +151,80 @@ __device__ inline void renormalize(int& i, double& dx) {
   }
 }
 
-__global__ void __launch_bounds__(256) push_kernel(Grid g, GatherPlanes fp, ParticleArrays P) {
+// exp(t) for |t| <= 0.11: Taylor series to t^11 (remainder below 1e-20 relative)
+__device__ inline double exp_small(double t) {
+  double p = fma(t, 1.0 / 39916800.0, 1.0 / 3628800.0);
+  p = fma(t, p, 1.0 / 362880.0);
+  p = fma(t, p, 1.0 / 40320.0);
+  p = fma(t, p, 1.0 / 5040.0);
+  p = fma(t, p, 1.0 / 720.0);
+  p = fma(t, p, 1.0 / 120.0);
+  p = fma(t, p, 1.0 / 24.0);
+  p = fma(t, p, 1.0 / 6.0);
+  p = fma(t, p, 0.5);
+  p = fma(t, p, 1.0);
+  return fma(t, p, 1.0);
+}
+
+// sin and cos for |x| <= 0.11: Taylor series to x^13 and x^14
+__device__ inline void sincos_small(double x, double* s, double* c) {
+  const double z = x * x;
+  double ps = fma(z, 1.0 / 6227020800.0, -1.0 / 39916800.0);
+  ps = fma(z, ps, 1.0 / 362880.0);
+  ps = fma(z, ps, -1.0 / 5040.0);
+  ps = fma(z, ps, 1.0 / 120.0);
+  ps = fma(z, ps, -1.0 / 6.0);
+  *s = fma(x * z, ps, x);
+  double pc = fma(z, -1.0 / 87178291200.0, 1.0 / 479001600.0);
+  pc = fma(z, pc, -1.0 / 3628800.0);
+  pc = fma(z, pc, 1.0 / 40320.0);
+  pc = fma(z, pc, -1.0 / 720.0);
+  pc = fma(z, pc, 1.0 / 24.0);
+  pc = fma(z, pc, -0.5);
+  *c = fma(z, pc, 1.0);
+}
+
+// pi - (pi rounded to double)
+constexpr double kPiLo = 1.2246467991473531772e-16;
+
+// r, sin, cos at code position (x1, x2) near cell (i1, i2) (|x - i| <= 1.5):
+// r = r_i exp((x1 - i1) dxi); the polar angle is first rounded and clamped as
+// theta = clamp(x2 dth), and the result is the sine and cosine of that double:
+// by the short series on theta itself within 0.11 of theta = 0, on
+// psi = pi - theta (exact subtraction plus the low part of pi) within 0.11 of
+// theta = pi, so that sin keeps its relative precision next to both axes, and
+// by angle addition from the tables elsewhere.  Library functions when the
+// grid is too coarse for the short series.
+template <bool FAST>
+__device__ inline RSC rsc_near(const Grid& g, const Tables& t, int i1, double x1, int i2, double x2) {
+  if (!FAST) return rsc_direct(g, x1, x2);
+  RSC p;
+  p.r = t.r[0][i1 + g.ng] * exp_small((x1 - (double)i1) * g.dxi);
+  const double th = x2 * g.dth;
+  if (th <= g.small_angle) {
+    p.s = g.sin_lo;
+    p.c = g.cos_lo;
+  } else if (th >= kPi - g.small_angle) {
+    p.s = g.sin_hi;
+    p.c = g.cos_hi;
+  } else if (th <= 0.11) {
+    sincos_small(th, &p.s, &p.c);
+  } else if (th >= kPi - 0.11) {
+    double cq;
+    sincos_small((kPi - th) + kPiLo, &p.s, &cq);
+    p.c = -cq;
+  } else {
+    double sp, cp;
+    sincos_small(th - (double)i2 * g.dth, &sp, &cp);
+    const double sj = t.s[0][i2 + g.ng], cj = t.c[0][i2 + g.ng];
+    p.s = fma(sj, cp, cj * sp);
+    p.c = fma(cj, cp, -(sj * sp));
+  }
+  return p;
+}
+
+template <bool FAST>
+__global__ void __launch_bounds__(256) push_kernel(Grid g, Tables tab, GatherPlanes fp, ParticleArrays P) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P.n) return;
   uint8_t t = P.tag[k];
@@ -168,7 +248,7 @@ __global__ void __launch_bounds__(256) push_kernel(Grid g, GatherPlanes fp, Part
   const double x1 = (double)i1 + dx1, x2 = (double)i2 + dx2;
   Frame f;
   Grad d;
-  frame_at(g, x1, x2, &f, &d);
+  frame_from(g, rsc_near<FAST>(g, tab, i1, x1, i2, x2), &f, &d);
   const double qm = species_sign(t);
   if (qm != 0.0) {
     // D^i, B^i at x^n -> tetrad components, scaled by the lapse
@@ -189,17 +269,25 @@ __global__ void __launch_bounds__(256) push_kernel(Grid g, GatherPlanes fp, Part
     geodesic_u(g, f, d, u1, u2, u3);
   }
 
-  // implicit coordinate update (eq. discretized-geodesic-x)
+  // implicit coordinate update (eq. discretized-geodesic-x); an iterate that
+  // repeats exactly is the fixed point of the map, so stopping there gives the
+  // same result as running all n_iter iterations
   double d1 = 0.0, d2 = 0.0;
   for (int it = 0; it < g.n_iter; ++it) {
-    const Coeffs m = coeffs_at(g, x1 + 0.5 * d1, x2 + 0.5 * d2);
-    const double iu0 = m.alpha / gamma_of(m, u1, u2, u3);
-    d1 = g.dt * ((m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1);
-    d2 = g.dt * (m.hu22 * u2 * iu0);
+    const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
+    const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
+                                       m.hu33 * u3 * u3 + 2.0 * m.hu13 * u1 * u3);
+    const double n1 = g.dt * ((m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1);
+    const double n2 = g.dt * (m.hu22 * u2 * iu0);
+    const bool fixed = n1 == d1 && n2 == d2;
+    d1 = n1;
+    d2 = n2;
+    if (fixed) break;
   }
   {
-    const Coeffs m = coeffs_at(g, x1 + 0.5 * d1, x2 + 0.5 * d2);
-    const double iu0 = m.alpha / gamma_of(m, u1, u2, u3);
+    const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
+    const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
+                                       m.hu33 * u3 * u3 + 2.0 * m.hu13 * u1 * u3);
     P.phi[k] += g.dt * (m.hu13 * u1 + m.hu33 * u3) * iu0;
   }
   dx1 += d1;
@@ -237,22 +325,37 @@ __device__ inline void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); 
 // Zigzag charge-conserving deposit (Umeda et al. 2003) in code coordinates
 // from the previous to the current position, plus J^3 = q alpha u^3 / gamma at
 // the path midpoint with first-order node weights.
-__global__ void __launch_bounds__(256) deposit_kernel(Grid g, ParticleArrays P, CurrentPlanes c) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= P.n) return;
+//
+// A block first accumulates its particles' contributions in a shared-memory
+// tile of kTI x kTJ nodes per component (LDS atomics), then adds each touched
+// tile node to the global planes once.  Particles sorted by cell make the
+// block's footprint small; a block whose footprint exceeds the tile adds
+// directly to global memory.
+constexpr int kDepBlock = 256;
+constexpr int kTI = 8, kTJ = 48;
+
+struct Contrib {
+  int ia, ja;         // previous cell: anchor of the 4 x 4 footprint [ia-1, ia+2] x [ja-1, ja+2]
+  int di, dj, km, lm; // cell step, J^3 node corner (relative to the anchor)
+  double j1[4], j2[4], j3[4];
+};
+
+template <bool FAST>
+__device__ inline bool make_contrib(const Grid& g, const Tables& tab, const ParticleArrays& P,
+                                    int64_t k, Contrib& c) {
+  if (k >= P.n) return false;
   const uint8_t t = P.tag[k];
-  if (!is_live(t)) return;
+  if (!is_live(t)) return false;
   const double sg = species_sign(t);
-  if (sg == 0.0) return;
-  const double q = sg * g.charge_scale * P.w[k];
-  const double qdt = q / g.dt;
+  if (sg == 0.0) return false;
   const int ia = P.i1p[k], ja = P.i2p[k];
   const int di = P.i1[k] - ia, dj = P.i2[k] - ja;
   // the zigzag touches at most cells ia-1 .. ia+2: both ends must be in range
   if (!in_grid(g, ia, P.dx1p[k], ja, P.dx2p[k]) ||
       !in_deposit_range(g, P.i1[k], P.dx1[k], P.i2[k], P.dx2[k]) || abs(di) > 1 || abs(dj) > 1)
-    return;
-  // positions relative to the corner of the previous cell
+    return false;
+  const double q = sg * g.charge_scale * P.w[k];
+  const double qdt = q / g.dt;
   const double xa = P.dx1p[k], ya = P.dx2p[k];
   const double xb = (double)di + P.dx1[k], yb = (double)dj + P.dx2[k];
   const double xr = fmin((double)min(0, di) + 1.0, fmax((double)max(0, di), 0.5 * (xa + xb)));
@@ -261,30 +364,102 @@ __global__ void __launch_bounds__(256) deposit_kernel(Grid g, ParticleArrays P, 
   const double fx2 = qdt * (xb - xr), fy2 = qdt * (yb - yr);
   const double wx1 = 0.5 * (xa + xr), wy1 = 0.5 * (ya + yr);
   const double wx2 = 0.5 * (xr + xb) - di, wy2 = 0.5 * (yr + yb) - dj;
-  double* J1 = c.J[0];
-  double* J2 = c.J[1];
-  const int64_t oa = ix(g, ia, ja), ob = ix(g, ia + di, ja + dj);
-  atomic_add(J1 + oa, fx1 * (1.0 - wy1));
-  atomic_add(J1 + oa + 1, fx1 * wy1);
-  atomic_add(J2 + oa, fy1 * (1.0 - wx1));
-  atomic_add(J2 + oa + g.ld, fy1 * wx1);
-  atomic_add(J1 + ob, fx2 * (1.0 - wy2));
-  atomic_add(J1 + ob + 1, fx2 * wy2);
-  atomic_add(J2 + ob, fy2 * (1.0 - wx2));
-  atomic_add(J2 + ob + g.ld, fy2 * wx2);
-
+  c.ia = ia;
+  c.ja = ja;
+  c.di = di;
+  c.dj = dj;
+  // J^1 at (ia, ja), (ia, ja+1), (ib, jb), (ib, jb+1); J^2 at (ia, ja), (ia+1, ja), (ib, jb), (ib+1, jb)
+  c.j1[0] = fx1 * (1.0 - wy1);
+  c.j1[1] = fx1 * wy1;
+  c.j1[2] = fx2 * (1.0 - wy2);
+  c.j1[3] = fx2 * wy2;
+  c.j2[0] = fy1 * (1.0 - wx1);
+  c.j2[1] = fy1 * wx1;
+  c.j2[2] = fy2 * (1.0 - wx2);
+  c.j2[3] = fy2 * wx2;
   const double xm = 0.5 * (xa + xb), ym = 0.5 * (ya + yb);
-  const Coeffs m = coeffs_at(g, (double)ia + xm, (double)ja + ym);
+  const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, ia, (double)ia + xm, ja, (double)ja + ym));
   const double u1 = P.u1[k], u2 = P.u2[k], u3 = P.u3[k];
-  const double vphi = (m.hu13 * u1 + m.hu33 * u3) * m.alpha / gamma_of(m, u1, u2, u3);
+  const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+                                     2.0 * m.hu13 * u1 * u3);
+  const double vphi = (m.hu13 * u1 + m.hu33 * u3) * iu0;
   const double fm = floor(xm), gm = floor(ym);
   const double w1 = xm - fm, w2 = ym - gm;
   const double c3 = q * vphi;
-  double* p3 = c.J[2] + ix(g, ia + (int)fm, ja + (int)gm);
-  atomic_add(p3, c3 * (1.0 - w1) * (1.0 - w2));
-  atomic_add(p3 + 1, c3 * (1.0 - w1) * w2);
-  atomic_add(p3 + g.ld, c3 * w1 * (1.0 - w2));
-  atomic_add(p3 + g.ld + 1, c3 * w1 * w2);
+  c.km = (int)fm;
+  c.lm = (int)gm;
+  // J^3 at (km, lm), (km, lm+1), (km+1, lm), (km+1, lm+1)
+  c.j3[0] = c3 * (1.0 - w1) * (1.0 - w2);
+  c.j3[1] = c3 * (1.0 - w1) * w2;
+  c.j3[2] = c3 * w1 * (1.0 - w2);
+  c.j3[3] = c3 * w1 * w2;
+  return true;
+}
+
+// Adds a contribution through `add(component, i, j, value)` (absolute node indices).
+template <class Add>
+__device__ inline void scatter(const Contrib& c, Add add) {
+  const int ia = c.ia, ja = c.ja, ib = c.ia + c.di, jb = c.ja + c.dj;
+  add(0, ia, ja, c.j1[0]);
+  add(0, ia, ja + 1, c.j1[1]);
+  add(0, ib, jb, c.j1[2]);
+  add(0, ib, jb + 1, c.j1[3]);
+  add(1, ia, ja, c.j2[0]);
+  add(1, ia + 1, ja, c.j2[1]);
+  add(1, ib, jb, c.j2[2]);
+  add(1, ib + 1, jb, c.j2[3]);
+  const int km = ia + c.km, lm = ja + c.lm;
+  add(2, km, lm, c.j3[0]);
+  add(2, km, lm + 1, c.j3[1]);
+  add(2, km + 1, lm, c.j3[2]);
+  add(2, km + 1, lm + 1, c.j3[3]);
+}
+
+template <bool FAST>
+__global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, ParticleArrays P,
+                                                            CurrentPlanes cp) {
+  __shared__ double tile[3][kTI][kTJ];
+  __shared__ int bound[4][kDepBlock / 64];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  Contrib c;
+  const bool act = make_contrib<FAST>(g, tab, P, k, c);
+  // block footprint: union of [ia-1, ia+2] x [ja-1, ja+2]
+  int v[4] = {act ? c.ia - 1 : INT_MAX, act ? -(c.ia + 2) : INT_MAX, act ? c.ja - 1 : INT_MAX,
+              act ? -(c.ja + 2) : INT_MAX};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (int off = 32; off > 0; off >>= 1) v[q] = min(v[q], __shfl_down(v[q], off, 64));
+    if (lane == 0) bound[q][wv] = v[q];
+  }
+  // zero the tile while the bounds settle
+  double* flat = &tile[0][0][0];
+  for (int e = threadIdx.x; e < 3 * kTI * kTJ; e += kDepBlock) flat[e] = 0.0;
+  __syncthreads();
+  int b[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    b[q] = bound[q][0];
+    for (int w = 1; w < kDepBlock / 64; ++w) b[q] = min(b[q], bound[q][w]);
+  }
+  const int i0 = b[0], i1 = -b[1], j0 = b[2], j1 = -b[3];
+  if (i0 == INT_MAX) return;  // no live charged particle in this block (uniform)
+  const bool fits = (i1 - i0 < kTI) && (j1 - j0 < kTJ);
+  if (!fits) {
+    if (act)
+      scatter(c, [&](int comp, int i, int j, double val) { atomic_add(cp.J[comp] + ix(g, i, j), val); });
+    return;
+  }
+  if (act)
+    scatter(c, [&](int comp, int i, int j, double val) { atomicAdd(&tile[comp][i - i0][j - j0], val); });
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * kTI * kTJ; e += kDepBlock) {
+    const double val = flat[e];
+    if (val != 0.0) {
+      const int comp = e / (kTI * kTJ), rem = e % (kTI * kTJ);
+      atomic_add(cp.J[comp] + ix(g, i0 + rem / kTJ, j0 + rem % kTJ), val);
+    }
+  }
 }
 
 }  // namespace grpic

@@ -1,0 +1,117 @@
+// sort.hpp -- counting sort of the particle slots by cell (c = i1 * n_th + i2).
+//
+// Not part of the paper's method: a layout device that keeps particles of one
+// cell adjacent in memory, so that a wavefront streams contiguous SoA data,
+// gathers from a few neighbouring field entries, and the deposit's per-block
+// footprint stays inside its shared-memory tile.  Empty and leaving slots get
+// the key n_cells and end up (emptied) after all live particles.
+#pragma once
+
+#include "particles.hpp"
+
+namespace grpic {
+
+constexpr int kScanBlock = 1024;  // elements scanned per block (4 per thread)
+
+__device__ inline int sort_key(const Grid& g, const ParticleArrays& P, int64_t k) {
+  const uint8_t t = P.tag[k];
+  const int ncell = g.n_r * g.n_th;
+  if (!is_live(t) || (t & kLeaving)) return ncell;
+  const int i1 = P.i1[k], i2 = P.i2[k];
+  if (i1 < 0 || i1 >= g.n_r || i2 < 0 || i2 >= g.n_th) return ncell;
+  return i1 * g.n_th + i2;
+}
+
+__global__ void sort_count_kernel(Grid g, ParticleArrays P, int* __restrict__ counts) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P.n) return;
+  atomicAdd(counts + sort_key(g, P, k), 1);
+}
+
+// Exclusive scan of n ints in place, three phases: per-block scan (block sums
+// out), scan of the block sums (one block), add the scanned block sums.
+__device__ inline int block_exclusive_scan(int v, int* sh) {
+  // Hillis-Steele over 256 threads in LDS
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(256) scan_blocks_kernel(int* __restrict__ a, int64_t n,
+                                                          int* __restrict__ sums) {
+  __shared__ int sh[256];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + 4 * threadIdx.x;
+  int v[4];
+  int tot = 0;
+  for (int q = 0; q < 4; ++q) {
+    v[q] = base + q < n ? a[base + q] : 0;
+    tot += v[q];
+  }
+  const int ex = block_exclusive_scan(tot, sh);
+  int run = ex;
+  for (int q = 0; q < 4; ++q) {
+    if (base + q < n) a[base + q] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == 255) sums[blockIdx.x] = ex + tot;
+}
+
+__global__ void __launch_bounds__(256) scan_sums_kernel(int* __restrict__ sums, int nb) {
+  __shared__ int sh[256];
+  // serial over chunks of 256 (nb is small: n / 1024)
+  int carry = 0;
+  for (int base = 0; base < nb; base += 256) {
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? sums[i] : 0;
+    const int ex = block_exclusive_scan(v, sh);
+    if (i < nb) sums[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 255) sh[0] = ex + v;
+    __syncthreads();
+    carry += sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void scan_add_kernel(int* __restrict__ a, int64_t n, const int* __restrict__ sums) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] += sums[i / kScanBlock];
+}
+
+// Moves slot k of S to its cell's next free slot in D; emptied slots get tag 0.
+// The order of particles inside one cell follows the order of the atomics.
+__global__ void sort_scatter_kernel(Grid g, ParticleArrays S, ParticleArrays D, int* __restrict__ off) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= S.n) return;
+  const int key = sort_key(g, S, k);
+  const int64_t o = atomicAdd(off + key, 1);
+  if (key == g.n_r * g.n_th) {
+    D.tag[o] = 0;
+    return;
+  }
+  D.i1[o] = S.i1[k];
+  D.i2[o] = S.i2[k];
+  D.dx1[o] = S.dx1[k];
+  D.dx2[o] = S.dx2[k];
+  D.u1[o] = S.u1[k];
+  D.u2[o] = S.u2[k];
+  D.u3[o] = S.u3[k];
+  D.w[o] = S.w[k];
+  D.phi[o] = S.phi[k];
+  D.i1p[o] = S.i1p[k];
+  D.i2p[o] = S.i2p[k];
+  D.dx1p[o] = S.dx1p[k];
+  D.dx2p[o] = S.dx2p[k];
+  D.tag[o] = S.tag[k];
+}
+
+}  // namespace grpic

@@ -75,6 +75,7 @@ _sigs = {
     "grpic_push": ([c_void_p, _F, _PP, c_void_p], c_int32),
     "grpic_deposit": ([c_void_p, _PP, _F, c_void_p], c_int32),
     "grpic_field_advance": ([c_void_p, _F, c_int32, c_void_p], c_int32),
+    "grpic_sort": ([c_void_p, _PP, _PP, POINTER(c_int64), c_void_p], c_int32),
     "grpic_diagnostics": ([c_void_p, _F, _PP, c_double, POINTER(Diag), c_void_p, c_void_p,
                            c_void_p, c_void_p], c_int32),
 }
@@ -203,6 +204,15 @@ class Context:
     def field_advance(self, F: torch.Tensor, stage: int):
         _check(_lib.grpic_field_advance(self._h, ctypes.byref(self._fields(F)), stage, _stream()),
                "grpic_field_advance")
+
+    def sort(self, P: dict, Q: dict, count: bool = False):
+        """Cell-sort the slots of P into Q (same size); returns the number of
+        live slots when count is True (waits for the stream)."""
+        n = c_int64(0)
+        _check(_lib.grpic_sort(self._h, ctypes.byref(self._particles(P)),
+                               ctypes.byref(self._particles(Q)),
+                               ctypes.byref(n) if count else None, _stream()), "grpic_sort")
+        return n.value if count else None
 
     def diagnostics(self, F: torch.Tensor, P: dict, B0: float, per_particle: bool = False,
                     gauss_plane: bool = False) -> dict:

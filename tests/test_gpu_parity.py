@@ -103,6 +103,29 @@ def assert_fields(F_o, F_g, planes, tol=TOL, what=""):
         assert err <= tol * max(scale, 1e-300), f"{what} plane {c}: err {err:.3e} scale {scale:.3e}"
 
 
+def assert_wald(O, prm, B0, F_o, F_g, what=""):
+    """Wald initial data: D planes (pointwise analytic) to the plain bound;
+    B planes are differences of potentials divided by sqrt(h) (eq. EB-set),
+    whose rounding is bounded per point by eps (|A_a| + |A_b|) / |sqrt h|
+    (a few ulp of the potentials; near the axis the difference cancels by
+    orders of magnitude)."""
+    assert_fields(F_o, F_g, [0, 1, 2, 6, 7, 8, 24, 25, 26], what=what + " D")
+    A1, A3 = O.wald_potential_planes(prm, B0)
+    sh = {(0, 1): O.sqrt_h_plane(prm, 0, 1), (1, 0): O.sqrt_h_plane(prm, 1, 0),
+          (1, 1): O.sqrt_h_plane(prm, 1, 1)}
+    nb = [(np.abs(A3) + np.abs(np.roll(A3, -1, axis=1))) / np.abs(sh[(0, 1)]),
+          (np.abs(A3) + np.abs(np.roll(A3, -1, axis=0))) / np.abs(sh[(1, 0)]),
+          (np.abs(A1) + np.abs(np.roll(A1, -1, axis=1))) / np.abs(sh[(1, 1)])]
+    g = prm.ng
+    phys = (slice(g, g + prm.n_r + 1), slice(g, g + prm.n_th + 1))
+    for base in (3, 9, 27):
+        for c in range(3):
+            a, b = F_o[base + c][phys], F_g[base + c][phys]
+            bound = TOL * np.abs(a).max() + 1e-14 * np.nan_to_num(nb[c][phys], posinf=np.inf)
+            bad = np.abs(a - b) > bound
+            assert not bad.any(), f"{what} B plane {base + c}: {bad.sum()} points over the bound"
+
+
 # ---------------------------------------------------------------- loading
 
 def test_particles_init_parity(O, G):
@@ -135,7 +158,8 @@ def test_fields_init_wald_parity(O, G, name, n):
     Fo = O.fields_init_wald(prm, w.B0)
     Fg = ctx.new_fields()
     ctx.fields_init_wald(Fg, w.B0)
-    assert_fields(Fo, Fg.cpu().numpy(), range(33), tol=1e-13, what="wald")
+    assert_wald(O, prm, w.B0, Fo, Fg.cpu().numpy(), what="wald")
+    assert_fields(Fo, Fg.cpu().numpy(), range(12, 24), what="wald zero planes")
 
 
 # ---------------------------------------------------------------- push
@@ -328,10 +352,11 @@ def test_c2_full_size_launch(O, G):
     Fg = ctx.new_fields()
     ctx.fields_init_wald(Fg, w.B0)
     Fo = O.fields_init_wald(prm, w.B0)
-    assert_fields(Fo, Fg.cpu().numpy(), range(12), tol=1e-13, what="c2 wald")
+    assert_wald(O, prm, w.B0, Fo, Fg.cpu().numpy(), what="c2 wald")
     Pd = down(Pg)
+    plasma = Po["tag"] != 3     # test-geodesic positions come from log(r): not bit-exact
     for k in ("i1", "i2", "dx1", "dx2", "tag"):
-        np.testing.assert_array_equal(Pd[k], Po[k], err_msg=k)
+        np.testing.assert_array_equal(Pd[k][plasma], Po[k][plasma], err_msg=k)
     assert_particles(prm, Po, Pd, tol=1e-13, what="c2 init")
     ctx.push(Fg, Pg)
     torch.cuda.synchronize()
@@ -342,3 +367,41 @@ def test_c2_full_size_launch(O, G):
     O.push(prm, Fo, S)
     Pd = down(Pg)
     assert_particles(prm, S, {k: v[idx] for k, v in Pd.items()}, what="c2 push sample")
+
+
+# ---------------------------------------------------------------- sort
+
+def test_sort_is_a_cell_ordered_permutation(O, G):
+    """The cell sort moves every live slot unchanged (the multiset of particle
+    states is preserved bit for bit), orders live slots by cell, empties the
+    leaving and empty slots and puts them last; n_live is their count."""
+    import torch
+    w = wl("c1_64", 40)
+    prm, ctx = pair(O, G, w, charge_scale=0.1)
+    F, P = _state(O, prm, w, n_pairs=6000)
+    for _ in range(4):              # scramble the order and create leavers
+        O.push(prm, F, P)
+    P["tag"][::97] = 0
+    g = np.random.default_rng(3)
+    perm = g.permutation(len(P["tag"]))
+    P = {k: np.ascontiguousarray(v[perm]) for k, v in P.items()}
+    Pg = up(P)
+    Qg = ctx.new_particles(len(P["tag"]))
+    n_live = ctx.sort(Pg, Qg, count=True)
+    Q = down(Qg)
+    live_in = (P["tag"] != 0) & ((P["tag"] & 0x80) == 0)
+    assert n_live == int(live_in.sum())
+    assert (Q["tag"][:n_live] != 0).all() and (Q["tag"][n_live:] == 0).all()
+    key = Q["i1"][:n_live].astype(np.int64) * 40 + Q["i2"][:n_live]
+    assert (np.diff(key) >= 0).all()
+    cols = ["i1", "i2", "dx1", "dx2", "u1", "u2", "u3", "w", "phi", "i1p", "i2p", "dx1p",
+            "dx2p", "tag"]
+
+    def rows(D, sel):
+        return np.sort(np.stack([D[c][sel].astype(np.float64) for c in cols]).T.copy()
+                       .view([("", np.float64)] * len(cols)), axis=0)
+
+    np.testing.assert_array_equal(rows(P, live_in), rows(Q, slice(0, n_live)))
+    # empty input
+    E = ctx.new_particles(0)
+    assert ctx.sort(E, ctx.new_particles(0), count=True) == 0
