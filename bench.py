@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--workload", default="c2_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--iter-tol", type=float, default=0.0,
+                    help="FP64 convergence test of the implicit iterations (0: fixed count)")
     ap.add_argument("--sort-every", type=int, default=10,
                     help="cell-sort the particles every k steps (0: never)")
     return ap.parse_args()
@@ -87,7 +89,7 @@ def main():
     dev = torch.device("cuda:0")
     ctx = grpic.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, cfl=w.cfl, n_iter=w.n_iter,
                         small_angle=w.small_angle, charge_scale=0.0, n_filter=w.n_filter,
-                        n_absorb=w.n_absorb)
+                        n_absorb=w.n_absorb, iter_tol=ARGS.iter_tol)
     F = ctx.new_fields(dev)
     ctx.fields_init_wald(F, w.B0)
     P = ctx.new_particles(w.n_particles, dev)
@@ -157,7 +159,7 @@ def main():
                    "r_range": [w.r_min, w.r_max], "particles": w.n_particles, "ppc": w.ppc,
                    "test_geodesics": w.n_geo, "T": w.T, "B0": w.B0, "n_iter": w.n_iter,
                    "dt": ctx.dt, "full_step": w.full_step, "precision": w.precision,
-                   "sort_every": ARGS.sort_every},
+                   "sort_every": ARGS.sort_every, "iter_tol": ARGS.iter_tol},
         "roofline": {"bound": "hbm", "kernel": "push_kernel", "achieved": push_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": push_gbs / HBM_PEAK_GBS,
                      "traffic": None,

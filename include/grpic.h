@@ -76,6 +76,13 @@ typedef struct {
   double cfl;           /* Courant number used when dt <= 0                  */
   double small_angle;   /* theta clamp for metric evaluation (Sec. 3.3.2)   */
   double charge_scale;  /* deposited charge per unit particle weight          */
+  double iter_tol;      /* 0: the implicit iterations run n_iter times (an
+                           iterate that repeats exactly ends them early with
+                           the same result); > 0: they also end once the FP64
+                           change of an iterate is at most iter_tol times its
+                           size (a convergence test; results then differ from
+                           the fixed count by about iter_tol times the
+                           contraction of the map)                          */
   int32_t n_r, n_th;    /* cells in r and theta, >= 8 each                   */
   int32_t n_ghost;      /* ghost cells per side; must be 2                   */
   int32_t n_iter;       /* implicit-midpoint iterations (Sec. 3.1), >= 1    */

@@ -30,6 +30,7 @@ struct Grid {
   double dt;
   double small_angle;
   double charge_scale;
+  double iter_tol;  // relative FP64 convergence test of the implicit iterations (0: off)
   // sin, cos of the clamped polar angles small_angle and pi - small_angle
   double sin_lo, cos_lo, sin_hi, cos_hi;
   int n_r, n_th, ng, ld;  // ld = n_th + 2 ng (row length of a plane)

@@ -159,6 +159,7 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     return fail(GRPIC_EINVAL, "need |a| < M (or M = a = 0)");
   if (!(p->small_angle > 0.0 && p->small_angle < 0.1)) return fail(GRPIC_EINVAL, "small_angle out of range");
   if (p->reserved != 0) return fail(GRPIC_EINVAL, "reserved must be 0");
+  if (!(p->iter_tol >= 0.0 && p->iter_tol < 1e-6)) return fail(GRPIC_EINVAL, "iter_tol must be in [0, 1e-6)");
   if ((int64_t)(p->n_r + 2 * p->n_ghost) * (p->n_th + 2 * p->n_ghost) > (int64_t)1 << 31)
     return fail(GRPIC_EINVAL, "grid too large");
 
@@ -173,6 +174,7 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   g.inv_dth2 = 1.0 / (g.dth * g.dth);
   g.small_angle = p->small_angle;
   g.charge_scale = p->charge_scale;
+  g.iter_tol = p->iter_tol;
   g.n_r = p->n_r;
   g.n_th = p->n_th;
   g.ng = p->n_ghost;

@@ -132,7 +132,9 @@ __device__ inline void geodesic_u(const Grid& g, const Frame& f, const Grad& d, 
       fr[i] = -gb * d.alpha[i] + b1 * d.beta1[i] - h * q;
     }
     const double n1 = s1 + g.dt * fr[0], n2 = s2 + g.dt * fr[1];
-    const bool fixed = n1 == t1 && n2 == t2;  // exact repeat: fixed point reached
+    // exact repeat: the fixed point of the map; or the optional FP64 convergence test
+    const bool fixed = (n1 == t1 && n2 == t2) ||
+                       fabs(n1 - t1) + fabs(n2 - t2) <= g.iter_tol * (fabs(n1) + fabs(n2));
     t1 = n1;
     t2 = n2;
     if (fixed) break;
@@ -271,7 +273,8 @@ __global__ void __launch_bounds__(256) push_kernel(Grid g, Tables tab, GatherPla
 
   // implicit coordinate update (eq. discretized-geodesic-x); an iterate that
   // repeats exactly is the fixed point of the map, so stopping there gives the
-  // same result as running all n_iter iterations
+  // same result as running all n_iter iterations (and with iter_tol > 0 the
+  // loop also ends once the FP64 change is below the relative tolerance)
   double d1 = 0.0, d2 = 0.0;
   for (int it = 0; it < g.n_iter; ++it) {
     const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
@@ -279,7 +282,8 @@ __global__ void __launch_bounds__(256) push_kernel(Grid g, Tables tab, GatherPla
                                        m.hu33 * u3 * u3 + 2.0 * m.hu13 * u1 * u3);
     const double n1 = g.dt * ((m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1);
     const double n2 = g.dt * (m.hu22 * u2 * iu0);
-    const bool fixed = n1 == d1 && n2 == d2;
+    const bool fixed = (n1 == d1 && n2 == d2) ||
+                       fabs(n1 - d1) + fabs(n2 - d2) <= g.iter_tol * (fabs(n1) + fabs(n2));
     d1 = n1;
     d2 = n2;
     if (fixed) break;

@@ -22,10 +22,34 @@ __device__ inline int sort_key(const Grid& g, const ParticleArrays& P, int64_t k
   return i1 * g.n_th + i2;
 }
 
-__global__ void sort_count_kernel(Grid g, ParticleArrays P, int* __restrict__ counts) {
+// Runs of equal keys in consecutive lanes of a wavefront (particles arrive
+// nearly sorted, so a wave holds a few runs): one atomic per run.
+struct Run {
+  int key, head, len;  // this lane's key, its run's first lane, the run length
+  bool first;          // lane is the first of its run
+};
+
+__device__ inline Run wave_run(int key) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  const bool first = lane == 0 || prev != key;
+  const unsigned long long heads = __ballot(first);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1);
+  Run r;
+  r.key = key;
+  r.first = first;
+  r.head = 63 - __clzll(heads & upto);
+  const unsigned long long after = lane == 63 ? 0ull : (heads >> (lane + 1));
+  r.len = first ? (after ? __ffsll((long long)after) : 64 - lane) : 0;
+  return r;
+}
+
+__global__ void __launch_bounds__(256) sort_count_kernel(Grid g, ParticleArrays P,
+                                                         int* __restrict__ counts) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= P.n) return;
-  atomicAdd(counts + sort_key(g, P, k), 1);
+  const int key = k < P.n ? sort_key(g, P, k) : -1;  // -1: past the end (own run)
+  const Run r = wave_run(key);
+  if (r.first && key >= 0) atomicAdd(counts + key, r.len);
 }
 
 // Exclusive scan of n ints in place, three phases: per-block scan (block sums
@@ -87,13 +111,19 @@ __global__ void scan_add_kernel(int* __restrict__ a, int64_t n, const int* __res
   if (i < n) a[i] += sums[i / kScanBlock];
 }
 
-// Moves slot k of S to its cell's next free slot in D; emptied slots get tag 0.
-// The order of particles inside one cell follows the order of the atomics.
-__global__ void sort_scatter_kernel(Grid g, ParticleArrays S, ParticleArrays D, int* __restrict__ off) {
+// Moves slot k of S to its cell's next free slots in D; emptied slots get tag
+// 0.  A run of equal keys in a wavefront takes consecutive slots in lane order;
+// the order of runs of one cell follows the order of the atomics.
+__global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArrays S, ParticleArrays D,
+                                                           int* __restrict__ off) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= S.n) return;
-  const int key = sort_key(g, S, k);
-  const int64_t o = atomicAdd(off + key, 1);
+  const int key = k < S.n ? sort_key(g, S, k) : -1;
+  const Run r = wave_run(key);
+  int base = 0;
+  if (r.first && key >= 0) base = atomicAdd(off + key, r.len);
+  base = __shfl(base, r.head, 64);
+  if (key < 0) return;
+  const int64_t o = (int64_t)base + ((threadIdx.x & 63) - r.head);
   if (key == g.n_r * g.n_th) {
     D.tag[o] = 0;
     return;

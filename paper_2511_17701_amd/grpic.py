@@ -40,7 +40,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 class Params(ctypes.Structure):
     _fields_ = [("a", c_double), ("M", c_double), ("r_min", c_double), ("r_max", c_double),
                 ("dt", c_double), ("cfl", c_double), ("small_angle", c_double),
-                ("charge_scale", c_double), ("n_r", c_int32), ("n_th", c_int32),
+                ("charge_scale", c_double), ("iter_tol", c_double), ("n_r", c_int32),
+                ("n_th", c_int32),
                 ("n_ghost", c_int32), ("n_iter", c_int32), ("n_filter", c_int32),
                 ("n_absorb", c_int32), ("precision", c_int32), ("reserved", c_int32)]
 
@@ -110,9 +111,10 @@ class Context:
 
     def __init__(self, a, M, r_min, r_max, n_r, n_th, dt=0.0, cfl=0.5, n_iter=10,
                  small_angle=1e-5, charge_scale=0.0, n_filter=0, n_absorb=0,
-                 precision=GRPIC_FP64, n_ghost=2):
+                 precision=GRPIC_FP64, n_ghost=2, iter_tol=0.0):
         p = Params(a=a, M=M, r_min=r_min, r_max=r_max, dt=dt, cfl=cfl, small_angle=small_angle,
-                   charge_scale=charge_scale, n_r=n_r, n_th=n_th, n_ghost=n_ghost,
+                   charge_scale=charge_scale, iter_tol=iter_tol, n_r=n_r, n_th=n_th,
+                   n_ghost=n_ghost,
                    n_iter=n_iter, n_filter=n_filter, n_absorb=n_absorb, precision=precision,
                    reserved=0)
         h = c_void_p()
