@@ -37,10 +37,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2_512")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
+                    help="storage precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--iter-tol", type=float, default=0.0,
                     help="FP64 convergence test of the implicit iterations (0: fixed count)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="separate push and deposit passes (default: one fused pass)")
     ap.add_argument("--sort-every", type=int, default=10,
                     help="cell-sort the particles every k steps (0: never)")
     return ap.parse_args()
@@ -52,8 +56,8 @@ def cpu_baseline(w, dt):
     import numpy as np  # noqa: F401
     import oracle as O
     prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, dt, n_iter=w.n_iter,
-                        small_angle=w.small_angle, charge_scale=0.0, n_filter=w.n_filter,
-                        n_absorb=w.n_absorb)
+                        small_angle=w.small_angle, charge_scale=w.charge_scale,
+                        n_filter=w.n_filter, n_absorb=w.n_absorb)
     F = O.fields_init_wald(prm, w.B0)
     P = O.particles_init(prm, w.n_pairs_total if w.ppc == 0 else 0, w.ppc, w.T, w.n_geo, w.seed)
     n = int((P["tag"] != 0).sum())
@@ -83,13 +87,13 @@ def main():
     from paper_2511_17701_amd.workloads import WORKLOADS
 
     w = WORKLOADS[ARGS.workload]
-    if w.precision != "fp64":
-        raise SystemExit(f"workload {w.name} needs the {w.precision} form")
+    precision = ARGS.precision or w.precision
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     ctx = grpic.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, cfl=w.cfl, n_iter=w.n_iter,
-                        small_angle=w.small_angle, charge_scale=0.0, n_filter=w.n_filter,
-                        n_absorb=w.n_absorb, iter_tol=ARGS.iter_tol)
+                        small_angle=w.small_angle, charge_scale=w.charge_scale,
+                        n_filter=w.n_filter, n_absorb=w.n_absorb, iter_tol=ARGS.iter_tol,
+                        precision=grpic.GRPIC_FP32 if precision == "fp32" else grpic.GRPIC_FP64)
     F = ctx.new_fields(dev)
     ctx.fields_init_wald(F, w.B0)
     P = ctx.new_particles(w.n_particles, dev)
@@ -106,10 +110,14 @@ def main():
             ctx.field_advance(F, grpic.PRE_PUSH)
         if ev is not None:
             ev[0].record()
-        ctx.push(F, P)
+        if ARGS.unfused:
+            ctx.push(F, P)
+        else:
+            ctx.push_deposit(F, P)
         if ev is not None:
             ev[1].record()
-        ctx.deposit(P, F)
+        if ARGS.unfused:
+            ctx.deposit(P, F)
         if ev is not None:
             ev[2].record()
         if w.full_step:
@@ -153,18 +161,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == "fp64" else "f32 (FP64 horizon metric)",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": f"{w.n_r}x{w.n_th}", "a": w.a,
                    "r_range": [w.r_min, w.r_max], "particles": w.n_particles, "ppc": w.ppc,
                    "test_geodesics": w.n_geo, "T": w.T, "B0": w.B0, "n_iter": w.n_iter,
-                   "dt": ctx.dt, "full_step": w.full_step, "precision": w.precision,
+                   "dt": ctx.dt, "full_step": w.full_step, "precision": precision,
+                   "charge_scale": w.charge_scale,
                    "sort_every": ARGS.sort_every, "iter_tol": ARGS.iter_tol},
         "roofline": {"bound": "hbm", "kernel": "push_kernel", "achieved": push_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": push_gbs / HBM_PEAK_GBS,
                      "traffic": None,
                      "bytes_per_particle": PUSH_BYTES_FP64, "avg_launch_ms": push_ms},
-        "kernels_ms_per_step": {"push": push_ms, "deposit": dep_ms,
+        "kernels_ms_per_step": {"push" if ARGS.unfused else "push_deposit": push_ms,
+                                "deposit": dep_ms,
                                 "fields_and_rest": ms - push_ms - dep_ms},
         "push_deposit_rate": live / ((push_ms + dep_ms) * 1e-3),
         "live_particles": [live0, live1],

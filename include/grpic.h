@@ -92,16 +92,22 @@ typedef struct {
   int32_t reserved;     /* must be 0                                         */
 } grpic_params;
 
-/* Device pointers to the 33 field planes (Sec. 3.4 storage):
+/* Device pointers to the field planes (Sec. 3.4 storage):
  * D, B   = em   (D^n, B^{n-1/2});
  * D0, B0 = em0  (D^{n-1}, B^{n-3/2} at a step boundary; B0 holds B^n after
  *          the pre-push stage, which is what the push interpolates);
  * E, H   = aux; J = cur (J^{n+1/2}, accumulated by the deposit);
  * J0     = cur0 (J^{n-1/2}); Dinit, Binit = targets of the absorbing layer;
- * T      = scratch. */
+ * T      = scratch;
+ * Dc, Bc = GRPIC_FP32 only (ignored, may be NULL, for GRPIC_FP64): low-order
+ *          parts of D and B.  The time integration keeps D + Dc and B + Bc to
+ *          about 48 bits and stores their rounding to float in D and B, which
+ *          is what every other stage reads; grpic_fields_init_wald zeroes them.
+ * The 33 (FP64) or 39 (FP32) planes may be separate allocations. */
 typedef struct {
   void *D[3], *B[3], *D0[3], *B0[3], *E[3], *H[3], *J[3], *J0[3];
   void *Dinit[3], *Binit[3], *T[3];
+  void *Dc[3], *Bc[3];
 } grpic_fields;
 
 typedef struct {
@@ -152,7 +158,7 @@ grpic_status grpic_particles_init(grpic_ctx* ctx, const grpic_particles* P, int6
 
 /* Wald vacuum field of amplitude B0 (Sec. 4.1.2, eq. Wald): B from the
  * discrete curl of A_mu (eq. EB-set), D from the analytic solution; fills D, B,
- * D0, B0, Dinit, Binit, zeroes E, H, J, J0, T. */
+ * D0, B0, Dinit, Binit, zeroes E, H, J, J0, T (and Dc, Bc in GRPIC_FP32). */
 grpic_status grpic_fields_init_wald(grpic_ctx* ctx, const grpic_fields* F, double B0,
                                     void* stream);
 
@@ -168,6 +174,14 @@ grpic_status grpic_push(grpic_ctx* ctx, const grpic_fields* F, const grpic_parti
  * field stage does). */
 grpic_status grpic_deposit(grpic_ctx* ctx, const grpic_particles* P, const grpic_fields* F,
                            void* stream);
+
+/* grpic_push followed by grpic_deposit in one pass over the particles (same
+ * arguments, same results up to rounding order): the deposit takes each move
+ * from registers and J^3 from the push's own evaluation of the phi velocity
+ * at the path midpoint (Sec. 3.1 step 10, Sec. 3.2), so the previous
+ * positions are written but not read back. */
+grpic_status grpic_push_deposit(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,
+                                void* stream);
 
 /* Field stages of the PIC loop (Sec. 3.4): stage GRPIC_FIELDS_PRE_PUSH or
  * GRPIC_FIELDS_POST_DEPOSIT (grpic_field_stage). */

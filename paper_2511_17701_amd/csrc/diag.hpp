@@ -17,9 +17,10 @@ struct DiagAcc {
 
 constexpr int kDiagBlock = 256;
 
+template <class T>
 __global__ void __launch_bounds__(kDiagBlock)
-diag_particles_kernel(Grid g, ParticleArrays P, double B0, double* __restrict__ Eout,
-                      double* __restrict__ Lout, DiagAcc* acc) {
+diag_particles_kernel(Grid g, ParticleArraysT<T> P, double B0, T* __restrict__ Eout,
+                      T* __restrict__ Lout, DiagAcc* acc) {
   __shared__ unsigned long long sc[8][kDiagBlock / 64];
   __shared__ double ss[8][kDiagBlock / 64];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,7 +86,8 @@ diag_particles_kernel(Grid g, ParticleArrays P, double B0, double* __restrict__ 
 }
 
 // first-order charge sqrt(h) rho = sum q S at the nodes around the current positions
-__global__ void charge_kernel(Grid g, ParticleArrays P, double* __restrict__ Q) {
+template <class T>
+__global__ void charge_kernel(Grid g, ParticleArraysT<T> P, T* __restrict__ Q) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P.n) return;
   const uint8_t t = P.tag[k];
@@ -95,17 +97,18 @@ __global__ void charge_kernel(Grid g, ParticleArrays P, double* __restrict__ Q) 
   const double q = sg * g.charge_scale * P.w[k];
   const double w1 = P.dx1[k], w2 = P.dx2[k];
   if (!in_deposit_range(g, P.i1[k], w1, P.i2[k], w2)) return;
-  double* p = Q + ix(g, P.i1[k], P.i2[k]);
-  atomic_add(p, q * (1.0 - w1) * (1.0 - w2));
-  atomic_add(p + 1, q * (1.0 - w1) * w2);
-  atomic_add(p + g.ld, q * w1 * (1.0 - w2));
-  atomic_add(p + g.ld + 1, q * w1 * w2);
+  T* p = Q + ix(g, P.i1[k], P.i2[k]);
+  atomic_add(p, (T)(q * (1.0 - w1) * (1.0 - w2)));
+  atomic_add(p + 1, (T)(q * (1.0 - w1) * w2));
+  atomic_add(p + g.ld, (T)(q * w1 * (1.0 - w2)));
+  atomic_add(p + g.ld + 1, (T)(q * w1 * w2));
 }
 
 // residual div D - 4 pi rho at nodes i in [n_f + 2, n_r - n_absorb), j in [1, n_th)
-__global__ void gauss_kernel(Grid g, Tables t, const double* __restrict__ D1,
-                             const double* __restrict__ D2, const double* __restrict__ Q,
-                             double* __restrict__ res, DiagAcc* acc) {
+template <class T>
+__global__ void gauss_kernel(Grid g, Tables t, const T* __restrict__ D1,
+                             const T* __restrict__ D2, const T* __restrict__ Q,
+                             T* __restrict__ res, DiagAcc* acc) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x + 1;
   const int i = blockIdx.y * blockDim.y + threadIdx.y + g.n_filter + 2;
   double rmax = 0.0, smax = 0.0;
@@ -132,7 +135,8 @@ __global__ void gauss_kernel(Grid g, Tables t, const double* __restrict__ D1,
 }
 
 // even-parity theta ghosts of a node-located scalar plane
-__global__ void scalar_axis_kernel(Grid g, double* __restrict__ C) {
+template <class T>
+__global__ void scalar_axis_kernel(Grid g, T* __restrict__ C) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
   if (i >= g.n_r + g.ng) return;
   for (int k = 1; k <= g.ng; ++k) C[ix(g, i, -k)] = C[ix(g, i, k)];

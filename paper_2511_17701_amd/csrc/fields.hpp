@@ -1,4 +1,9 @@
-// fields.hpp -- field-solver kernels (Sec. 3.3, 3.4), FP64 form.
+// fields.hpp -- field-solver kernels (Sec. 3.3, 3.4).
+//
+// Kernels are templated on the storage type T of the planes (double, or float
+// in the single-precision form); the metric weights and the update arithmetic
+// are FP64 and each result is rounded once on store.  The solver is bound by
+// plane traffic, so the FP64 arithmetic costs nothing.
 //
 // Threads run along theta (the contiguous index of a plane), blocks along r.
 // Geometry at staggered grid points is assembled from 1-D tables of r at
@@ -31,18 +36,39 @@ __device__ inline Cell cell_tab(const Grid& g, const Tables& t, int i, int o1, i
   return e;
 }
 
-struct Tri {
-  double* __restrict__ p[3];
+template <class T>
+struct TriT {
+  T* __restrict__ p[3];
 };
-struct CTri {
-  const double* __restrict__ p[3];
+template <class T>
+struct CTriT {
+  const T* __restrict__ p[3];
 };
+using Tri = TriT<double>;
+using CTri = CTriT<double>;
+
+// X[o] += inc.  In the single-precision form the evolved fields D and B carry
+// a compensation plane L (null otherwise): X + L holds the running sum to about
+// 48 bits and X, what every reader sees, is its rounding to float, so rounding
+// errors of the time integration do not accumulate step after step.
+template <class T>
+__device__ inline void add_to(T* __restrict__ X, T* __restrict__ L, int64_t o, double inc) {
+  if (sizeof(T) == 4 && L) {
+    const double v = ((double)X[o] + (double)L[o]) + inc;
+    const T h = (T)v;
+    X[o] = h;
+    L[o] = (T)(v - (double)h);
+  } else {
+    X[o] = (T)((double)X[o] + inc);
+  }
+}
 
 // ---------------------------------------------------------------- aux E, H
 // eq. discretized-auxE/-auxH with the volume-weighted radial averages of
 // Sec. 3.3.1 (weights sqrt(h)/sin(theta)); for i in [-1, n_r], j in [0, n_th].
 
-__global__ void aux_e_kernel(Grid g, Tables t, CTri Bs, CTri Ds, Tri E) {
+template <class T>
+__global__ void aux_e_kernel(Grid g, Tables t, CTriT<T> Bs, CTriT<T> Ds, TriT<T> E) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y - 1;
   if (j > g.n_th || i > g.n_r) return;
@@ -72,7 +98,8 @@ __global__ void aux_e_kernel(Grid g, Tables t, CTri Bs, CTri Ds, Tri E) {
   }
 }
 
-__global__ void aux_h_kernel(Grid g, Tables t, CTri Bs, CTri Ds, Tri H) {
+template <class T>
+__global__ void aux_h_kernel(Grid g, Tables t, CTriT<T> Bs, CTriT<T> Ds, TriT<T> H) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y - 1;
   if (j > g.n_th || i > g.n_r) return;
@@ -107,23 +134,24 @@ __global__ void aux_h_kernel(Grid g, Tables t, CTri Bs, CTri Ds, Tri H) {
 // ---------------------------------------------------------------- Faraday
 // eq. discretized-faraday on the evolved ranges (thread (i, j), i in [0, n_r],
 // j in [0, n_th]).
-__global__ void faraday_kernel(Grid g, Tables t, Tri X, CTri E) {
+template <class T>
+__global__ void faraday_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> E) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y;
   if (j > g.n_th || i > g.n_r) return;
   const int64_t o = ix(g, i, j);
   if (j < g.n_th) {
     const Cell c = cell_tab(g, t, i, 0, j, 1);
-    X.p[0][o] -= g.dt * (E.p[2][o + 1] - E.p[2][o]) / c.sqrt_h;
+    add_to(X.p[0], L.p[0], o, -(g.dt * (E.p[2][o + 1] - E.p[2][o]) / c.sqrt_h));
   }
   if (i < g.n_r && j >= 1 && j < g.n_th) {
     const Cell c = cell_tab(g, t, i, 1, j, 0);
-    X.p[1][o] += g.dt * (E.p[2][o + g.ld] - E.p[2][o]) / c.sqrt_h;
+    add_to(X.p[1], L.p[1], o, g.dt * (E.p[2][o + g.ld] - E.p[2][o]) / c.sqrt_h);
   }
   if (i < g.n_r && j < g.n_th) {
     const Cell c = cell_tab(g, t, i, 1, j, 1);
     const double curl = (E.p[1][o + g.ld] - E.p[1][o]) - (E.p[0][o + 1] - E.p[0][o]);
-    X.p[2][o] -= g.dt * curl / c.sqrt_h;
+    add_to(X.p[2], L.p[2], o, -(g.dt * curl / c.sqrt_h));
   }
 }
 
@@ -132,7 +160,8 @@ __global__ void faraday_kernel(Grid g, Tables t, Tri X, CTri E) {
 // polar-cap integral form (Sec. 3.3.2): cap area A_{i+1/2}; the theta = pi cap
 // has the opposite orientation, and the one-sided axis-row current enters
 // with 4 pi.
-__global__ void ampere_kernel(Grid g, Tables t, Tri X, CTri H, CTri Ja, CTri Jb, double wa,
+template <class T>
+__global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H, CTriT<T> Ja, CTriT<T> Jb, double wa,
                               double wb, double polar_k) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y;
@@ -143,25 +172,25 @@ __global__ void ampere_kernel(Grid g, Tables t, Tri X, CTri H, CTri Ja, CTri Jb,
     const double J1 = wa * Ja.p[0][o] + wb * Jb.p[0][o];
     if (j >= 1 && j < g.n_th) {
       const Cell c = cell_tab(g, t, i, 1, j, 0);
-      X.p[0][o] += g.dt * ((H.p[2][o] - H.p[2][o - 1]) - fpi * J1) / c.sqrt_h;
+      add_to(X.p[0], L.p[0], o, g.dt * ((H.p[2][o] - H.p[2][o - 1]) - fpi * J1) / c.sqrt_h);
     } else {
       const double r = t.r[1][i + g.ng];
       const double ra = r * r + g.a * g.a;
       const double Ap = g.dxi * r * ra * sqrt(1.0 + 2.0 * g.M * r / ra) * polar_k;
       const double h3 = (j == 0) ? H.p[2][o] : -H.p[2][o - 1];
-      X.p[0][o] += g.dt * (h3 - fpi * J1) / Ap;
+      add_to(X.p[0], L.p[0], o, g.dt * (h3 - fpi * J1) / Ap);
     }
   }
   if (j < g.n_th) {
     const Cell c = cell_tab(g, t, i, 0, j, 1);
     const double J2 = wa * Ja.p[1][o] + wb * Jb.p[1][o];
-    X.p[1][o] += g.dt * (-(H.p[2][o] - H.p[2][o - g.ld]) - fpi * J2) / c.sqrt_h;
+    add_to(X.p[1], L.p[1], o, g.dt * (-(H.p[2][o] - H.p[2][o - g.ld]) - fpi * J2) / c.sqrt_h);
   }
   if (j >= 1 && j < g.n_th) {
     const Cell c = cell_tab(g, t, i, 0, j, 0);
     const double J3 = wa * Ja.p[2][o] + wb * Jb.p[2][o];
     const double curl = (H.p[1][o] - H.p[1][o - g.ld]) - (H.p[0][o] - H.p[0][o - 1]);
-    X.p[2][o] += g.dt * (curl - fpi * J3) / c.sqrt_h;
+    add_to(X.p[2], L.p[2], o, g.dt * (curl - fpi * J3) / c.sqrt_h);
   }
 }
 
@@ -170,7 +199,8 @@ __global__ void ampere_kernel(Grid g, Tables t, Tri X, CTri H, CTri Ja, CTri Jb,
 // absorbing layer (F <- F - lambda (F - F_init), lambda a cubic ramp over the
 // last n_absorb cells); whole plane incl. ghosts.  half1[c] = staggering of
 // component c in x1.
-__global__ void bc_radial_kernel(Grid g, Tri X, CTri X0, int3 half1) {
+template <class T>
+__global__ void bc_radial_kernel(Grid g, TriT<T> X, TriT<T> L, CTriT<T> X0, int3 half1) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
   const int i = blockIdx.y * blockDim.y + threadIdx.y - g.ng;
   if (j >= g.n_th + g.ng || i >= g.n_r + g.ng) return;
@@ -180,13 +210,22 @@ __global__ void bc_radial_kernel(Grid g, Tri X, CTri X0, int3 half1) {
   for (int c = 0; c < 3; ++c) {
     if (i <= g.n_filter) {
       X.p[c][o] = X.p[c][ix(g, g.n_filter + 1, j)];
+      if (sizeof(T) == 4 && L.p[c]) L.p[c][o] = L.p[c][ix(g, g.n_filter + 1, j)];
     } else if (g.n_absorb > 0) {
       const double x = (double)i + 0.5 * hs[c];
       const double x0 = (double)(g.n_r - g.n_absorb);
       if (x > x0) {
         const double s = fmin((x - x0) / g.n_absorb, 1.0);
         const double lam = s * s * s;
-        X.p[c][o] = X.p[c][o] - lam * (X.p[c][o] - X0.p[c][o]);
+        if (sizeof(T) == 4 && L.p[c]) {
+          const double v = (double)X.p[c][o] + (double)L.p[c][o];
+          const double w = v - lam * (v - X0.p[c][o]);
+          const T h = (T)w;
+          X.p[c][o] = h;
+          L.p[c][o] = (T)(w - (double)h);
+        } else {
+          X.p[c][o] = X.p[c][o] - lam * (X.p[c][o] - X0.p[c][o]);
+        }
       }
     }
   }
@@ -195,7 +234,8 @@ __global__ void bc_radial_kernel(Grid g, Tri X, CTri X0, int3 half1) {
 // Axis reflection (Sec. 3.3.3): r-components even, theta and phi components
 // odd; with zero_axis, the theta component of B (B^2) or the phi component of
 // D (D^3) vanishes on the axis rows.  half2[c] = staggering in x2.
-__global__ void bc_axis_kernel(Grid g, Tri X, int3 half2, int zero_comp) {
+template <class T>
+__global__ void bc_axis_kernel(Grid g, TriT<T> X, TriT<T> L, int3 half2, int zero_comp) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
   if (i >= g.n_r + g.ng) return;
   const int hs[3] = {half2.x, half2.y, half2.z};
@@ -203,11 +243,15 @@ __global__ void bc_axis_kernel(Grid g, Tri X, int3 half2, int zero_comp) {
   const int n = g.n_th;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double* C = X.p[c];
+    T* C = X.p[c];
     if (!hs[c]) {
       if (c == zero_comp) {
         C[ix(g, i, 0)] = 0.0;
         C[ix(g, i, n)] = 0.0;
+        if (sizeof(T) == 4 && L.p[c]) {
+          L.p[c][ix(g, i, 0)] = 0.0;
+          L.p[c][ix(g, i, n)] = 0.0;
+        }
       }
       // node rows run 0..n: ng ghost rows below the axis, ng - 1 above
       for (int k = 1; k <= g.ng; ++k) C[ix(g, i, -k)] = par[c] * C[ix(g, i, k)];
@@ -223,21 +267,24 @@ __global__ void bc_axis_kernel(Grid g, Tri X, int3 half2, int zero_comp) {
 
 // ---------------------------------------------------------------- misc
 // elementwise over ncomp planes (whole planes incl. ghosts)
-__global__ void average_kernel(int64_t n, Tri A, CTri B) {  // A <- (A + B) / 2
+template <class T>
+__global__ void average_kernel(int64_t n, TriT<T> A, CTriT<T> B) {  // A <- (A + B) / 2
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
 #pragma unroll
   for (int c = 0; c < 3; ++c) A.p[c][k] = 0.5 * (A.p[c][k] + B.p[c][k]);
 }
 
-__global__ void copy_kernel(int64_t n, Tri A, CTri B) {  // A <- B
+template <class T>
+__global__ void copy_kernel(int64_t n, TriT<T> A, CTriT<T> B) {  // A <- B
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
 #pragma unroll
   for (int c = 0; c < 3; ++c) A.p[c][k] = B.p[c][k];
 }
 
-__global__ void rotate_currents_kernel(int64_t n, Tri J0, Tri J) {  // J0 <- J, J <- 0
+template <class T>
+__global__ void rotate_currents_kernel(int64_t n, TriT<T> J0, TriT<T> J) {  // J0 <- J, J <- 0
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
 #pragma unroll
@@ -247,14 +294,16 @@ __global__ void rotate_currents_kernel(int64_t n, Tri J0, Tri J) {  // J0 <- J, 
   }
 }
 
-__global__ void fill_kernel(int64_t n, double* __restrict__ p, double v) {
+template <class T>
+__global__ void fill_kernel(int64_t n, T* __restrict__ p, double v) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
 }
 
 // One binomial pass (1,2,1)/4 x (1,2,1)/4 from S into X for i in
 // [1 - ng, n_r + ng - 2], j in [0, n_th - half2[c]].
-__global__ void filter_kernel(Grid g, Tri X, CTri S, int3 half2, int ncomp) {
+template <class T>
+__global__ void filter_kernel(Grid g, TriT<T> X, CTriT<T> S, int3 half2, int ncomp) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y + 1 - g.ng;
   if (j > g.n_th || i > g.n_r + g.ng - 2) return;
@@ -262,7 +311,7 @@ __global__ void filter_kernel(Grid g, Tri X, CTri S, int3 half2, int ncomp) {
   const int64_t o = ix(g, i, j);
   for (int c = 0; c < ncomp; ++c) {
     if (j > g.n_th - hs[c]) continue;
-    const double* s = S.p[c];
+    const T* s = S.p[c];
     const double r0 = s[o - g.ld - 1] + 2.0 * s[o - g.ld] + s[o - g.ld + 1];
     const double r1 = s[o - 1] + 2.0 * s[o] + s[o + 1];
     const double r2 = s[o + g.ld - 1] + 2.0 * s[o + g.ld] + s[o + g.ld + 1];

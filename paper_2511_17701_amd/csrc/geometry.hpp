@@ -36,6 +36,8 @@ struct Grid {
   int n_r, n_th, ng, ld;  // ld = n_th + 2 ng (row length of a plane)
   int n_iter, n_filter, n_absorb;
   int fast;               // offsets small enough for the polynomial path
+  int i_fp64;             // single-precision push: cells i1 < i_fp64 (r < 3 M, the
+                          // horizon region) take the metric and its derivatives in FP64
   int64_t plane;          // reals per plane
 };
 
@@ -43,34 +45,47 @@ __host__ __device__ inline int64_t ix(const Grid& g, int i, int j) {
   return (int64_t)(i + g.ng) * g.ld + (j + g.ng);
 }
 
-// 1-D coordinate tables, indexed by (index + ng); [0] integer, [1] half-integer.
+// 1-D coordinate tables, indexed by (index + ng); [0] integer, [1] half-integer;
+// rf, sf, cf: single-precision copies of the integer-point tables.
 struct Tables {
   const double* __restrict__ r[2];
   const double* __restrict__ s[2];
   const double* __restrict__ c[2];
+  const float* __restrict__ rf;
+  const float* __restrict__ sf;
+  const float* __restrict__ cf;
 };
 
 // Pusher coefficients at a point: lapse, shift and inverse spatial metric.
-struct Coeffs {
-  double alpha, beta1, hu11, hu22, hu33, hu13;
+template <class R>
+struct CoeffsT {
+  R alpha, beta1, hu11, hu22, hu33, hu13;
 };
 
 // Coefficients plus the tetrad factors of App. A at a point:
 // s11 = sqrt(h^11), s22 = sqrt(h_22), s33 = sqrt(h_33), k13 = h_13 / h_33.
-struct Frame {
-  Coeffs c;
-  double s11, s22, s33, k13;
+template <class R>
+struct FrameT {
+  CoeffsT<R> c;
+  R s11, s22, s33, k13;
 };
 
 // d/dx1 ([0]) and d/dx2 ([1]) of the pusher coefficients.
-struct Grad {
-  double alpha[2], beta1[2], hu11[2], hu22[2], hu33[2], hu13[2];
+template <class R>
+struct GradT {
+  R alpha[2], beta1[2], hu11[2], hu22[2], hu33[2], hu13[2];
 };
 
 // r, sin(theta), cos(theta) of a point
-struct RSC {
-  double r, s, c;
+template <class R>
+struct RSCT {
+  R r, s, c;
 };
+
+using Coeffs = CoeffsT<double>;
+using Frame = FrameT<double>;
+using Grad = GradT<double>;
+using RSC = RSCT<double>;
 
 __host__ __device__ inline double clamp_theta(const Grid& g, double th) {
   return fmin(fmax(th, g.small_angle), kPi - g.small_angle);
@@ -85,8 +100,9 @@ __host__ __device__ inline void sin_cos(double th, double* s, double* c) {
 #endif
 }
 
-// 1/x and 1/sqrt(x) for positive normal x: hardware seeds refined by two
-// Newton steps on the device (error ~1 ulp), plain division on the host.
+// 1/x and 1/sqrt(x) for positive normal x: hardware seeds refined by Newton
+// steps on the device (two in double, one in single; error ~1 ulp), plain
+// division on the host.
 __host__ __device__ inline double rcp(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
   double y = __builtin_amdgcn_rcp(x);
@@ -112,6 +128,24 @@ __host__ __device__ inline double rsqrt(double x) {
 #endif
 }
 
+__host__ __device__ inline float rcp(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(y, fmaf(-x, y, 1.0f), y);
+#else
+  return 1.0f / x;
+#endif
+}
+
+__host__ __device__ inline float rsqrt(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const float y = __builtin_amdgcn_rsqf(x);
+  return fmaf(y, fmaf(-0.5f * x * y, y, 0.5f), y);
+#else
+  return 1.0f / std::sqrt(x);
+#endif
+}
+
 // r and clamped sin/cos by the library functions
 __host__ __device__ inline RSC rsc_direct(const Grid& g, double x1, double x2) {
   RSC p;
@@ -121,26 +155,27 @@ __host__ __device__ inline RSC rsc_direct(const Grid& g, double x1, double x2) {
 }
 
 // Inverse metric, lapse and shift at a point (R = dxi r).
-__host__ __device__ inline Coeffs coeffs_from(const Grid& g, RSC p) {
-  const double r = p.r, s = p.s, c = p.c;
-  const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r;
-  const double Sig = r2 + a2 * c * c;
-  const double S2 = Sig + tMr;
-  const double ra = r2 + a2;
-  const double s2 = s * s;
-  const double A = ra * ra - a2 * (ra - tMr) * s2;
-  const double R = g.dxi * r;
+template <class R>
+__host__ __device__ inline CoeffsT<R> coeffs_from(const Grid& g, RSCT<R> p) {
+  const R r = p.r, s = p.s, c = p.c;
+  const R a = (R)g.a, a2 = a * a, r2 = r * r, tMr = (R)(2.0 * g.M) * r;
+  const R Sig = r2 + a2 * c * c;
+  const R S2 = Sig + tMr;
+  const R ra = r2 + a2;
+  const R s2 = s * s;
+  const R A = ra * ra - a2 * (ra - tMr) * s2;
+  const R Rr = (R)g.dxi * r;
   // one reciprocal for 1/Sigma, 1/S2, 1/sin^2 and 1/R
-  const double q = rcp(Sig * S2 * s2 * R);
-  const double iSig = S2 * s2 * R * q, iS2 = Sig * s2 * R * q;
-  const double is2 = Sig * S2 * R * q, iR = Sig * S2 * s2 * q;
-  Coeffs m;
-  const double y = Sig * iS2;
+  const R q = rcp(Sig * S2 * s2 * Rr);
+  const R iSig = S2 * s2 * Rr * q, iS2 = Sig * s2 * Rr * q;
+  const R is2 = Sig * S2 * Rr * q, iR = Sig * S2 * s2 * q;
+  CoeffsT<R> m;
+  const R y = Sig * iS2;
   m.alpha = y * rsqrt(y);
   m.beta1 = tMr * iS2 * iR;
   m.hu11 = A * iSig * iS2 * iR * iR;
-  m.hu13 = g.a * iSig * iR;
-  m.hu22 = iSig * g.inv_dth2;
+  m.hu13 = a * iSig * iR;
+  m.hu22 = iSig * (R)g.inv_dth2;
   m.hu33 = iSig * is2;
   return m;
 }
@@ -150,66 +185,67 @@ __host__ __device__ inline Coeffs coeffs_at(const Grid& g, double x1, double x2)
 }
 
 // Coefficients, tetrad factors and first derivatives at a point.
-__host__ __device__ inline void frame_from(const Grid& g, RSC p, Frame* f, Grad* d) {
-  const double r = p.r, s = p.s, c = p.c;
-  const double a = g.a, M = g.M;
-  const double a2 = a * a, r2 = r * r, tMr = 2.0 * M * r;
-  const double Sig = r2 + a2 * c * c;
-  const double S2 = Sig + tMr;
-  const double ra = r2 + a2;
-  const double Del = ra - tMr;
-  const double s2 = s * s;
-  const double A = ra * ra - a2 * Del * s2;
-  const double R = g.dxi * r;
-  const double q = rcp(Sig * S2 * s2 * R * A);
-  const double iSig = S2 * s2 * R * A * q, iS2 = Sig * s2 * R * A * q;
-  const double is2 = Sig * S2 * R * A * q, iR = Sig * S2 * s2 * A * q;
-  const double iA = Sig * S2 * s2 * R * q;
-  const double y = Sig * iS2;
-  const double ialpha = rsqrt(y);
-  const double alpha = y * ialpha;
+template <class R>
+__host__ __device__ inline void frame_from(const Grid& g, RSCT<R> p, FrameT<R>* f, GradT<R>* d) {
+  const R r = p.r, s = p.s, c = p.c;
+  const R a = (R)g.a, M = (R)g.M, dxi = (R)g.dxi, dth = (R)g.dth;
+  const R a2 = a * a, r2 = r * r, tMr = (R)2 * M * r;
+  const R Sig = r2 + a2 * c * c;
+  const R S2 = Sig + tMr;
+  const R ra = r2 + a2;
+  const R Del = ra - tMr;
+  const R s2 = s * s;
+  const R A = ra * ra - a2 * Del * s2;
+  const R Rr = dxi * r;
+  const R q = rcp(Sig * S2 * s2 * Rr * A);
+  const R iSig = S2 * s2 * Rr * A * q, iS2 = Sig * s2 * Rr * A * q;
+  const R is2 = Sig * S2 * Rr * A * q, iR = Sig * S2 * s2 * A * q;
+  const R iA = Sig * S2 * s2 * Rr * q;
+  const R y = Sig * iS2;
+  const R ialpha = rsqrt(y);
+  const R alpha = y * ialpha;
 
   f->c.alpha = alpha;
   f->c.beta1 = tMr * iS2 * iR;
-  const double hrr = A * iSig * iS2;
+  const R hrr = A * iSig * iS2;
   f->c.hu11 = hrr * iR * iR;
   f->c.hu13 = a * iSig * iR;
-  f->c.hu22 = iSig * g.inv_dth2;
+  f->c.hu22 = iSig * (R)g.inv_dth2;
   f->c.hu33 = iSig * is2;
   f->s11 = hrr * rsqrt(hrr) * iR;
-  f->s22 = Sig * rsqrt(Sig) * g.dth;
-  const double AiS = A * iSig;
+  f->s22 = Sig * rsqrt(Sig) * dth;
+  const R AiS = A * iSig;
   f->s33 = AiS * rsqrt(AiS) * s;
-  f->k13 = -a * R * S2 * iA;
+  f->k13 = -a * Rr * S2 * iA;
 
   // radial and polar derivatives of Sigma, A (S2 shares dSigma/dtheta)
-  const double dSig_r = 2.0 * r, dSig_t = -2.0 * a2 * s * c;
-  const double dA_r = 4.0 * r * ra - a2 * s2 * (2.0 * r - 2.0 * M);
-  const double dA_t = -2.0 * a2 * Del * s * c;
-  const double iS22 = iS2 * iS2, iSig2 = iSig * iSig;
+  const R dSig_r = (R)2 * r, dSig_t = (R)-2 * a2 * s * c;
+  const R dA_r = (R)4 * r * ra - a2 * s2 * ((R)2 * r - (R)2 * M);
+  const R dA_t = (R)-2 * a2 * Del * s * c;
+  const R iS22 = iS2 * iS2, iSig2 = iSig * iSig;
 
   // alpha
-  d->alpha[0] = R * M * (2.0 * r2 - Sig) * ialpha * iS22;
-  d->alpha[1] = g.dth * M * r * dSig_t * ialpha * iS22;
+  d->alpha[0] = Rr * M * ((R)2 * r2 - Sig) * ialpha * iS22;
+  d->alpha[1] = dth * M * r * dSig_t * ialpha * iS22;
   // beta^1 = beta^r / R
-  const double dbr_r = 2.0 * M * (Sig - 2.0 * r2) * iS22;
-  const double dbr_t = -tMr * dSig_t * iS22;
-  d->beta1[0] = dbr_r - g.dxi * f->c.beta1;
-  d->beta1[1] = g.dth * dbr_t * iR;
+  const R dbr_r = (R)2 * M * (Sig - (R)2 * r2) * iS22;
+  const R dbr_t = -tMr * dSig_t * iS22;
+  d->beta1[0] = dbr_r - dxi * f->c.beta1;
+  d->beta1[1] = dth * dbr_t * iR;
   // h^11 = h^rr / R^2
-  const double dhrr_r = (dA_r - hrr * (dSig_r * S2 + Sig * (dSig_r + 2.0 * M))) * iSig * iS2;
-  const double dhrr_t = (dA_t - hrr * 2.0 * dSig_t * (Sig + M * r)) * iSig * iS2;
-  d->hu11[0] = dhrr_r * iR - 2.0 * g.dxi * f->c.hu11;
-  d->hu11[1] = g.dth * dhrr_t * iR * iR;
+  const R dhrr_r = (dA_r - hrr * (dSig_r * S2 + Sig * (dSig_r + (R)2 * M))) * iSig * iS2;
+  const R dhrr_t = (dA_t - hrr * (R)2 * dSig_t * (Sig + M * r)) * iSig * iS2;
+  d->hu11[0] = dhrr_r * iR - (R)2 * dxi * f->c.hu11;
+  d->hu11[1] = dth * dhrr_t * iR * iR;
   // h^13 = a / (Sigma R)
-  d->hu13[0] = -a * dSig_r * iSig2 - g.dxi * f->c.hu13;
-  d->hu13[1] = -g.dth * a * dSig_t * iSig2 * iR;
+  d->hu13[0] = -a * dSig_r * iSig2 - dxi * f->c.hu13;
+  d->hu13[1] = -dth * a * dSig_t * iSig2 * iR;
   // h^22 = 1 / (Sigma dth^2)
-  d->hu22[0] = -R * dSig_r * iSig2 * g.inv_dth2;
-  d->hu22[1] = -dSig_t * iSig2 * (g.dth * g.inv_dth2);
+  d->hu22[0] = -Rr * dSig_r * iSig2 * (R)g.inv_dth2;
+  d->hu22[1] = -dSig_t * iSig2 * (R)(g.dth * g.inv_dth2);
   // h^33 = 1 / (Sigma sin^2)
-  d->hu33[0] = -R * dSig_r * iSig2 * is2;
-  d->hu33[1] = -g.dth * (dSig_t + 2.0 * Sig * c * s * is2) * iSig2 * is2;
+  d->hu33[0] = -Rr * dSig_r * iSig2 * is2;
+  d->hu33[1] = -dth * (dSig_t + (R)2 * Sig * c * s * is2) * iSig2 * is2;
 }
 
 __host__ __device__ inline void frame_at(const Grid& g, double x1, double x2, Frame* f, Grad* d) {

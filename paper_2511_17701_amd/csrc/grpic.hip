@@ -19,7 +19,8 @@ struct grpic_ctx {
   grpic_params prm;
   Grid g;
   int device;
-  double* tables;  // r[2], s[2], c[2], each of length n + 2 ng
+  bool f32;        // single-precision storage (GRPIC_FP32)
+  double* tables;  // r[2], s[2], c[2] (n + 2 ng each), then float r, sin, cos at nodes
   Tables tab;
   DiagAcc* acc;    // device accumulators for diagnostics
   double polar_k;  // 1 - cos(dth / 2)
@@ -73,10 +74,11 @@ grpic_status check_ctx(const grpic_ctx* c) {
   return GRPIC_OK;
 }
 
-grpic_status check_fields(const grpic_fields* F) {
+grpic_status check_fields(const grpic_ctx* c, const grpic_fields* F) {
   if (!F) return fail(GRPIC_EINVAL, "null field set");
   void* const* p = &F->D[0];
-  for (int k = 0; k < 33; ++k)
+  const int n = c->f32 ? 39 : 33;  // the compensation planes Dc, Bc in the FP32 form
+  for (int k = 0; k < n; ++k)
     if (!p[k]) return fail(GRPIC_EINVAL, "field plane %d is null", k);
   return GRPIC_OK;
 }
@@ -91,28 +93,44 @@ grpic_status check_particles(const grpic_particles* P) {
   return GRPIC_OK;
 }
 
-ParticleArrays arrays(const grpic_particles* P) {
-  ParticleArrays a;
+template <class T>
+ParticleArraysT<T> arrays(const grpic_particles* P) {
+  ParticleArraysT<T> a;
   a.i1 = P->i1;
   a.i2 = P->i2;
-  a.dx1 = (double*)P->dx1;
-  a.dx2 = (double*)P->dx2;
-  a.u1 = (double*)P->u1;
-  a.u2 = (double*)P->u2;
-  a.u3 = (double*)P->u3;
-  a.w = (double*)P->w;
-  a.phi = (double*)P->phi;
+  a.dx1 = (T*)P->dx1;
+  a.dx2 = (T*)P->dx2;
+  a.u1 = (T*)P->u1;
+  a.u2 = (T*)P->u2;
+  a.u3 = (T*)P->u3;
+  a.w = (T*)P->w;
+  a.phi = (T*)P->phi;
   a.i1p = P->i1p;
   a.i2p = P->i2p;
-  a.dx1p = (double*)P->dx1p;
-  a.dx2p = (double*)P->dx2p;
+  a.dx1p = (T*)P->dx1p;
+  a.dx2p = (T*)P->dx2p;
   a.tag = P->tag;
   a.n = P->n;
   return a;
 }
 
-Tri tri(void* const p[3]) { return Tri{{(double*)p[0], (double*)p[1], (double*)p[2]}}; }
-CTri ctri(void* const p[3]) { return CTri{{(const double*)p[0], (const double*)p[1], (const double*)p[2]}}; }
+template <class T>
+TriT<T> tri(void* const p[3]) {
+  return TriT<T>{{(T*)p[0], (T*)p[1], (T*)p[2]}};
+}
+template <class T>
+CTriT<T> ctri(void* const p[3]) {
+  return CTriT<T>{{(const T*)p[0], (const T*)p[1], (const T*)p[2]}};
+}
+// compensation planes of an evolved triple (single-precision form only)
+template <class T>
+TriT<T> comp(const grpic_ctx* c, void* const p[3]) {
+  return c->f32 ? tri<T>(p) : TriT<T>{{nullptr, nullptr, nullptr}};
+}
+template <class T>
+TriT<T> none() {
+  return TriT<T>{{nullptr, nullptr, nullptr}};
+}
 
 constexpr int kB = 256;
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
@@ -125,14 +143,257 @@ const int3 kStagD1 = {1, 0, 0}, kStagD2 = {0, 1, 0};  // x1 / x2 staggering of D
 const int3 kStagB1 = {0, 1, 1}, kStagB2 = {1, 0, 1};  // x1 / x2 staggering of B^i
 
 // boundaries of an updated triple: horizon layer + absorbing layer, then axis
-grpic_status field_bc(grpic_ctx* c, Tri X, CTri X0, bool is_B, hipStream_t s) {
+template <class T>
+grpic_status field_bc(grpic_ctx* c, TriT<T> X, TriT<T> L, CTriT<T> X0, bool is_B, hipStream_t s) {
   const Grid& g = c->g;
-  hipLaunchKernelGGL(bc_radial_kernel, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, X,
-                     X0, is_B ? kStagB1 : kStagD1);
+  hipLaunchKernelGGL(bc_radial_kernel<T>, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, X,
+                     L, X0, is_B ? kStagB1 : kStagD1);
   LAUNCH_CHECK("bc_radial");
-  hipLaunchKernelGGL(bc_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, X,
+  hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, X, L,
                      is_B ? kStagB2 : kStagD2, is_B ? 1 : 2);
   LAUNCH_CHECK("bc_axis");
+  return GRPIC_OK;
+}
+
+// ------------------------------------------------------------------ stages by storage type
+
+template <class T>
+grpic_status particles_init_impl(grpic_ctx* c, const grpic_particles* P, int64_t n_pairs, int32_t ppc,
+                                 double T_, int64_t n_geo, uint64_t seed, hipStream_t s) {
+  const Grid& g = c->g;
+  const ParticleArraysT<T> a = arrays<T>(P);
+  if (n_pairs > 0) {
+    hipLaunchKernelGGL(load_pairs_kernel<T>, dim3(blocks(n_pairs)), dim3(kB), 0, s, g, a, n_pairs, ppc, T_,
+                       seed);
+    LAUNCH_CHECK("load_pairs");
+  }
+  if (n_geo > 0) {
+    hipLaunchKernelGGL(load_geodesics_kernel<T>, dim3(blocks(n_geo)), dim3(kB), 0, s, g, a, 2 * n_pairs,
+                       n_geo, seed);
+    LAUNCH_CHECK("load_geodesics");
+  }
+  return GRPIC_OK;
+}
+
+template <class T>
+grpic_status wald_impl(grpic_ctx* c, const grpic_fields* F, double B0, hipStream_t s) {
+  const Grid& g = c->g;
+  void* const* pl = &F->D[0];
+  for (int k = 0; k < (c->f32 ? 39 : 33); ++k) {
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (T*)pl[k], 0.0);
+    LAUNCH_CHECK("fill");
+  }
+  hipLaunchKernelGGL(wald_kernel<T>, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, c->tab,
+                     tri<T>(F->D), tri<T>(F->B), B0);
+  LAUNCH_CHECK("wald");
+  hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g,
+                     tri<T>(F->D), none<T>(), kStagD2, 2);
+  LAUNCH_CHECK("bc_axis");
+  hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g,
+                     tri<T>(F->B), none<T>(), kStagB2, 1);
+  LAUNCH_CHECK("bc_axis");
+  void* const* dst[4] = {F->D0, F->B0, F->Dinit, F->Binit};
+  void* const* src[4] = {F->D, F->B, F->D, F->B};
+  for (int k = 0; k < 4; ++k) {
+    hipLaunchKernelGGL(copy_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri<T>(dst[k]),
+                       ctri<T>(src[k]));
+    LAUNCH_CHECK("copy");
+  }
+  return GRPIC_OK;
+}
+
+grpic_status push_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, hipStream_t s) {
+  const dim3 grid(blocks(P->n));
+  if (c->f32) {
+    GatherPlanesT<float> gp;
+    for (int k = 0; k < 3; ++k) {
+      gp.D[k] = (const float*)F->D[k];
+      gp.B[k] = (const float*)F->B0[k];
+    }
+    if (c->g.fast)
+      hipLaunchKernelGGL(push_kernel_f32<true>, grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<float>(P));
+    else
+      hipLaunchKernelGGL(push_kernel_f32<false>, grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<float>(P));
+  } else {
+    GatherPlanesT<double> gp;
+    for (int k = 0; k < 3; ++k) {
+      gp.D[k] = (const double*)F->D[k];
+      gp.B[k] = (const double*)F->B0[k];
+    }
+    if (c->g.fast)
+      hipLaunchKernelGGL(push_kernel<true>, grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<double>(P));
+    else
+      hipLaunchKernelGGL(push_kernel<false>, grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<double>(P));
+  }
+  LAUNCH_CHECK("push");
+  return GRPIC_OK;
+}
+
+grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, hipStream_t s) {
+  const dim3 grid((unsigned)((P->n + kDepBlock - 1) / kDepBlock));
+  if (c->f32) {
+    GatherPlanesT<float> gp;
+    for (int k = 0; k < 3; ++k) {
+      gp.D[k] = (const float*)F->D[k];
+      gp.B[k] = (const float*)F->B0[k];
+    }
+    CurrentPlanesT<float> cp{{(float*)F->J[0], (float*)F->J[1], (float*)F->J[2]}};
+    if (c->g.fast)
+      hipLaunchKernelGGL(push_deposit_kernel_f32<true>, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp,
+                         arrays<float>(P), cp);
+    else
+      hipLaunchKernelGGL(push_deposit_kernel_f32<false>, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp,
+                         arrays<float>(P), cp);
+  } else {
+    GatherPlanesT<double> gp;
+    for (int k = 0; k < 3; ++k) {
+      gp.D[k] = (const double*)F->D[k];
+      gp.B[k] = (const double*)F->B0[k];
+    }
+    CurrentPlanesT<double> cp{{(double*)F->J[0], (double*)F->J[1], (double*)F->J[2]}};
+    if (c->g.fast)
+      hipLaunchKernelGGL(push_deposit_kernel<true>, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp,
+                         arrays<double>(P), cp);
+    else
+      hipLaunchKernelGGL(push_deposit_kernel<false>, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp,
+                         arrays<double>(P), cp);
+  }
+  LAUNCH_CHECK("push_deposit");
+  return GRPIC_OK;
+}
+
+template <class T>
+grpic_status deposit_impl(grpic_ctx* c, const grpic_particles* P, const grpic_fields* F, hipStream_t s) {
+  CurrentPlanesT<T> cp{{(T*)F->J[0], (T*)F->J[1], (T*)F->J[2]}};
+  const dim3 grid((unsigned)((P->n + kDepBlock - 1) / kDepBlock));
+  if (c->g.fast)
+    hipLaunchKernelGGL((deposit_kernel<T, true>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp);
+  else
+    hipLaunchKernelGGL((deposit_kernel<T, false>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp);
+  LAUNCH_CHECK("deposit");
+  return GRPIC_OK;
+}
+
+template <class T>
+grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst, hipStream_t s) {
+  const Grid& g = c->g;
+  const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
+  const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
+  const ParticleArraysT<T> a = arrays<T>(src), b = arrays<T>(dst);
+  hipLaunchKernelGGL(sort_count_kernel<T>, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, c->sort_off);
+  LAUNCH_CHECK("sort_count");
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, c->sort_off, nkeys, c->sort_sums);
+  LAUNCH_CHECK("scan_blocks");
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, c->sort_sums, nb);
+  LAUNCH_CHECK("scan_sums");
+  hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, c->sort_off, nkeys, c->sort_sums);
+  LAUNCH_CHECK("scan_add");
+  hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, c->sort_off + (nkeys - 1), c->sort_live);
+  LAUNCH_CHECK("copy_int");
+  hipLaunchKernelGGL(sort_scatter_kernel<T>, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, b, c->sort_off);
+  LAUNCH_CHECK("sort_scatter");
+  return GRPIC_OK;
+}
+
+template <class T>
+grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t stage, hipStream_t s) {
+  grpic_status st;
+  const Grid& g = c->g;
+  const dim3 gaux = grid2(g.n_r + 2, g.n_th + 1);   // i in [-1, n_r], j in [0, n_th]
+  const dim3 gupd = grid2(g.n_r + 1, g.n_th + 1);   // i in [0, n_r],  j in [0, n_th]
+  const dim3 gpl(blocks(g.plane));
+  if (stage == GRPIC_FIELDS_PRE_PUSH) {
+    hipLaunchKernelGGL(average_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->B0), ctri<T>(F->B));
+    LAUNCH_CHECK("average");
+    hipLaunchKernelGGL(average_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->D0), ctri<T>(F->D));
+    LAUNCH_CHECK("average");
+    hipLaunchKernelGGL(aux_e_kernel<T>, gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B), ctri<T>(F->D0),
+                       tri<T>(F->E));
+    LAUNCH_CHECK("aux_e");
+    hipLaunchKernelGGL(faraday_kernel<T>, gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->B0), none<T>(),
+                       ctri<T>(F->E));
+    LAUNCH_CHECK("faraday");
+    return field_bc<T>(c, tri<T>(F->B0), none<T>(), ctri<T>(F->Binit), true, s);
+  }
+  // current filter (n_f passes) on the freshly deposited J^{n+1/2}
+  for (int pass = 0; pass < g.n_filter; ++pass) {
+    hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g,
+                       tri<T>(F->J), none<T>(), kStagD2, -1);
+    LAUNCH_CHECK("bc_axis");
+    hipLaunchKernelGGL(copy_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->T), ctri<T>(F->J));
+    LAUNCH_CHECK("copy");
+    hipLaunchKernelGGL(filter_kernel<T>, grid2(g.n_r + 2 * g.ng - 2, g.n_th + 1), kBlock2, 0, s, g,
+                       tri<T>(F->J), ctri<T>(F->T), kStagD2, 3);
+    LAUNCH_CHECK("filter");
+  }
+  hipLaunchKernelGGL(aux_e_kernel<T>, gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B0), ctri<T>(F->D),
+                     tri<T>(F->E));
+  LAUNCH_CHECK("aux_e");
+  hipLaunchKernelGGL(aux_h_kernel<T>, gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B0), ctri<T>(F->D),
+                     tri<T>(F->H));
+  LAUNCH_CHECK("aux_h");
+  hipLaunchKernelGGL(copy_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->B0), ctri<T>(F->B));
+  LAUNCH_CHECK("copy");
+  hipLaunchKernelGGL(faraday_kernel<T>, gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->B), comp<T>(c, F->Bc),
+                     ctri<T>(F->E));
+  LAUNCH_CHECK("faraday");
+  if ((st = field_bc<T>(c, tri<T>(F->B), comp<T>(c, F->Bc), ctri<T>(F->Binit), true, s))) return st;
+  hipLaunchKernelGGL(ampere_kernel<T>, gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->D0), none<T>(),
+                     ctri<T>(F->H), ctri<T>(F->J0), ctri<T>(F->J), 0.5, 0.5, c->polar_k);
+  LAUNCH_CHECK("ampere");
+  if ((st = field_bc<T>(c, tri<T>(F->D0), none<T>(), ctri<T>(F->Dinit), false, s))) return st;
+  hipLaunchKernelGGL(aux_h_kernel<T>, gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B), ctri<T>(F->D0),
+                     tri<T>(F->H));
+  LAUNCH_CHECK("aux_h");
+  hipLaunchKernelGGL(copy_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->D0), ctri<T>(F->D));
+  LAUNCH_CHECK("copy");
+  hipLaunchKernelGGL(ampere_kernel<T>, gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->D), comp<T>(c, F->Dc),
+                     ctri<T>(F->H), ctri<T>(F->J), ctri<T>(F->J), 1.0, 0.0, c->polar_k);
+  LAUNCH_CHECK("ampere");
+  if ((st = field_bc<T>(c, tri<T>(F->D), comp<T>(c, F->Dc), ctri<T>(F->Dinit), false, s))) return st;
+  hipLaunchKernelGGL(rotate_currents_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->J0), tri<T>(F->J));
+  LAUNCH_CHECK("rotate_currents");
+  return GRPIC_OK;
+}
+
+template <class T>
+grpic_status diagnostics_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, double B0,
+                              void* E_out, void* L_out, void* gauss_res, hipStream_t s) {
+  const Grid& g = c->g;
+  if (P->n > 0) {
+    hipLaunchKernelGGL(diag_particles_kernel<T>, dim3(blocks(P->n)), dim3(kDiagBlock), 0, s, g, arrays<T>(P),
+                       B0, (T*)E_out, (T*)L_out, c->acc);
+    LAUNCH_CHECK("diag_particles");
+  }
+  // Gauss residual: charge into T[0], filtered like the currents (T[1] scratch)
+  T* Q = (T*)F->T[0];
+  T* tmp = (T*)F->T[1];
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, Q, 0.0);
+  LAUNCH_CHECK("fill");
+  if (P->n > 0) {
+    hipLaunchKernelGGL(charge_kernel<T>, dim3(blocks(P->n)), dim3(kB), 0, s, g, arrays<T>(P), Q);
+    LAUNCH_CHECK("charge");
+  }
+  for (int pass = 0; pass < g.n_filter; ++pass) {
+    hipLaunchKernelGGL(scalar_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, Q);
+    LAUNCH_CHECK("scalar_axis");
+    HIP_TRY(hipMemcpyAsync(tmp, Q, g.plane * sizeof(T), hipMemcpyDeviceToDevice, s));
+    TriT<T> X{{Q, nullptr, nullptr}};
+    CTriT<T> Sv{{tmp, nullptr, nullptr}};
+    hipLaunchKernelGGL(filter_kernel<T>, grid2(g.n_r + 2 * g.ng - 2, g.n_th + 1), kBlock2, 0, s, g, X, Sv,
+                       int3{0, 0, 0}, 1);
+    LAUNCH_CHECK("filter");
+  }
+  if (gauss_res) {
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (T*)gauss_res, 0.0);
+    LAUNCH_CHECK("fill");
+  }
+  const int ni = g.n_r - g.n_absorb - (g.n_filter + 2), nj = g.n_th - 1;
+  if (ni > 0 && nj > 0) {
+    hipLaunchKernelGGL(gauss_kernel<T>, grid2(ni, nj), kBlock2, 0, s, g, c->tab, (const T*)F->D[0],
+                       (const T*)F->D[1], (const T*)Q, (T*)gauss_res, c->acc);
+    LAUNCH_CHECK("gauss");
+  }
   return GRPIC_OK;
 }
 
@@ -145,8 +406,8 @@ const char* grpic_last_error(void) { return g_err.c_str(); }
 grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   if (!p || !out) return fail(GRPIC_EINVAL, "null argument");
   *out = nullptr;
-  if (p->precision != GRPIC_FP64)
-    return fail(GRPIC_EINVAL, "precision %d is not available in this library", p->precision);
+  if (p->precision != GRPIC_FP64 && p->precision != GRPIC_FP32)
+    return fail(GRPIC_EINVAL, "unknown precision %d", p->precision);
   if (p->n_r < 8 || p->n_th < 8) return fail(GRPIC_EINVAL, "grid %d x %d too small", p->n_r, p->n_th);
   if (p->n_ghost != 2) return fail(GRPIC_EINVAL, "n_ghost must be 2 (got %d)", p->n_ghost);
   if (p->n_iter < 1) return fail(GRPIC_EINVAL, "n_iter must be >= 1");
@@ -165,6 +426,7 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
 
   grpic_ctx* c = new grpic_ctx();
   c->prm = *p;
+  c->f32 = p->precision == GRPIC_FP32;
   Grid& g = c->g;
   g.a = p->a;
   g.M = p->M;
@@ -210,11 +472,21 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   // the push evaluates exp and sincos of in-cell offsets (at most 1.5 cells)
   // by short series that are exact to rounding for arguments up to 0.11
   g.fast = 1.5 * std::fmax(g.dxi, g.dth) <= 0.11 ? 1 : 0;
+  // single-precision push: cells whose inner edge lies below r = 3 M keep the
+  // metric and its derivatives in FP64 (the horizon region, where lapse and
+  // shift vary fastest)
+  g.i_fp64 = 0;
+  if (g.M > 0.0) {
+    const double x = std::ceil((std::log(3.0 * g.M) - g.xi_min) / g.dxi);
+    g.i_fp64 = (int)std::fmin(std::fmax(x, 0.0), (double)p->n_r);
+  }
 
   hipError_t e = hipGetDevice(&c->device);
   const int nr = p->n_r + 2 * p->n_ghost, nt = p->n_th + 2 * p->n_ghost;
   const size_t nt_all = 2 * (size_t)nr + 4 * (size_t)nt;
-  if (e == hipSuccess) e = hipMalloc(&c->tables, nt_all * sizeof(double));
+  const size_t nf_all = (size_t)nr + 2 * (size_t)nt;  // float r, sin, cos at integer nodes
+  const size_t bytes = nt_all * sizeof(double) + nf_all * sizeof(float);
+  if (e == hipSuccess) e = hipMalloc(&c->tables, bytes);
   if (e != hipSuccess) {
     delete c;
     return fail(GRPIC_ENOMEM, "table allocation: %s", hipGetErrorString(e));
@@ -238,7 +510,7 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     c->sort_sums = c->sort_off + nkeys;
     c->sort_live = c->sort_sums + nb;
   }
-  double* h = new double[nt_all];
+  double* h = new double[(bytes + sizeof(double) - 1) / sizeof(double)];
   double* pr0 = h;
   double* pr1 = h + nr;
   double* ps0 = h + 2 * nr;
@@ -256,7 +528,13 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     ps1[j] = std::sin(t1);
     pc1[j] = std::cos(t1);
   }
-  e = hipMemcpy(c->tables, h, nt_all * sizeof(double), hipMemcpyHostToDevice);
+  float* hf = reinterpret_cast<float*>(h + nt_all);
+  for (int i = 0; i < nr; ++i) hf[i] = (float)pr0[i];
+  for (int j = 0; j < nt; ++j) {
+    hf[nr + j] = (float)ps0[j];
+    hf[nr + nt + j] = (float)pc0[j];
+  }
+  e = hipMemcpy(c->tables, h, bytes, hipMemcpyHostToDevice);
   delete[] h;
   if (e != hipSuccess) {
     (void)hipFree(c->tables);
@@ -271,6 +549,10 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   c->tab.s[1] = c->tab.s[0] + nt;
   c->tab.c[0] = c->tab.s[1] + nt;
   c->tab.c[1] = c->tab.c[0] + nt;
+  const float* tf = reinterpret_cast<const float*>(c->tables + nt_all);
+  c->tab.rf = tf;
+  c->tab.sf = tf + nr;
+  c->tab.cf = tf + nr + nt;
   *out = c;
   return GRPIC_OK;
 }
@@ -305,78 +587,36 @@ grpic_status grpic_particles_init(grpic_ctx* c, const grpic_particles* P, int64_
   if (2 * n_pairs + n_geo > 0xFFFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^32 particles");
   if (n_geo > 0 && !(std::log(6.0) > g.xi_min && std::log(15.0) < g.xi_min + g.n_r * g.dxi && g.M > 0.0))
     return fail(GRPIC_EINVAL, "test geodesics need r in [6, 15] inside the grid and M > 0");
-  ParticleArrays a = arrays(P);
-  if (n_pairs > 0) {
-    hipLaunchKernelGGL(load_pairs_kernel, dim3(blocks(n_pairs)), dim3(kB), 0, S(stream), g, a, n_pairs,
-                       ppc, T, seed);
-    LAUNCH_CHECK("load_pairs");
-  }
-  if (n_geo > 0) {
-    hipLaunchKernelGGL(load_geodesics_kernel, dim3(blocks(n_geo)), dim3(kB), 0, S(stream), g, a,
-                       2 * n_pairs, n_geo, seed);
-    LAUNCH_CHECK("load_geodesics");
-  }
-  return GRPIC_OK;
+  return c->f32 ? particles_init_impl<float>(c, P, n_pairs, ppc, T, n_geo, seed, S(stream))
+                : particles_init_impl<double>(c, P, n_pairs, ppc, T, n_geo, seed, S(stream));
 }
 
 grpic_status grpic_fields_init_wald(grpic_ctx* c, const grpic_fields* F, double B0, void* stream) {
   grpic_status st;
-  if ((st = check_ctx(c)) || (st = check_fields(F))) return st;
-  const Grid& g = c->g;
-  hipStream_t s = S(stream);
-  void* const* pl = &F->D[0];
-  for (int k = 0; k < 33; ++k) {
-    hipLaunchKernelGGL(fill_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (double*)pl[k], 0.0);
-    LAUNCH_CHECK("fill");
-  }
-  hipLaunchKernelGGL(wald_kernel, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, c->tab,
-                     tri(F->D), tri(F->B), B0);
-  LAUNCH_CHECK("wald");
-  hipLaunchKernelGGL(bc_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, tri(F->D),
-                     kStagD2, 2);
-  LAUNCH_CHECK("bc_axis");
-  hipLaunchKernelGGL(bc_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, tri(F->B),
-                     kStagB2, 1);
-  LAUNCH_CHECK("bc_axis");
-  void* const* dst[4] = {F->D0, F->B0, F->Dinit, F->Binit};
-  void* const* src[4] = {F->D, F->B, F->D, F->B};
-  for (int k = 0; k < 4; ++k) {
-    hipLaunchKernelGGL(copy_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(dst[k]),
-                       ctri(src[k]));
-    LAUNCH_CHECK("copy");
-  }
-  return GRPIC_OK;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F))) return st;
+  return c->f32 ? wald_impl<float>(c, F, B0, S(stream)) : wald_impl<double>(c, F, B0, S(stream));
 }
 
 grpic_status grpic_push(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, void* stream) {
   grpic_status st;
-  if ((st = check_ctx(c)) || (st = check_fields(F)) || (st = check_particles(P))) return st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
   if (P->n == 0) return GRPIC_OK;
-  GatherPlanes gp;
-  for (int k = 0; k < 3; ++k) {
-    gp.D[k] = (const double*)F->D[k];
-    gp.B[k] = (const double*)F->B0[k];
-  }
-  if (c->g.fast)
-    hipLaunchKernelGGL(push_kernel<true>, dim3(blocks(P->n)), dim3(kB), 0, S(stream), c->g, c->tab, gp, arrays(P));
-  else
-    hipLaunchKernelGGL(push_kernel<false>, dim3(blocks(P->n)), dim3(kB), 0, S(stream), c->g, c->tab, gp, arrays(P));
-  LAUNCH_CHECK("push");
-  return GRPIC_OK;
+  return push_impl(c, F, P, S(stream));
 }
 
 grpic_status grpic_deposit(grpic_ctx* c, const grpic_particles* P, const grpic_fields* F, void* stream) {
   grpic_status st;
-  if ((st = check_ctx(c)) || (st = check_fields(F)) || (st = check_particles(P))) return st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
   if (P->n == 0) return GRPIC_OK;
-  CurrentPlanes cp{{(double*)F->J[0], (double*)F->J[1], (double*)F->J[2]}};
-  const dim3 grid((unsigned)((P->n + kDepBlock - 1) / kDepBlock));
-  if (c->g.fast)
-    hipLaunchKernelGGL(deposit_kernel<true>, grid, dim3(kDepBlock), 0, S(stream), c->g, c->tab, arrays(P), cp);
-  else
-    hipLaunchKernelGGL(deposit_kernel<false>, grid, dim3(kDepBlock), 0, S(stream), c->g, c->tab, arrays(P), cp);
-  LAUNCH_CHECK("deposit");
-  return GRPIC_OK;
+  return c->f32 ? deposit_impl<float>(c, P, F, S(stream)) : deposit_impl<double>(c, P, F, S(stream));
+}
+
+grpic_status grpic_push_deposit(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P,
+                                void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
+  if (P->n == 0) return GRPIC_OK;
+  return push_deposit_impl(c, F, P, S(stream));
 }
 
 grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst,
@@ -391,23 +631,10 @@ grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_pa
   const Grid& g = c->g;
   hipStream_t s = S(stream);
   const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
-  const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(fill_int_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, nkeys, c->sort_off, 0);
   LAUNCH_CHECK("fill_int");
   if (src->n > 0) {
-    ParticleArrays a = arrays(src), b = arrays(dst);
-    hipLaunchKernelGGL(sort_count_kernel, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, c->sort_off);
-    LAUNCH_CHECK("sort_count");
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, c->sort_off, nkeys, c->sort_sums);
-    LAUNCH_CHECK("scan_blocks");
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, c->sort_sums, nb);
-    LAUNCH_CHECK("scan_sums");
-    hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, c->sort_off, nkeys, c->sort_sums);
-    LAUNCH_CHECK("scan_add");
-    hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, c->sort_off + (nkeys - 1), c->sort_live);
-    LAUNCH_CHECK("copy_int");
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, b, c->sort_off);
-    LAUNCH_CHECK("sort_scatter");
+    if ((st = c->f32 ? sort_impl<float>(c, src, dst, s) : sort_impl<double>(c, src, dst, s))) return st;
   } else {
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, (int64_t)1, c->sort_live, 0);
     LAUNCH_CHECK("fill_int");
@@ -423,104 +650,23 @@ grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_pa
 
 grpic_status grpic_field_advance(grpic_ctx* c, const grpic_fields* F, int32_t stage, void* stream) {
   grpic_status st;
-  if ((st = check_ctx(c)) || (st = check_fields(F))) return st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F))) return st;
   if (stage != GRPIC_FIELDS_PRE_PUSH && stage != GRPIC_FIELDS_POST_DEPOSIT)
     return fail(GRPIC_EINVAL, "unknown field stage %d", stage);
-  const Grid& g = c->g;
-  hipStream_t s = S(stream);
-  const dim3 gaux = grid2(g.n_r + 2, g.n_th + 1);   // i in [-1, n_r], j in [0, n_th]
-  const dim3 gupd = grid2(g.n_r + 1, g.n_th + 1);   // i in [0, n_r],  j in [0, n_th]
-  if (stage == GRPIC_FIELDS_PRE_PUSH) {
-    hipLaunchKernelGGL(average_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->B0), ctri(F->B));
-    LAUNCH_CHECK("average");
-    hipLaunchKernelGGL(average_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->D0), ctri(F->D));
-    LAUNCH_CHECK("average");
-    hipLaunchKernelGGL(aux_e_kernel, gaux, kBlock2, 0, s, g, c->tab, ctri(F->B), ctri(F->D0), tri(F->E));
-    LAUNCH_CHECK("aux_e");
-    hipLaunchKernelGGL(faraday_kernel, gupd, kBlock2, 0, s, g, c->tab, tri(F->B0), ctri(F->E));
-    LAUNCH_CHECK("faraday");
-    return field_bc(c, tri(F->B0), ctri(F->Binit), true, s);
-  }
-  // current filter (n_f passes) on the freshly deposited J^{n+1/2}
-  for (int pass = 0; pass < g.n_filter; ++pass) {
-    hipLaunchKernelGGL(bc_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, tri(F->J),
-                       kStagD2, -1);
-    LAUNCH_CHECK("bc_axis");
-    hipLaunchKernelGGL(copy_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->T), ctri(F->J));
-    LAUNCH_CHECK("copy");
-    hipLaunchKernelGGL(filter_kernel, grid2(g.n_r + 2 * g.ng - 2, g.n_th + 1), kBlock2, 0, s, g,
-                       tri(F->J), ctri(F->T), kStagD2, 3);
-    LAUNCH_CHECK("filter");
-  }
-  hipLaunchKernelGGL(aux_e_kernel, gaux, kBlock2, 0, s, g, c->tab, ctri(F->B0), ctri(F->D), tri(F->E));
-  LAUNCH_CHECK("aux_e");
-  hipLaunchKernelGGL(aux_h_kernel, gaux, kBlock2, 0, s, g, c->tab, ctri(F->B0), ctri(F->D), tri(F->H));
-  LAUNCH_CHECK("aux_h");
-  hipLaunchKernelGGL(copy_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->B0), ctri(F->B));
-  LAUNCH_CHECK("copy");
-  hipLaunchKernelGGL(faraday_kernel, gupd, kBlock2, 0, s, g, c->tab, tri(F->B), ctri(F->E));
-  LAUNCH_CHECK("faraday");
-  if ((st = field_bc(c, tri(F->B), ctri(F->Binit), true, s))) return st;
-  hipLaunchKernelGGL(ampere_kernel, gupd, kBlock2, 0, s, g, c->tab, tri(F->D0), ctri(F->H), ctri(F->J0),
-                     ctri(F->J), 0.5, 0.5, c->polar_k);
-  LAUNCH_CHECK("ampere");
-  if ((st = field_bc(c, tri(F->D0), ctri(F->Dinit), false, s))) return st;
-  hipLaunchKernelGGL(aux_h_kernel, gaux, kBlock2, 0, s, g, c->tab, ctri(F->B), ctri(F->D0), tri(F->H));
-  LAUNCH_CHECK("aux_h");
-  hipLaunchKernelGGL(copy_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->D0), ctri(F->D));
-  LAUNCH_CHECK("copy");
-  hipLaunchKernelGGL(ampere_kernel, gupd, kBlock2, 0, s, g, c->tab, tri(F->D), ctri(F->H), ctri(F->J),
-                     ctri(F->J), 1.0, 0.0, c->polar_k);
-  LAUNCH_CHECK("ampere");
-  if ((st = field_bc(c, tri(F->D), ctri(F->Dinit), false, s))) return st;
-  hipLaunchKernelGGL(rotate_currents_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri(F->J0),
-                     tri(F->J));
-  LAUNCH_CHECK("rotate_currents");
-  return GRPIC_OK;
+  return c->f32 ? field_advance_impl<float>(c, F, stage, S(stream))
+                : field_advance_impl<double>(c, F, stage, S(stream));
 }
 
 grpic_status grpic_diagnostics(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, double B0,
                                grpic_diag* out, void* E_out, void* L_out, void* gauss_res, void* stream) {
   grpic_status st;
-  if ((st = check_ctx(c)) || (st = check_fields(F)) || (st = check_particles(P))) return st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
   if (!out) return fail(GRPIC_EINVAL, "null output");
-  const Grid& g = c->g;
   hipStream_t s = S(stream);
   HIP_TRY(hipMemsetAsync(c->acc, 0, sizeof(DiagAcc), s));
-  if (P->n > 0) {
-    hipLaunchKernelGGL(diag_particles_kernel, dim3(blocks(P->n)), dim3(kDiagBlock), 0, s, g, arrays(P), B0,
-                       (double*)E_out, (double*)L_out, c->acc);
-    LAUNCH_CHECK("diag_particles");
-  }
-  // Gauss residual: charge into T[0], filtered like the currents (T[1] scratch)
-  double* Q = (double*)F->T[0];
-  double* tmp = (double*)F->T[1];
-  hipLaunchKernelGGL(fill_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, Q, 0.0);
-  LAUNCH_CHECK("fill");
-  if (P->n > 0) {
-    hipLaunchKernelGGL(charge_kernel, dim3(blocks(P->n)), dim3(kB), 0, s, g, arrays(P), Q);
-    LAUNCH_CHECK("charge");
-  }
-  for (int pass = 0; pass < g.n_filter; ++pass) {
-    hipLaunchKernelGGL(scalar_axis_kernel, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, Q);
-    LAUNCH_CHECK("scalar_axis");
-    HIP_TRY(hipMemcpyAsync(tmp, Q, g.plane * sizeof(double), hipMemcpyDeviceToDevice, s));
-    Tri X{{Q, nullptr, nullptr}};
-    CTri Sv{{tmp, nullptr, nullptr}};
-    hipLaunchKernelGGL(filter_kernel, grid2(g.n_r + 2 * g.ng - 2, g.n_th + 1), kBlock2, 0, s, g, X, Sv,
-                       int3{0, 0, 0}, 1);
-    LAUNCH_CHECK("filter");
-  }
-  if (gauss_res) {
-    hipLaunchKernelGGL(fill_kernel, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (double*)gauss_res, 0.0);
-    LAUNCH_CHECK("fill");
-  }
-  const int ni = g.n_r - g.n_absorb - (g.n_filter + 2), nj = g.n_th - 1;
-  if (ni > 0 && nj > 0) {
-    hipLaunchKernelGGL(gauss_kernel, grid2(ni, nj), kBlock2, 0, s, g, c->tab, (const double*)F->D[0],
-                       (const double*)F->D[1], (const double*)Q, (double*)gauss_res, c->acc);
-    LAUNCH_CHECK("gauss");
-  }
+  if ((st = c->f32 ? diagnostics_impl<float>(c, F, P, B0, E_out, L_out, gauss_res, s)
+                   : diagnostics_impl<double>(c, F, P, B0, E_out, L_out, gauss_res, s)))
+    return st;
   DiagAcc h;
   HIP_TRY(hipMemcpyAsync(&h, c->acc, sizeof(DiagAcc), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -93,7 +93,8 @@ __device__ inline void hat_to_cov(const Tetrad& e, const double uh[3], double& u
   u3 = e.s33 * uh[2];
 }
 
-__device__ inline void store_particle(ParticleArrays& P, int64_t q, int i1, int i2, double dx1,
+template <class T>
+__device__ inline void store_particle(ParticleArraysT<T>& P, int64_t q, int i1, int i2, double dx1,
                                       double dx2, double u1, double u2, double u3, uint8_t tag) {
   P.i1[q] = i1;
   P.i2[q] = i2;
@@ -112,7 +113,8 @@ __device__ inline void store_particle(ParticleArrays& P, int64_t q, int i1, int 
 }
 
 // One thread per pair k: slots 2k (e+) and 2k+1 (e-) at one position.
-__global__ void load_pairs_kernel(Grid g, ParticleArrays P, int64_t n_pairs, int ppc, double T,
+template <class T>
+__global__ void load_pairs_kernel(Grid g, ParticleArraysT<T> P, int64_t n_pairs, int ppc, double temp,
                                   uint64_t seed) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_pairs) return;
@@ -127,7 +129,7 @@ __global__ void load_pairs_kernel(Grid g, ParticleArrays P, int64_t n_pairs, int
   for (int s = 0; s < 2; ++s) {
     const int64_t q = 2 * k + s;
     double uh[3], u1, u2, u3;
-    maxwell_juttner(seed, (uint32_t)q, T, uh);
+    maxwell_juttner(seed, (uint32_t)q, temp, uh);
     hat_to_cov(e, uh, u1, u2, u3);
     store_particle(P, q, i1, i2, dx1, dx2, u1, u2, u3, (uint8_t)(s == 0 ? 1 : 2));
   }
@@ -136,7 +138,8 @@ __global__ void load_pairs_kernel(Grid g, ParticleArrays P, int64_t n_pairs, int
 // Neutral bound test particles (tag 3): r in U[6, 15], theta in U[pi/3, 2pi/3],
 // tetrad velocity (0.05 U[-1,1], 0.05 U[-1,1], (0.9 + 0.2 U) sqrt(M/(r - 3M))),
 // redrawn until E = alpha gamma - beta^1 u_1 < 1.
-__global__ void load_geodesics_kernel(Grid g, ParticleArrays P, int64_t first, int64_t n_geo,
+template <class T>
+__global__ void load_geodesics_kernel(Grid g, ParticleArraysT<T> P, int64_t first, int64_t n_geo,
                                       uint64_t seed) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_geo) return;
@@ -259,7 +262,8 @@ __device__ inline double wald_B(const Grid& g, double x1, double x2, double B0, 
 // Whole planes incl. ghosts: D pointwise, B by the discrete Stokes curl of
 // A_3 (nodes) and A_1 (r-edges); the last row/column (no neighbour) takes the
 // analytic B.
-__global__ void wald_kernel(Grid g, Tables t, Tri D, Tri B, double B0) {
+template <class T>
+__global__ void wald_kernel(Grid g, Tables t, TriT<T> D, TriT<T> B, double B0) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
   const int i = blockIdx.y * blockDim.y + threadIdx.y - g.ng;
   if (j >= g.n_th + g.ng || i >= g.n_r + g.ng) return;

@@ -1,8 +1,12 @@
-// particles.hpp -- push and deposit kernels (FP64 form).
+// particles.hpp -- push and deposit kernels, FP64 form and single-precision form.
 //
 // One particle per lane; structure-of-arrays loads and stores are contiguous
 // across a wavefront.  The push follows Sec. 3.1 steps 1-11 of the paper; the
-// deposit Sec. 3.2.
+// deposit Sec. 3.2.  The single-precision form stores cell indices as int32
+// and offsets, momenta, fields and currents as float, evaluates the metric in
+// float from offsets relative to the particle's cell (angles from the nearer
+// axis), and takes the metric and its derivatives at x^n in FP64 inside the
+// horizon region (cells i1 < i_fp64).
 #pragma once
 
 #include <climits>
@@ -18,38 +22,43 @@ constexpr uint8_t kSpecies = 0x03;
 __host__ __device__ inline bool is_live(uint8_t t) { return t != 0 && !(t & kInvalid); }
 
 // a position inside the grid (what the push may start from)
-__device__ inline bool in_grid(const Grid& g, int i1, double dx1, int i2, double dx2) {
-  return i1 >= 0 && i1 < g.n_r && i2 >= 0 && i2 < g.n_th && dx1 >= 0.0 && dx1 <= 1.0 &&
-         dx2 >= 0.0 && dx2 <= 1.0;
+template <class T>
+__device__ inline bool in_grid(const Grid& g, int i1, T dx1, int i2, T dx2) {
+  return i1 >= 0 && i1 < g.n_r && i2 >= 0 && i2 < g.n_th && dx1 >= (T)0 && dx1 <= (T)1 &&
+         dx2 >= (T)0 && dx2 <= (T)1;
 }
 
 // a position the deposit may write around: one cell beyond the radial edges
-__device__ inline bool in_deposit_range(const Grid& g, int i1, double dx1, int i2, double dx2) {
-  return i1 >= -1 && i1 <= g.n_r && i2 >= 0 && i2 < g.n_th && dx1 >= 0.0 && dx1 <= 1.0 &&
-         dx2 >= 0.0 && dx2 <= 1.0;
+template <class T>
+__device__ inline bool in_deposit_range(const Grid& g, int i1, T dx1, int i2, T dx2) {
+  return i1 >= -1 && i1 <= g.n_r && i2 >= 0 && i2 < g.n_th && dx1 >= (T)0 && dx1 <= (T)1 &&
+         dx2 >= (T)0 && dx2 <= (T)1;
 }
 
-struct ParticleArrays {
+template <class T>
+struct ParticleArraysT {
   int32_t* __restrict__ i1;
   int32_t* __restrict__ i2;
-  double* __restrict__ dx1;
-  double* __restrict__ dx2;
-  double* __restrict__ u1;
-  double* __restrict__ u2;
-  double* __restrict__ u3;
-  double* __restrict__ w;
-  double* __restrict__ phi;
+  T* __restrict__ dx1;
+  T* __restrict__ dx2;
+  T* __restrict__ u1;
+  T* __restrict__ u2;
+  T* __restrict__ u3;
+  T* __restrict__ w;
+  T* __restrict__ phi;
   int32_t* __restrict__ i1p;
   int32_t* __restrict__ i2p;
-  double* __restrict__ dx1p;
-  double* __restrict__ dx2p;
+  T* __restrict__ dx1p;
+  T* __restrict__ dx2p;
   uint8_t* __restrict__ tag;
   int64_t n;
 };
+using ParticleArrays = ParticleArraysT<double>;
 
-struct GatherPlanes {
-  const double* __restrict__ D[3];
-  const double* __restrict__ B[3];
+template <class T>
+struct GatherPlanesT {
+  const T* __restrict__ D[3];
+  const T* __restrict__ B[3];
 };
 
 __device__ inline double species_sign(uint8_t t) {
@@ -59,50 +68,52 @@ __device__ inline double species_sign(uint8_t t) {
 
 // First-order interpolation in code coordinates of a plane staggered by half a
 // cell in x1 (H1) and/or x2 (H2).
-template <int H1, int H2>
-__device__ inline double interp(const Grid& g, const double* __restrict__ F, int i1, double dx1,
-                                int i2, double dx2) {
+template <int H1, int H2, class T>
+__device__ inline T interp(const Grid& g, const T* __restrict__ F, int i1, T dx1, int i2, T dx2) {
   int k1 = i1, k2 = i2;
-  double w1 = dx1, w2 = dx2;
+  T w1 = dx1, w2 = dx2;
+  const T half = (T)0.5;
   if (H1) {
-    const bool up = dx1 >= 0.5;
+    const bool up = dx1 >= half;
     k1 = up ? i1 : i1 - 1;
-    w1 = up ? dx1 - 0.5 : dx1 + 0.5;
+    w1 = up ? dx1 - half : dx1 + half;
   }
   if (H2) {
-    const bool up = dx2 >= 0.5;
+    const bool up = dx2 >= half;
     k2 = up ? i2 : i2 - 1;
-    w2 = up ? dx2 - 0.5 : dx2 + 0.5;
+    w2 = up ? dx2 - half : dx2 + half;
   }
-  const double* p = F + ix(g, k1, k2);
-  const double f00 = p[0], f01 = p[1], f10 = p[g.ld], f11 = p[g.ld + 1];
-  const double a0 = f00 + w2 * (f01 - f00);
-  const double a1 = f10 + w2 * (f11 - f10);
+  const T* p = F + ix(g, k1, k2);
+  const T f00 = p[0], f01 = p[1], f10 = p[g.ld], f11 = p[g.ld + 1];
+  const T a0 = f00 + w2 * (f01 - f00);
+  const T a1 = f10 + w2 * (f11 - f10);
   return a0 + w1 * (a1 - a0);
 }
 
 // Relativistic Boris rotation for duration tau in an orthonormal frame.
-__device__ inline void boris(double& ux, double& uy, double& uz, const double E[3],
-                             const double B[3], double k /* = qm tau / 2 */) {
-  const double mx = ux + k * E[0], my = uy + k * E[1], mz = uz + k * E[2];
-  const double ig = k / sqrt(1.0 + mx * mx + my * my + mz * mz);
-  const double tx = B[0] * ig, ty = B[1] * ig, tz = B[2] * ig;
-  const double f = 2.0 / (1.0 + tx * tx + ty * ty + tz * tz);
-  const double sx = f * tx, sy = f * ty, sz = f * tz;
-  const double px = mx + (my * tz - mz * ty);
-  const double py = my + (mz * tx - mx * tz);
-  const double pz = mz + (mx * ty - my * tx);
+template <class R>
+__device__ inline void boris(R& ux, R& uy, R& uz, const R E[3], const R B[3],
+                             R k /* = qm tau / 2 */) {
+  const R mx = ux + k * E[0], my = uy + k * E[1], mz = uz + k * E[2];
+  const R ig = k / sqrt((R)1 + mx * mx + my * my + mz * mz);
+  const R tx = B[0] * ig, ty = B[1] * ig, tz = B[2] * ig;
+  const R f = (R)2 / ((R)1 + tx * tx + ty * ty + tz * tz);
+  const R sx = f * tx, sy = f * ty, sz = f * tz;
+  const R px = mx + (my * tz - mz * ty);
+  const R py = my + (mz * tx - mx * tz);
+  const R pz = mz + (mx * ty - my * tx);
   ux = mx + (py * sz - pz * sy) + k * E[0];
   uy = my + (pz * sx - px * sz) + k * E[1];
   uz = mz + (px * sy - py * sx) + k * E[2];
 }
 
 // EM half step: covariant -> tetrad (App. A), Boris, tetrad -> covariant.
-__device__ inline void em_half(const Frame& f, const double E[3], const double B[3], double k,
-                               double& u1, double& u2, double& u3) {
-  double x = f.s11 * (u1 - f.k13 * u3);
-  double y = u2 / f.s22;
-  double z = u3 / f.s33;
+template <class R>
+__device__ inline void em_half(const FrameT<R>& f, const R E[3], const R B[3], R k, R& u1, R& u2,
+                               R& u3) {
+  R x = f.s11 * (u1 - f.k13 * u3);
+  R y = u2 / f.s22;
+  R z = u3 / f.s33;
   boris(x, y, z, E, B, k);
   u1 = x / f.s11 + f.k13 * f.s33 * z;
   u2 = f.s22 * y;
@@ -111,30 +122,33 @@ __device__ inline void em_half(const Frame& f, const double E[3], const double B
 
 // Implicit-midpoint geodesic momentum update at fixed x^n (eq.
 // discretized-geodesic-u); u_3 is untouched.
-__device__ inline void geodesic_u(const Grid& g, const Frame& f, const Grad& d, double& u1,
-                                  double& u2, double u3) {
-  const Coeffs& m = f.c;
-  const double s1 = u1, s2 = u2;
-  const double u33 = u3 * u3;
-  double t1 = s1, t2 = s2;
+template <class R>
+__device__ inline void geodesic_u(const Grid& g, const FrameT<R>& f, const GradT<R>& d, R& u1, R& u2,
+                                  R u3) {
+  const CoeffsT<R>& m = f.c;
+  const R s1 = u1, s2 = u2;
+  const R u33 = u3 * u3;
+  const R dt = (R)g.dt;
+  R t1 = s1, t2 = s2;
   for (int it = 0; it < g.n_iter; ++it) {
-    const double b1 = 0.5 * (s1 + t1), b2 = 0.5 * (s2 + t2);
-    const double Q = 1.0 + m.hu11 * b1 * b1 + m.hu22 * b2 * b2 + m.hu33 * u33 +
-                     2.0 * m.hu13 * b1 * u3;
-    const double ig = rsqrt(Q);
-    const double gb = Q * ig;
-    const double h = 0.5 * m.alpha * ig;
-    double fr[2];
+    const R b1 = (R)0.5 * (s1 + t1), b2 = (R)0.5 * (s2 + t2);
+    const R Q = (R)1 + m.hu11 * b1 * b1 + m.hu22 * b2 * b2 + m.hu33 * u33 + (R)2 * m.hu13 * b1 * u3;
+    const R ig = rsqrt(Q);
+    const R gb = Q * ig;
+    const R h = (R)0.5 * m.alpha * ig;
+    R fr[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const double q = d.hu11[i] * b1 * b1 + d.hu22[i] * b2 * b2 + d.hu33[i] * u33 +
-                       2.0 * d.hu13[i] * b1 * u3;
+      const R q = d.hu11[i] * b1 * b1 + d.hu22[i] * b2 * b2 + d.hu33[i] * u33 +
+                  (R)2 * d.hu13[i] * b1 * u3;
       fr[i] = -gb * d.alpha[i] + b1 * d.beta1[i] - h * q;
     }
-    const double n1 = s1 + g.dt * fr[0], n2 = s2 + g.dt * fr[1];
-    // exact repeat: the fixed point of the map; or the optional FP64 convergence test
+    const R n1 = s1 + dt * fr[0], n2 = s2 + dt * fr[1];
+    // exact repeat: the fixed point of the map; or the optional convergence
+    // test, evaluated in FP64
     const bool fixed = (n1 == t1 && n2 == t2) ||
-                       fabs(n1 - t1) + fabs(n2 - t2) <= g.iter_tol * (fabs(n1) + fabs(n2));
+                       fabs((double)n1 - (double)t1) + fabs((double)n2 - (double)t2) <=
+                           g.iter_tol * (fabs((double)n1) + fabs((double)n2));
     t1 = n1;
     t2 = n2;
     if (fixed) break;
@@ -143,12 +157,13 @@ __device__ inline void geodesic_u(const Grid& g, const Frame& f, const Grad& d, 
   u2 = t2;
 }
 
-__device__ inline void renormalize(int& i, double& dx) {
-  const double f = floor(dx);
+template <class R>
+__device__ inline void renormalize(int& i, R& dx) {
+  const R f = floor(dx);
   i += (int)f;
   dx -= f;
-  if (dx >= 1.0) {
-    dx -= 1.0;
+  if (dx >= (R)1) {
+    dx -= (R)1;
     i += 1;
   }
 }
@@ -225,27 +240,103 @@ __device__ inline RSC rsc_near(const Grid& g, const Tables& t, int i1, double x1
   return p;
 }
 
+// single-precision series for |x| <= 0.11 (truncation below 1e-9 relative)
+__device__ inline float exp_small_f(float t) {
+  float p = fmaf(t, 1.0f / 720.0f, 1.0f / 120.0f);
+  p = fmaf(t, p, 1.0f / 24.0f);
+  p = fmaf(t, p, 1.0f / 6.0f);
+  p = fmaf(t, p, 0.5f);
+  p = fmaf(t, p, 1.0f);
+  return fmaf(t, p, 1.0f);
+}
+
+__device__ inline void sincos_small_f(float x, float* s, float* c) {
+  const float z = x * x;
+  float ps = fmaf(z, -1.0f / 5040.0f, 1.0f / 120.0f);
+  ps = fmaf(z, ps, -1.0f / 6.0f);
+  *s = fmaf(x * z, ps, x);
+  float pc = fmaf(z, 1.0f / 40320.0f, -1.0f / 720.0f);
+  pc = fmaf(z, pc, 1.0f / 24.0f);
+  pc = fmaf(z, pc, -0.5f);
+  *c = fmaf(z, pc, 1.0f);
+}
+
+// Single precision: r, sin, cos at offsets (f1, f2) from the corner of cell
+// (i1, i2), |f| <= 1.5.  The polar angle is measured from the nearer axis,
+// theta = (i2 + f2) dth or pi - theta = (n_th - i2 - f2) dth, so that sin keeps
+// its relative precision next to either axis; clamped at small_angle.
 template <bool FAST>
-__global__ void __launch_bounds__(256) push_kernel(Grid g, Tables tab, GatherPlanes fp, ParticleArrays P) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= P.n) return;
+__device__ inline RSCT<float> rsc_near_f(const Grid& g, const Tables& t, int i1, float f1, int i2,
+                                        float f2) {
+  RSCT<float> p;
+  const float dth = (float)g.dth, eps = (float)g.small_angle;
+  p.r = FAST ? t.rf[i1 + g.ng] * exp_small_f(f1 * (float)g.dxi)
+             : t.rf[i1 + g.ng] * expf(f1 * (float)g.dxi);
+  const bool upper = 2 * i2 >= g.n_th;
+  const float ang = upper ? ((float)(g.n_th - i2) - f2) * dth : ((float)i2 + f2) * dth;
+  float s, c;
+  if (ang <= eps) {
+    s = (float)g.sin_lo;
+    c = (float)g.cos_lo;
+  } else if (!FAST) {
+    sincosf(ang, &s, &c);
+  } else if (ang <= 0.11f) {
+    sincos_small_f(ang, &s, &c);
+  } else {
+    // angle addition about the table node theta_i2 (float tables)
+    float sp, cp;
+    sincos_small_f(f2 * dth, &sp, &cp);
+    const float sj = t.sf[i2 + g.ng], cj = t.cf[i2 + g.ng];
+    p.s = fmaf(sj, cp, cj * sp);
+    p.c = fmaf(cj, cp, -(sj * sp));
+    return p;
+  }
+  p.s = s;
+  p.c = upper ? -c : c;
+  return p;
+}
+
+// What the deposit needs from one particle's move (Sec. 3.2).
+template <class T>
+struct Move {
+  bool dep;            // deposits a current this step
+  bool mid;            // vphi holds alpha u^3 / gamma at the deposit's path midpoint
+  int ia, ja, ib, jb;  // previous and current cell
+  T xa, ya, xb, yb;    // previous and current offsets
+  T q;                 // species sign x charge_scale x weight
+  T vphi;
+  T u1, u2, u3;        // u^{n+1/2}, for vphi when !mid
+};
+
+// FP64 particle update (Sec. 3.1 steps 1-11) of slot k; writes the new state
+// and returns the move for the deposit.
+template <bool FAST>
+__device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const GatherPlanesT<double>& fp,
+                                        const ParticleArrays& P, int64_t k) {
+  Move<double> mv;
+  mv.dep = false;
+  if (k >= P.n) return mv;
   uint8_t t = P.tag[k];
-  if (!is_live(t)) return;
+  if (!is_live(t)) return mv;
   if (t & kLeaving) {
     P.tag[k] = 0;
-    return;
+    return mv;
   }
   int i1 = P.i1[k], i2 = P.i2[k];
   double dx1 = P.dx1[k], dx2 = P.dx2[k];
   if (!in_grid(g, i1, dx1, i2, dx2)) {  // corrupt input: drop, never index with it
     P.tag[k] = kInvalid;
-    return;
+    return mv;
   }
   double u1 = P.u1[k], u2 = P.u2[k], u3 = P.u3[k];
   P.i1p[k] = i1;
   P.i2p[k] = i2;
   P.dx1p[k] = dx1;
   P.dx2p[k] = dx2;
+  mv.ia = i1;
+  mv.ja = i2;
+  mv.xa = dx1;
+  mv.ya = dx2;
 
   const double x1 = (double)i1 + dx1, x2 = (double)i2 + dx2;
   Frame f;
@@ -289,23 +380,28 @@ __global__ void __launch_bounds__(256) push_kernel(Grid g, Tables tab, GatherPla
     if (fixed) break;
   }
   {
+    // phi update and the phi velocity at the path midpoint (the J^3 of the deposit)
     const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
     const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
                                        m.hu33 * u3 * u3 + 2.0 * m.hu13 * u1 * u3);
     P.phi[k] += g.dt * (m.hu13 * u1 + m.hu33 * u3) * iu0;
+    mv.vphi = (m.hu13 * u1 + m.hu33 * u3) * iu0;
   }
   dx1 += d1;
   renormalize(i1, dx1);
   dx2 += d2;
   renormalize(i2, dx2);
+  mv.mid = true;
   if (i2 < 0) {
     i2 = 0;
     dx2 = 1.0 - dx2;
     u2 = -u2;
+    mv.mid = false;
   } else if (i2 >= g.n_th) {
     i2 = g.n_th - 1;
     dx2 = 1.0 - dx2;
     u2 = -u2;
+    mv.mid = false;
   }
   if (i1 < 0 || i1 >= g.n_r) t |= kLeaving;
   // a non-finite or more-than-one-cell move cannot be deposited: drop it
@@ -318,91 +414,276 @@ __global__ void __launch_bounds__(256) push_kernel(Grid g, Tables tab, GatherPla
   P.u2[k] = u2;
   P.u3[k] = u3;
   P.tag[k] = t;
+  mv.dep = is_live(t) && qm != 0.0;
+  mv.ib = i1;
+  mv.jb = i2;
+  mv.xb = dx1;
+  mv.yb = dx2;
+  mv.q = (qm * g.charge_scale) * P.w[k];
+  mv.u1 = u1;
+  mv.u2 = u2;
+  mv.u3 = u3;
+  return mv;
 }
 
-struct CurrentPlanes {
-  double* __restrict__ J[3];
+// Single-precision form of the same update (see the file comment).
+template <bool FAST>
+__device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, const GatherPlanesT<float>& fp,
+                                           const ParticleArraysT<float>& P, int64_t k) {
+  Move<float> mv;
+  mv.dep = false;
+  if (k >= P.n) return mv;
+  uint8_t t = P.tag[k];
+  if (!is_live(t)) return mv;
+  if (t & kLeaving) {
+    P.tag[k] = 0;
+    return mv;
+  }
+  int i1 = P.i1[k], i2 = P.i2[k];
+  float dx1 = P.dx1[k], dx2 = P.dx2[k];
+  if (!in_grid(g, i1, dx1, i2, dx2)) {
+    P.tag[k] = kInvalid;
+    return mv;
+  }
+  float u1 = P.u1[k], u2 = P.u2[k], u3 = P.u3[k];
+  P.i1p[k] = i1;
+  P.i2p[k] = i2;
+  P.dx1p[k] = dx1;
+  P.dx2p[k] = dx2;
+  mv.ia = i1;
+  mv.ja = i2;
+  mv.xa = dx1;
+  mv.ya = dx2;
+
+  FrameT<float> f;
+  GradT<float> d;
+  if (i1 < g.i_fp64) {
+    // horizon region: metric and derivatives in FP64, then rounded
+    Frame fd;
+    Grad dd;
+    frame_from(g, rsc_near<FAST>(g, tab, i1, (double)i1 + dx1, i2, (double)i2 + dx2), &fd, &dd);
+    f.c = CoeffsT<float>{(float)fd.c.alpha, (float)fd.c.beta1, (float)fd.c.hu11,
+                         (float)fd.c.hu22, (float)fd.c.hu33, (float)fd.c.hu13};
+    f.s11 = (float)fd.s11;
+    f.s22 = (float)fd.s22;
+    f.s33 = (float)fd.s33;
+    f.k13 = (float)fd.k13;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      d.alpha[q] = (float)dd.alpha[q];
+      d.beta1[q] = (float)dd.beta1[q];
+      d.hu11[q] = (float)dd.hu11[q];
+      d.hu22[q] = (float)dd.hu22[q];
+      d.hu33[q] = (float)dd.hu33[q];
+      d.hu13[q] = (float)dd.hu13[q];
+    }
+  } else {
+    frame_from(g, rsc_near_f<FAST>(g, tab, i1, dx1, i2, dx2), &f, &d);
+  }
+  const float qm = (float)species_sign(t);
+  if (qm != 0.0f) {
+    const float D1 = interp<1, 0>(g, fp.D[0], i1, dx1, i2, dx2);
+    const float D2 = interp<0, 1>(g, fp.D[1], i1, dx1, i2, dx2);
+    const float D3 = interp<0, 0>(g, fp.D[2], i1, dx1, i2, dx2);
+    const float B1 = interp<0, 1>(g, fp.B[0], i1, dx1, i2, dx2);
+    const float B2 = interp<1, 0>(g, fp.B[1], i1, dx1, i2, dx2);
+    const float B3 = interp<1, 1>(g, fp.B[2], i1, dx1, i2, dx2);
+    const float al = f.c.alpha;
+    const float E[3] = {al * D1 / f.s11, al * f.s22 * D2, al * f.s33 * (f.k13 * D1 + D3)};
+    const float B[3] = {al * B1 / f.s11, al * f.s22 * B2, al * f.s33 * (f.k13 * B1 + B3)};
+    const float kb = 0.25f * qm * (float)g.dt;
+    em_half(f, E, B, kb, u1, u2, u3);
+    geodesic_u(g, f, d, u1, u2, u3);
+    em_half(f, E, B, kb, u1, u2, u3);
+  } else {
+    geodesic_u(g, f, d, u1, u2, u3);
+  }
+
+  // implicit coordinate update with the displacement (d1, d2) in cells
+  const float dt = (float)g.dt;
+  float d1 = 0.0f, d2 = 0.0f;
+  for (int it = 0; it < g.n_iter; ++it) {
+    const CoeffsT<float> m =
+        coeffs_from(g, rsc_near_f<FAST>(g, tab, i1, dx1 + 0.5f * d1, i2, dx2 + 0.5f * d2));
+    const float iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
+                                      m.hu33 * u3 * u3 + 2.0f * m.hu13 * u1 * u3);
+    const float n1 = dt * ((m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1);
+    const float n2 = dt * (m.hu22 * u2 * iu0);
+    const bool fixed = (n1 == d1 && n2 == d2) ||
+                       fabs((double)n1 - (double)d1) + fabs((double)n2 - (double)d2) <=
+                           g.iter_tol * (fabs((double)n1) + fabs((double)n2));
+    d1 = n1;
+    d2 = n2;
+    if (fixed) break;
+  }
+  {
+    const CoeffsT<float> m =
+        coeffs_from(g, rsc_near_f<FAST>(g, tab, i1, dx1 + 0.5f * d1, i2, dx2 + 0.5f * d2));
+    const float iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
+                                      m.hu33 * u3 * u3 + 2.0f * m.hu13 * u1 * u3);
+    mv.vphi = (m.hu13 * u1 + m.hu33 * u3) * iu0;
+    P.phi[k] += dt * mv.vphi;
+  }
+  dx1 += d1;
+  renormalize(i1, dx1);
+  dx2 += d2;
+  renormalize(i2, dx2);
+  mv.mid = true;
+  if (i2 < 0) {
+    i2 = 0;
+    dx2 = 1.0f - dx2;
+    u2 = -u2;
+    mv.mid = false;
+  } else if (i2 >= g.n_th) {
+    i2 = g.n_th - 1;
+    dx2 = 1.0f - dx2;
+    u2 = -u2;
+    mv.mid = false;
+  }
+  if (i1 < 0 || i1 >= g.n_r) t |= kLeaving;
+  if (!(fabsf(d1) < 1.0f && fabsf(d2) < 1.0f)) t = kInvalid;
+  P.i1[k] = i1;
+  P.i2[k] = i2;
+  P.dx1[k] = dx1;
+  P.dx2[k] = dx2;
+  P.u1[k] = u1;
+  P.u2[k] = u2;
+  P.u3[k] = u3;
+  P.tag[k] = t;
+  mv.dep = is_live(t) && qm != 0.0f;
+  mv.ib = i1;
+  mv.jb = i2;
+  mv.xb = dx1;
+  mv.yb = dx2;
+  mv.q = (float)(species_sign(t) * g.charge_scale) * P.w[k];
+  mv.u1 = u1;
+  mv.u2 = u2;
+  mv.u3 = u3;
+  return mv;
+}
+
+// The move of slot k as stored by the push (previous and current position).
+template <class T>
+__device__ inline Move<T> load_move(const Grid& g, const ParticleArraysT<T>& P, int64_t k) {
+  Move<T> mv;
+  mv.dep = false;
+  mv.mid = false;
+  if (k >= P.n) return mv;
+  const uint8_t t = P.tag[k];
+  if (!is_live(t)) return mv;
+  const double sg = species_sign(t);
+  if (sg == 0.0) return mv;
+  mv.dep = true;
+  mv.q = (T)(sg * g.charge_scale) * P.w[k];
+  mv.ia = P.i1p[k];
+  mv.ja = P.i2p[k];
+  mv.xa = P.dx1p[k];
+  mv.ya = P.dx2p[k];
+  mv.ib = P.i1[k];
+  mv.jb = P.i2[k];
+  mv.xb = P.dx1[k];
+  mv.yb = P.dx2[k];
+  mv.u1 = P.u1[k];
+  mv.u2 = P.u2[k];
+  mv.u3 = P.u3[k];
+  return mv;
+}
+
+template <class T>
+struct CurrentPlanesT {
+  T* __restrict__ J[3];
 };
+using CurrentPlanes = CurrentPlanesT<double>;
 
 __device__ inline void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+__device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
-// Zigzag charge-conserving deposit (Umeda et al. 2003) in code coordinates
-// from the previous to the current position, plus J^3 = q alpha u^3 / gamma at
-// the path midpoint with first-order node weights.
-//
-// A block first accumulates its particles' contributions in a shared-memory
-// tile of kTI x kTJ nodes per component (LDS atomics), then adds each touched
-// tile node to the global planes once.  Particles sorted by cell make the
-// block's footprint small; a block whose footprint exceeds the tile adds
-// directly to global memory.
+// ------------------------------------------------------------------ deposit
+// Charge-conserving zigzag split (Sec. 3.2) of the move from (ia + xa, ja + ya)
+// to (ib + xb, jb + yb): the path is cut at the relay point r, each segment
+// deposits J^1 and J^2 (normalised by 1/dt) on the edges of the cell it lies
+// in, with first-order weights at the segment midpoint; J^3 = q alpha u^3 /
+// gamma goes to the four nodes around the path midpoint.
 constexpr int kDepBlock = 256;
 constexpr int kTI = 8, kTJ = 48;
 
-struct Contrib {
+template <class T>
+struct ContribT {
   int ia, ja;         // previous cell: anchor of the 4 x 4 footprint [ia-1, ia+2] x [ja-1, ja+2]
   int di, dj, km, lm; // cell step, J^3 node corner (relative to the anchor)
-  double j1[4], j2[4], j3[4];
+  T j1[4], j2[4], j3[4];
 };
 
+// lapse-weighted phi velocity alpha u^3 / gamma at the path midpoint (ia + xm, ja + ym)
 template <bool FAST>
-__device__ inline bool make_contrib(const Grid& g, const Tables& tab, const ParticleArrays& P,
-                                    int64_t k, Contrib& c) {
-  if (k >= P.n) return false;
-  const uint8_t t = P.tag[k];
-  if (!is_live(t)) return false;
-  const double sg = species_sign(t);
-  if (sg == 0.0) return false;
-  const int ia = P.i1p[k], ja = P.i2p[k];
-  const int di = P.i1[k] - ia, dj = P.i2[k] - ja;
+__device__ inline double vphi_mid(const Grid& g, const Tables& tab, int ia, double xm, int ja,
+                                  double ym, double u1, double u2, double u3) {
+  const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, ia, (double)ia + xm, ja, (double)ja + ym));
+  const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+                                     2.0 * m.hu13 * u1 * u3);
+  return (m.hu13 * u1 + m.hu33 * u3) * iu0;
+}
+template <bool FAST>
+__device__ inline float vphi_mid(const Grid& g, const Tables& tab, int ia, float xm, int ja,
+                                 float ym, float u1, float u2, float u3) {
+  const CoeffsT<float> m = coeffs_from(g, rsc_near_f<FAST>(g, tab, ia, xm, ja, ym));
+  const float iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+                                    2.0f * m.hu13 * u1 * u3);
+  return (m.hu13 * u1 + m.hu33 * u3) * iu0;
+}
+
+template <class T, bool FAST>
+__device__ inline bool make_contrib(const Grid& g, const Tables& tab, const Move<T>& mv, ContribT<T>& c) {
+  c.ia = c.ja = c.di = c.dj = c.km = c.lm = 0;
+  if (!mv.dep) return false;
+  const int ia = mv.ia, ja = mv.ja;
+  const int di = mv.ib - ia, dj = mv.jb - ja;
   // the zigzag touches at most cells ia-1 .. ia+2: both ends must be in range
-  if (!in_grid(g, ia, P.dx1p[k], ja, P.dx2p[k]) ||
-      !in_deposit_range(g, P.i1[k], P.dx1[k], P.i2[k], P.dx2[k]) || abs(di) > 1 || abs(dj) > 1)
+  if (!in_grid(g, ia, mv.xa, ja, mv.ya) || !in_deposit_range(g, mv.ib, mv.xb, mv.jb, mv.yb) ||
+      abs(di) > 1 || abs(dj) > 1)
     return false;
-  const double q = sg * g.charge_scale * P.w[k];
-  const double qdt = q / g.dt;
-  const double xa = P.dx1p[k], ya = P.dx2p[k];
-  const double xb = (double)di + P.dx1[k], yb = (double)dj + P.dx2[k];
-  const double xr = fmin((double)min(0, di) + 1.0, fmax((double)max(0, di), 0.5 * (xa + xb)));
-  const double yr = fmin((double)min(0, dj) + 1.0, fmax((double)max(0, dj), 0.5 * (ya + yb)));
-  const double fx1 = qdt * (xr - xa), fy1 = qdt * (yr - ya);
-  const double fx2 = qdt * (xb - xr), fy2 = qdt * (yb - yr);
-  const double wx1 = 0.5 * (xa + xr), wy1 = 0.5 * (ya + yr);
-  const double wx2 = 0.5 * (xr + xb) - di, wy2 = 0.5 * (yr + yb) - dj;
+  const T q = mv.q;
+  const T qdt = q / (T)g.dt;
+  const T one = (T)1, half = (T)0.5;
+  const T xa = mv.xa, ya = mv.ya;
+  const T xb = (T)di + mv.xb, yb = (T)dj + mv.yb;
+  const T xr = fmin((T)min(0, di) + one, fmax((T)max(0, di), half * (xa + xb)));
+  const T yr = fmin((T)min(0, dj) + one, fmax((T)max(0, dj), half * (ya + yb)));
+  const T fx1 = qdt * (xr - xa), fy1 = qdt * (yr - ya);
+  const T fx2 = qdt * (xb - xr), fy2 = qdt * (yb - yr);
+  const T wx1 = half * (xa + xr), wy1 = half * (ya + yr);
+  const T wx2 = half * (xr + xb) - (T)di, wy2 = half * (yr + yb) - (T)dj;
   c.ia = ia;
   c.ja = ja;
   c.di = di;
   c.dj = dj;
   // J^1 at (ia, ja), (ia, ja+1), (ib, jb), (ib, jb+1); J^2 at (ia, ja), (ia+1, ja), (ib, jb), (ib+1, jb)
-  c.j1[0] = fx1 * (1.0 - wy1);
+  c.j1[0] = fx1 * (one - wy1);
   c.j1[1] = fx1 * wy1;
-  c.j1[2] = fx2 * (1.0 - wy2);
+  c.j1[2] = fx2 * (one - wy2);
   c.j1[3] = fx2 * wy2;
-  c.j2[0] = fy1 * (1.0 - wx1);
+  c.j2[0] = fy1 * (one - wx1);
   c.j2[1] = fy1 * wx1;
-  c.j2[2] = fy2 * (1.0 - wx2);
+  c.j2[2] = fy2 * (one - wx2);
   c.j2[3] = fy2 * wx2;
-  const double xm = 0.5 * (xa + xb), ym = 0.5 * (ya + yb);
-  const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, ia, (double)ia + xm, ja, (double)ja + ym));
-  const double u1 = P.u1[k], u2 = P.u2[k], u3 = P.u3[k];
-  const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
-                                     2.0 * m.hu13 * u1 * u3);
-  const double vphi = (m.hu13 * u1 + m.hu33 * u3) * iu0;
-  const double fm = floor(xm), gm = floor(ym);
-  const double w1 = xm - fm, w2 = ym - gm;
-  const double c3 = q * vphi;
+  const T xm = half * (xa + xb), ym = half * (ya + yb);
+  const T vphi = mv.mid ? mv.vphi : vphi_mid<FAST>(g, tab, ia, xm, ja, ym, mv.u1, mv.u2, mv.u3);
+  const T fm = floor(xm), gm = floor(ym);
+  const T w1 = xm - fm, w2 = ym - gm;
+  const T c3 = q * vphi;
   c.km = (int)fm;
   c.lm = (int)gm;
   // J^3 at (km, lm), (km, lm+1), (km+1, lm), (km+1, lm+1)
-  c.j3[0] = c3 * (1.0 - w1) * (1.0 - w2);
-  c.j3[1] = c3 * (1.0 - w1) * w2;
-  c.j3[2] = c3 * w1 * (1.0 - w2);
+  c.j3[0] = c3 * (one - w1) * (one - w2);
+  c.j3[1] = c3 * (one - w1) * w2;
+  c.j3[2] = c3 * w1 * (one - w2);
   c.j3[3] = c3 * w1 * w2;
   return true;
 }
 
 // Adds a contribution through `add(component, i, j, value)` (absolute node indices).
-template <class Add>
-__device__ inline void scatter(const Contrib& c, Add add) {
+template <class T, class Add>
+__device__ inline void scatter(const ContribT<T>& c, Add add) {
   const int ia = c.ia, ja = c.ja, ib = c.ia + c.di, jb = c.ja + c.dj;
   add(0, ia, ja, c.j1[0]);
   add(0, ia, ja + 1, c.j1[1]);
@@ -419,14 +700,60 @@ __device__ inline void scatter(const Contrib& c, Add add) {
   add(2, km + 1, lm + 1, c.j3[3]);
 }
 
-template <bool FAST>
-__global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, ParticleArrays P,
-                                                            CurrentPlanes cp) {
-  __shared__ double tile[3][kTI][kTJ];
+// Runs of equal keys in consecutive lanes of a wavefront: `end` is the last
+// lane of this lane's run, `head` marks the first lane of a run; `longest` is
+// the longest run (wave-uniform).
+struct Runs {
+  int end, longest;
+  bool head;
+};
+
+__device__ inline Runs runs_of(int key) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  Runs r;
+  r.head = lane == 0 || prev != key;
+  const unsigned long long heads = __ballot(r.head);
+  const unsigned long long after = lane == 63 ? 0ull : (heads >> (lane + 1));
+  r.end = after ? lane + __ffsll((long long)after) - 1 : 63;
+  // longest gap between consecutive heads (bit 0 is always set)
+  unsigned long long m = heads & ~1ull;
+  int last = 0, best = 0;
+  while (m) {
+    const int b = __ffsll((long long)m) - 1;
+    best = max(best, b - last);
+    last = b;
+    m &= m - 1;
+  }
+  r.longest = max(best, 64 - last);
+  return r;
+}
+
+// Sum of v over this lane's run from this lane to the run's end (the head
+// ends up with the run total): segmented suffix sum by doubling.
+template <class T>
+__device__ inline T run_sum(T v, const Runs& r) {
+  const int lane = threadIdx.x & 63;
+  for (int off = 1; off < r.longest; off <<= 1) {
+    const T o = __shfl_down(v, off, 64);
+    if (lane + off <= r.end) v += o;
+  }
+  return v;
+}
+
+// Block-level deposit: the 4 x 4 footprints of the block's particles are
+// accumulated in an LDS tile, then added to the planes with one global atomic
+// per touched node.  Particles are cell-sorted, so lanes of a wavefront share
+// cells: contributions of a run of lanes with the same cell are summed across
+// lanes first (one LDS atomic per run and node instead of one per lane, which
+// would serialise on the shared address).  A block whose footprint does not
+// fit the tile adds straight to the planes.  Every lane of the block must call
+// this.
+template <class T>
+__device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp, bool act,
+                                     const ContribT<T>& c) {
+  __shared__ T tile[3][kTI][kTJ];
   __shared__ int bound[4][kDepBlock / 64];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  Contrib c;
-  const bool act = make_contrib<FAST>(g, tab, P, k, c);
   // block footprint: union of [ia-1, ia+2] x [ja-1, ja+2]
   int v[4] = {act ? c.ia - 1 : INT_MAX, act ? -(c.ia + 2) : INT_MAX, act ? c.ja - 1 : INT_MAX,
               act ? -(c.ja + 2) : INT_MAX};
@@ -437,8 +764,8 @@ __global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, 
     if (lane == 0) bound[q][wv] = v[q];
   }
   // zero the tile while the bounds settle
-  double* flat = &tile[0][0][0];
-  for (int e = threadIdx.x; e < 3 * kTI * kTJ; e += kDepBlock) flat[e] = 0.0;
+  T* flat = &tile[0][0][0];
+  for (int e = threadIdx.x; e < 3 * kTI * kTJ; e += kDepBlock) flat[e] = (T)0;
   __syncthreads();
   int b[4];
 #pragma unroll
@@ -451,19 +778,96 @@ __global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, 
   const bool fits = (i1 - i0 < kTI) && (j1 - j0 < kTJ);
   if (!fits) {
     if (act)
-      scatter(c, [&](int comp, int i, int j, double val) { atomic_add(cp.J[comp] + ix(g, i, j), val); });
+      scatter(c, [&](int comp, int i, int j, T val) { atomic_add(cp.J[comp] + ix(g, i, j), val); });
     return;
   }
-  if (act)
-    scatter(c, [&](int comp, int i, int j, double val) { atomicAdd(&tile[comp][i - i0][j - j0], val); });
+  const T z = (T)0;
+  // segment 1 (previous cell), with segment 2 folded in when the particle stays in its cell
+  const bool stay = act && c.di == 0 && c.dj == 0;
+  const int ra = c.ia - i0, ca = c.ja - j0;
+  const Runs sa = runs_of(act ? ra * kTJ + ca : -1);
+  const T a0 = run_sum(act ? c.j1[0] + (stay ? c.j1[2] : z) : z, sa);
+  const T a1 = run_sum(act ? c.j1[1] + (stay ? c.j1[3] : z) : z, sa);
+  const T a2 = run_sum(act ? c.j2[0] + (stay ? c.j2[2] : z) : z, sa);
+  const T a3 = run_sum(act ? c.j2[1] + (stay ? c.j2[3] : z) : z, sa);
+  // J^3 nodes around the path midpoint
+  const int rm = ra + c.km, cm = ca + c.lm;
+  const Runs sm = runs_of(act ? rm * kTJ + cm : -1);
+  const T m0 = run_sum(act ? c.j3[0] : z, sm);
+  const T m1 = run_sum(act ? c.j3[1] : z, sm);
+  const T m2 = run_sum(act ? c.j3[2] : z, sm);
+  const T m3 = run_sum(act ? c.j3[3] : z, sm);
+  if (act && sa.head) {
+    atomicAdd(&tile[0][ra][ca], a0);
+    atomicAdd(&tile[0][ra][ca + 1], a1);
+    atomicAdd(&tile[1][ra][ca], a2);
+    atomicAdd(&tile[1][ra + 1][ca], a3);
+  }
+  if (act && !stay) {  // segment 2 in the new cell
+    const int rb = ra + c.di, cb = ca + c.dj;
+    atomicAdd(&tile[0][rb][cb], c.j1[2]);
+    atomicAdd(&tile[0][rb][cb + 1], c.j1[3]);
+    atomicAdd(&tile[1][rb][cb], c.j2[2]);
+    atomicAdd(&tile[1][rb + 1][cb], c.j2[3]);
+  }
+  if (act && sm.head) {
+    atomicAdd(&tile[2][rm][cm], m0);
+    atomicAdd(&tile[2][rm][cm + 1], m1);
+    atomicAdd(&tile[2][rm + 1][cm], m2);
+    atomicAdd(&tile[2][rm + 1][cm + 1], m3);
+  }
   __syncthreads();
   for (int e = threadIdx.x; e < 3 * kTI * kTJ; e += kDepBlock) {
-    const double val = flat[e];
-    if (val != 0.0) {
+    const T val = flat[e];
+    if (val != z) {
       const int comp = e / (kTI * kTJ), rem = e % (kTI * kTJ);
       atomic_add(cp.J[comp] + ix(g, i0 + rem / kTJ, j0 + rem % kTJ), val);
     }
   }
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <bool FAST>
+__global__ void __launch_bounds__(256) push_kernel(Grid g, Tables tab, GatherPlanesT<double> fp,
+                                                   ParticleArrays P) {
+  (void)push_one<FAST>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <bool FAST>
+__global__ void __launch_bounds__(256) push_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
+                                                       ParticleArraysT<float> P) {
+  (void)push_one_f32<FAST>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <class T, bool FAST>
+__global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, ParticleArraysT<T> P,
+                                                            CurrentPlanesT<T> cp) {
+  const Move<T> mv = load_move(g, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  ContribT<T> c;
+  const bool act = make_contrib<T, FAST>(g, tab, mv, c);
+  deposit_block(g, cp, act, c);
+}
+
+// Push and deposit in one pass: the deposit takes the move from registers and
+// J^3 from the push's own midpoint metric.
+template <bool FAST>
+__global__ void __launch_bounds__(kDepBlock) push_deposit_kernel(Grid g, Tables tab, GatherPlanesT<double> fp,
+                                                                 ParticleArrays P, CurrentPlanes cp) {
+  const Move<double> mv = push_one<FAST>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  ContribT<double> c;
+  const bool act = make_contrib<double, FAST>(g, tab, mv, c);
+  deposit_block(g, cp, act, c);
+}
+
+template <bool FAST>
+__global__ void __launch_bounds__(kDepBlock) push_deposit_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
+                                                                     ParticleArraysT<float> P,
+                                                                     CurrentPlanesT<float> cp) {
+  const Move<float> mv = push_one_f32<FAST>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  ContribT<float> c;
+  const bool act = make_contrib<float, FAST>(g, tab, mv, c);
+  deposit_block(g, cp, act, c);
 }
 
 }  // namespace grpic

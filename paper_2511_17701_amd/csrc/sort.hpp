@@ -13,7 +13,8 @@ namespace grpic {
 
 constexpr int kScanBlock = 1024;  // elements scanned per block (4 per thread)
 
-__device__ inline int sort_key(const Grid& g, const ParticleArrays& P, int64_t k) {
+template <class T>
+__device__ inline int sort_key(const Grid& g, const ParticleArraysT<T>& P, int64_t k) {
   const uint8_t t = P.tag[k];
   const int ncell = g.n_r * g.n_th;
   if (!is_live(t) || (t & kLeaving)) return ncell;
@@ -44,7 +45,8 @@ __device__ inline Run wave_run(int key) {
   return r;
 }
 
-__global__ void __launch_bounds__(256) sort_count_kernel(Grid g, ParticleArrays P,
+template <class T>
+__global__ void __launch_bounds__(256) sort_count_kernel(Grid g, ParticleArraysT<T> P,
                                                          int* __restrict__ counts) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int key = k < P.n ? sort_key(g, P, k) : -1;  // -1: past the end (own run)
@@ -114,7 +116,8 @@ __global__ void scan_add_kernel(int* __restrict__ a, int64_t n, const int* __res
 // Moves slot k of S to its cell's next free slots in D; emptied slots get tag
 // 0.  A run of equal keys in a wavefront takes consecutive slots in lane order;
 // the order of runs of one cell follows the order of the atomics.
-__global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArrays S, ParticleArrays D,
+template <class T>
+__global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArraysT<T> S, ParticleArraysT<T> D,
                                                            int* __restrict__ off) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int key = k < S.n ? sort_key(g, S, k) : -1;

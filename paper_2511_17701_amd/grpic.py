@@ -6,8 +6,9 @@ it loads libgrpic.so and raises if the library is missing: there is no CPU
 fallback.
 
 Storage mirrors the C ABI: a field set is one tensor of shape
-(33, n_r + 2 ng, n_th + 2 ng) whose planes are D(3) B(3) D0(3) B0(3) E(3) H(3)
-J(3) J0(3) Dinit(3) Binit(3) T(3); particles are a dict of 1-D tensors.
+(n_planes, n_r + 2 ng, n_th + 2 ng) whose planes are D(3) B(3) D0(3) B0(3) E(3)
+H(3) J(3) J0(3) Dinit(3) Binit(3) T(3), plus Dc(3) Bc(3) in the FP32 form
+(n_planes = 33 in FP64, 39 in FP32); particles are a dict of 1-D tensors.
 """
 from __future__ import annotations
 
@@ -23,8 +24,9 @@ LIB_PATH = os.path.join(HERE, "libgrpic.so")
 GRPIC_FP64, GRPIC_FP32 = 0, 1
 PRE_PUSH, POST_DEPOSIT = 0, 1
 NPLANE = 33
+NPLANE_FP32 = 39
 PLANES = {"D": 0, "B": 3, "D0": 6, "B0": 9, "E": 12, "H": 15, "J": 18, "J0": 21,
-          "Dinit": 24, "Binit": 27, "T": 30}
+          "Dinit": 24, "Binit": 27, "T": 30, "Dc": 33, "Bc": 36}
 TAG_LEAVING = 0x80
 
 PARTICLE_FIELDS = ["i1", "i2", "dx1", "dx2", "u1", "u2", "u3", "w", "phi",
@@ -48,7 +50,7 @@ class Params(ctypes.Structure):
 
 class Fields(ctypes.Structure):
     _fields_ = [(name, c_void_p * 3) for name in
-                ("D", "B", "D0", "B0", "E", "H", "J", "J0", "Dinit", "Binit", "T")]
+                ("D", "B", "D0", "B0", "E", "H", "J", "J0", "Dinit", "Binit", "T", "Dc", "Bc")]
 
 
 class Particles(ctypes.Structure):
@@ -75,6 +77,7 @@ _sigs = {
     "grpic_fields_init_wald": ([c_void_p, _F, c_double, c_void_p], c_int32),
     "grpic_push": ([c_void_p, _F, _PP, c_void_p], c_int32),
     "grpic_deposit": ([c_void_p, _PP, _F, c_void_p], c_int32),
+    "grpic_push_deposit": ([c_void_p, _F, _PP, c_void_p], c_int32),
     "grpic_field_advance": ([c_void_p, _F, c_int32, c_void_p], c_int32),
     "grpic_sort": ([c_void_p, _PP, _PP, POINTER(c_int64), c_void_p], c_int32),
     "grpic_diagnostics": ([c_void_p, _F, _PP, c_double, POINTER(Diag), c_void_p, c_void_p,
@@ -124,6 +127,7 @@ class Context:
         _check(_lib.grpic_get_params(h, ctypes.byref(q)), "grpic_get_params")
         self.params = q
         self.dtype = _dtype(precision)
+        self.n_planes = NPLANE_FP32 if precision == GRPIC_FP32 else NPLANE
 
     @property
     def dt(self) -> float:
@@ -147,7 +151,7 @@ class Context:
 
     # ------------------------------------------------------------ storage
     def new_fields(self, device="cuda") -> torch.Tensor:
-        return torch.zeros((NPLANE,) + self.shape, dtype=self.dtype, device=device)
+        return torch.zeros((self.n_planes,) + self.shape, dtype=self.dtype, device=device)
 
     def new_particles(self, n: int, device="cuda") -> dict:
         P = {}
@@ -161,15 +165,18 @@ class Context:
         return P
 
     def _fields(self, F: torch.Tensor) -> Fields:
-        if F.shape != (NPLANE,) + self.shape or F.dtype != self.dtype or not F.is_contiguous():
+        if F.shape != (self.n_planes,) + self.shape or F.dtype != self.dtype or \
+                not F.is_contiguous():
             raise GrpicError(f"field tensor must be contiguous {self.dtype} of shape "
-                             f"{(NPLANE,) + self.shape}")
+                             f"{(self.n_planes,) + self.shape}")
         if not F.is_cuda:
             raise GrpicError("field tensor must be on the GPU")
         s = Fields()
         base = F.data_ptr()
         step = F[0].numel() * F.element_size()
         for name, first in PLANES.items():
+            if first >= self.n_planes:
+                continue
             arr = getattr(s, name)
             for c in range(3):
                 arr[c] = base + (first + c) * step
@@ -202,6 +209,11 @@ class Context:
     def deposit(self, P: dict, F: torch.Tensor):
         _check(_lib.grpic_deposit(self._h, ctypes.byref(self._particles(P)),
                                   ctypes.byref(self._fields(F)), _stream()), "grpic_deposit")
+
+    def push_deposit(self, F: torch.Tensor, P: dict):
+        _check(_lib.grpic_push_deposit(self._h, ctypes.byref(self._fields(F)),
+                                       ctypes.byref(self._particles(P)), _stream()),
+               "grpic_push_deposit")
 
     def field_advance(self, F: torch.Tensor, stage: int):
         _check(_lib.grpic_field_advance(self._h, ctypes.byref(self._fields(F)), stage, _stream()),
@@ -238,9 +250,13 @@ class Context:
             out["gauss_res"] = R
         return out
 
-    def step(self, F: torch.Tensor, P: dict):
-        """One PIC step (Sec. 3.4): pre-push field stage, push, deposit, post-deposit stage."""
+    def step(self, F: torch.Tensor, P: dict, fused: bool = False):
+        """One PIC step (Sec. 3.4): pre-push field stage, push, deposit, post-deposit
+        stage (push and deposit in one pass when fused)."""
         self.field_advance(F, PRE_PUSH)
-        self.push(F, P)
-        self.deposit(P, F)
+        if fused:
+            self.push_deposit(F, P)
+        else:
+            self.push(F, P)
+            self.deposit(P, F)
         self.field_advance(F, POST_DEPOSIT)

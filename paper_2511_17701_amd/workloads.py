@@ -7,7 +7,10 @@ the oracle-side tests and the HIP-side tests and benchmark take their inputs
 from here.
 
 Configurations (Kerr, M = 1, log-spaced r from 0.9 r_h, theta in [0, pi], Wald
-vacuum field, Maxwell-Juttner pairs, CFL 0.5):
+vacuum field, Maxwell-Juttner pairs, CFL 0.5; deposited charge per unit weight
+kappa = 1e-8, a tenuous plasma whose plasma frequency stays far below 1/dt
+even in the smallest cells next to the axis, so the Wald field dominates while
+every particle still deposits a non-zero current):
 
 ========  =====  ======  =========  ====================================  =====  =========
 name      a      grid    r_max      particles                             steps  form
@@ -48,6 +51,7 @@ class Workload:
     n_iter: int = 10
     small_angle: float = 1e-5
     seed: int = 0
+    charge_scale: float = 1e-8
     ng: int = 2
     full_step: bool = False    # field_advance inside the step
 

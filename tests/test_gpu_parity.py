@@ -237,6 +237,65 @@ def test_deposit_parity(O, G):
     assert_fields(F, Fg.cpu().numpy(), range(18, 21), what="deposit")
 
 
+def _sorted_state(O, prm, w, ppc=16):
+    """Cell-ordered loading (pairs of cell c at slots of c): lanes of a
+    wavefront share cells, as after the cell sort."""
+    F = O.fields_init_wald(prm, w.B0)
+    P = O.particles_init(prm, 0, ppc, w.T, 0, w.seed)
+    return F, P
+
+
+def test_deposit_parity_cell_ordered(O, G):
+    """Deposit of cell-ordered particles: the LDS-tile path with the
+    wavefront run sums (C2 recipe, 64^2, 16 ppc)."""
+    w = wl("c2_512", 64)
+    prm, ctx = pair(O, G, w, charge_scale=0.3)
+    F, P = _sorted_state(O, prm, w)
+    for step in range(3):
+        O.push(prm, F, P)
+        Fg, Pg = up({"F": F})["F"], up(P)
+        O.deposit(prm, F, P)
+        ctx.deposit(Pg, Fg)
+        assert_fields(F, Fg.cpu().numpy(), range(18, 21), what=f"deposit {step}")
+        F[18:21] = 0.0
+
+
+@pytest.mark.parametrize("ordered", [True, False])
+def test_push_deposit_fused_parity(O, G, ordered):
+    """grpic_push_deposit against the oracle's push then deposit, per step
+    (particle state to the push bar, currents to the field bar)."""
+    w = wl("c2_512", 64) if ordered else wl("c1_64")
+    prm, ctx = pair(O, G, w, charge_scale=0.3)
+    F, P = _sorted_state(O, prm, w) if ordered else _state(O, prm, w, n_pairs=30000)
+    for step in range(3):
+        Fg, Pg = up({"F": F})["F"], up(P)
+        O.push(prm, F, P)
+        O.deposit(prm, F, P)
+        ctx.push_deposit(Fg, Pg)
+        assert_particles(prm, P, down(Pg), what=f"fused step {step}")
+        assert_fields(F, Fg.cpu().numpy(), range(18, 21), what=f"fused J step {step}")
+        F[18:21] = 0.0
+
+
+def test_push_deposit_fused_equals_separate(O, G):
+    """The fused pass writes the same particle state as grpic_push (bit for
+    bit) and the same currents as grpic_deposit (to rounding order)."""
+    import torch
+    w = wl("c2_512", 64)
+    prm, ctx = pair(O, G, w, charge_scale=0.3)
+    F, P = _sorted_state(O, prm, w)
+    Fa, Pa = up({"F": F})["F"], up(P)
+    Fb, Pb = up({"F": F})["F"], up(P)
+    for _ in range(3):
+        ctx.push(Fa, Pa)
+        ctx.deposit(Pa, Fa)
+        ctx.push_deposit(Fb, Pb)
+    torch.cuda.synchronize()
+    for k in Pa:
+        assert torch.equal(Pa[k], Pb[k]), k
+    assert_fields(Fa.cpu().numpy(), Fb.cpu().numpy(), range(18, 21), what="fused vs separate")
+
+
 # ---------------------------------------------------------------- fields
 
 def test_field_advance_parity(O, G):
@@ -258,16 +317,17 @@ def test_field_advance_parity(O, G):
     assert_fields(F, Fg.cpu().numpy(), list(range(0, 24)), what="post-deposit")
 
 
-def test_full_step_parity(O, G):
+@pytest.mark.parametrize("fused", [False, True])
+def test_full_step_parity(O, G, fused):
     """Full PIC steps (pre-push, push, deposit, post-deposit) with charge,
     4 filter passes and an absorbing layer (the C5 recipe on a 48^2 grid)."""
     w = wl("c5_4096", 48, n_absorb=6)
     prm, ctx = pair(O, G, w, charge_scale=0.02)
-    F, P = _state(O, prm, w, n_pairs=8000)
+    F, P = _sorted_state(O, prm, w, ppc=8) if fused else _state(O, prm, w, n_pairs=8000)
     for step in range(4):
         Fg, Pg = up({"F": F})["F"], up(P)
         O.step(prm, F, P)
-        ctx.step(Fg, Pg)
+        ctx.step(Fg, Pg, fused=fused)
         assert_fields(F, Fg.cpu().numpy(), list(range(0, 24)), what=f"step {step}")
         assert_particles(prm, P, down(Pg), what=f"step {step}")
 
@@ -339,6 +399,8 @@ def test_edge_cases(O, G):
     for step in range(3):
         Pg = up(P)
         Fg = up({"F": F})["F"]
+        P0 = {k: v.copy() for k, v in P.items()}
+        F0 = F.copy()
         O.push(prm, F, P)
         ctx.push(Fg, Pg)
         Pd = down(Pg)
@@ -346,6 +408,10 @@ def test_edge_cases(O, G):
         O.deposit(prm, F, P)
         ctx.deposit(Pg, Fg)
         assert_fields(F, Fg.cpu().numpy(), range(18, 21), what=f"edge deposit {step}")
+        Ph, Fh = up(P0), up({"F": F0})["F"]
+        ctx.push_deposit(Fh, Ph)
+        assert_particles(prm, P, down(Ph), what=f"edge fused step {step}")
+        assert_fields(F, Fh.cpu().numpy(), range(18, 21), what=f"edge fused deposit {step}")
         F[18:21] = 0.0
     assert (P["tag"][40:50] == 0).all()        # left through the inner boundary
     assert ((P["tag"][50:60] & 0x80) != 0).any() or (P["tag"][50:60] == 0).any()
