@@ -183,6 +183,25 @@ grpic_status grpic_deposit(grpic_ctx* ctx, const grpic_particles* P, const grpic
 grpic_status grpic_push_deposit(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,
                                 void* stream);
 
+/* Adjoint of one grpic_push step in a frozen field (the differentiation form;
+ * GRPIC_FP64 contexts only).  The particle state is s = (x1, x2, u1, u2, u3),
+ * x = cell + offset; the field set F holds B0 times a fixed field F1 (planes D
+ * and B0, as grpic_push reads them), B0 finite and non-zero.  For the step
+ * s' = Phi(s, B0) of Sec. 3.1 steps 2-10 with the particle boundaries of
+ * Sec. 3.3.3, starting from the state in P (as grpic_push would read it),
+ * computes per particle
+ *   gbar_out = (ds'/ds)^T gbar_in,   gbar_B0 += (ds'/dB0) . gbar_in.
+ * The implicit momentum and coordinate stages are differentiated at their
+ * fixed points (implicit-function theorem), so the forward pass must run its
+ * iterations to convergence (n_iter large enough; they stop at an exact
+ * repeat).  gbar_in, gbar_out: device arrays of 5 n doubles, rows x1, x2, u1,
+ * u2, u3 (row c at offset c n); they may be the same array.  gbar_B0: n
+ * doubles, accumulated.  Slots that the step does not move (empty, leaving,
+ * dropped) pass gbar through unchanged.  P is not modified. */
+grpic_status grpic_push_adjoint(grpic_ctx* ctx, const grpic_fields* F, double B0,
+                                const grpic_particles* P, const double* gbar_in, double* gbar_out,
+                                double* gbar_B0, void* stream);
+
 /* Field stages of the PIC loop (Sec. 3.4): stage GRPIC_FIELDS_PRE_PUSH or
  * GRPIC_FIELDS_POST_DEPOSIT (grpic_field_stage). */
 grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t stage,

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "grpic.h"
+#include "adjoint.hpp"
 #include "diag.hpp"
 #include "sort.hpp"
 
@@ -617,6 +618,25 @@ grpic_status grpic_push_deposit(grpic_ctx* c, const grpic_fields* F, const grpic
   if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
   if (P->n == 0) return GRPIC_OK;
   return push_deposit_impl(c, F, P, S(stream));
+}
+
+grpic_status grpic_push_adjoint(grpic_ctx* c, const grpic_fields* F, double B0, const grpic_particles* P,
+                                const double* gbar_in, double* gbar_out, double* gbar_B0, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
+  if (c->f32) return fail(GRPIC_ESTATE, "the adjoint needs a GRPIC_FP64 context");
+  if (!(B0 != 0.0 && std::isfinite(B0))) return fail(GRPIC_EINVAL, "B0 must be finite and non-zero");
+  if (P->n == 0) return GRPIC_OK;
+  if (!gbar_in || !gbar_out || !gbar_B0) return fail(GRPIC_EINVAL, "null adjoint array");
+  GatherPlanesT<double> gp;
+  for (int k = 0; k < 3; ++k) {
+    gp.D[k] = (const double*)F->D[k];
+    gp.B[k] = (const double*)F->B0[k];
+  }
+  hipLaunchKernelGGL(push_adjoint_kernel, dim3((unsigned)((P->n + 63) / 64)), dim3(64), 0, S(stream), c->g, gp,
+                     1.0 / B0, arrays<double>(P), gbar_in, gbar_out, gbar_B0);
+  LAUNCH_CHECK("push_adjoint");
+  return GRPIC_OK;
 }
 
 grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst,

@@ -78,6 +78,8 @@ _sigs = {
     "grpic_push": ([c_void_p, _F, _PP, c_void_p], c_int32),
     "grpic_deposit": ([c_void_p, _PP, _F, c_void_p], c_int32),
     "grpic_push_deposit": ([c_void_p, _F, _PP, c_void_p], c_int32),
+    "grpic_push_adjoint": ([c_void_p, _F, c_double, _PP, c_void_p, c_void_p, c_void_p, c_void_p],
+                           c_int32),
     "grpic_field_advance": ([c_void_p, _F, c_int32, c_void_p], c_int32),
     "grpic_sort": ([c_void_p, _PP, _PP, POINTER(c_int64), c_void_p], c_int32),
     "grpic_diagnostics": ([c_void_p, _F, _PP, c_double, POINTER(Diag), c_void_p, c_void_p,
@@ -214,6 +216,21 @@ class Context:
         _check(_lib.grpic_push_deposit(self._h, ctypes.byref(self._fields(F)),
                                        ctypes.byref(self._particles(P)), _stream()),
                "grpic_push_deposit")
+
+    def push_adjoint(self, F: torch.Tensor, B0: float, P: dict, gbar_in: torch.Tensor,
+                     gbar_out: torch.Tensor, gbar_B0: torch.Tensor):
+        """gbar_out = (ds'/ds)^T gbar_in, gbar_B0 += (ds'/dB0) . gbar_in for one
+        push step from state P in the frozen field F = B0 F1 (see grpic.h)."""
+        n = P["tag"].numel()
+        for t, shape in ((gbar_in, (5, n)), (gbar_out, (5, n)), (gbar_B0, (n,))):
+            if t.shape != shape or t.dtype != torch.float64 or not t.is_contiguous() or \
+                    not t.is_cuda:
+                raise GrpicError(f"adjoint arrays must be contiguous GPU float64 of shape {shape}")
+        _check(_lib.grpic_push_adjoint(self._h, ctypes.byref(self._fields(F)), B0,
+                                       ctypes.byref(self._particles(P)),
+                                       c_void_p(gbar_in.data_ptr()), c_void_p(gbar_out.data_ptr()),
+                                       c_void_p(gbar_B0.data_ptr()), _stream()),
+               "grpic_push_adjoint")
 
     def field_advance(self, F: torch.Tensor, stage: int):
         _check(_lib.grpic_field_advance(self._h, ctypes.byref(self._fields(F)), stage, _stream()),

@@ -18,9 +18,13 @@ name      a      grid    r_max      particles                             steps 
 c1_64     0.9    64^2    20         1e5 (5e4 pairs), T = 0.1, B0 = 1      10     FP64
 c2_512    0.9    512^2   50         16 ppc + 1e3 neutral geodesics, T=1   100    FP64
 c3_2048   0.99   2048^2  100        32 ppc, T = 1, B0 = 10                100    FP32 vs FP64
-c4_256    0.9    256^2   20         1e6, T = 1, frozen Wald, B0 learnable 50     adjoint
+c4_256    0.9    256^2   20         1e6, T = 1, frozen Wald, B0 learnable 50     adjoint (*)
 c5_4096   0.95   4096^2  200        16 ppc (pairs), T = 1, B0 = 10        200    FP32 full step
 ========  =====  ======  =========  ====================================  =====  =========
+
+(*) the differentiation form runs the implicit iterations to their fixed
+points (up to 30 iterations, stopping at an exact repeat), as its
+implicit-function-theorem adjoint assumes.
 """
 from __future__ import annotations
 
@@ -90,7 +94,8 @@ WORKLOADS = {
                         n_pairs=0, ppc=32, n_geo=0, steps=100, precision="fp32",
                         full_step=True),
     "c4_256": Workload("c4_256", a=0.9, n_r=256, n_th=256, r_max=20.0, B0=1.0, T=1.0,
-                       n_pairs=500_000, ppc=0, n_geo=0, steps=50, precision="fp64"),
+                       n_pairs=500_000, ppc=0, n_geo=0, steps=50, precision="fp64",
+                       n_iter=30),
     "c5_4096": Workload("c5_4096", a=0.95, n_r=4096, n_th=4096, r_max=200.0, B0=10.0, T=1.0,
                         n_pairs=0, ppc=16, n_geo=0, steps=200, precision="fp32",
                         n_filter=4, n_absorb=32, full_step=True),

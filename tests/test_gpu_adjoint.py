@@ -1,0 +1,152 @@
+"""The differentiation form on the GPU: grpic_push_adjoint behind
+paper_2511_17701_amd.adjoint.FrozenFieldPush, against the reference gradient
+(oracle/adjoint.py, autograd of a plain FP64 restatement of the step) and
+against central differences (h = 1e-6) of the GPU forward pass.
+
+Loss: mean final u_r (physical radial covariant momentum) after the push
+steps of the frozen-field workload (a = 0.9, Wald B0 = 1, Maxwell-Juttner
+T = 1); gradients with respect to the initial momenta and B0.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_17701_amd import grpic
+    torch.cuda.set_device(0)
+    return grpic
+
+
+def setup(O, G, n, n_pairs, seed=7):
+    import torch
+    from paper_2511_17701_amd.workloads import WORKLOADS
+    w = WORKLOADS["c4_256"]
+    if n:
+        w = w.scaled(n, n)
+    ctx = G.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, cfl=w.cfl, n_iter=w.n_iter,
+                    small_angle=w.small_angle)
+    F1 = ctx.new_fields()
+    ctx.fields_init_wald(F1, 1.0)
+    P = ctx.new_particles(2 * n_pairs)
+    ctx.particles_init(P, n_pairs, 0, w.T, 0, seed)
+    P["tag"][::7] = 3                           # some neutral particles
+    torch.cuda.synchronize()
+    return w, ctx, F1, P
+
+
+def loss_of(w, out):
+    import torch
+    dxi = math.log(w.r_max / w.r_min) / w.n_r
+    return (out[:, 2] / (dxi * w.r_min * torch.exp(out[:, 0] * dxi))).mean()
+
+
+def gpu_gradients(w, ctx, F1, P, steps, every=10):
+    import torch
+    from paper_2511_17701_amd.adjoint import FrozenFieldPush, FrozenRun
+    u0 = torch.stack([P["u1"], P["u2"], P["u3"]], 1).clone().requires_grad_(True)
+    B0 = torch.tensor(w.B0, dtype=torch.float64, requires_grad=True)
+    run = FrozenRun(ctx, F1, P, steps, every)
+    out = FrozenFieldPush.apply(u0, B0, run)
+    loss = loss_of(w, out)
+    loss.backward()
+    return loss.item(), u0.grad, B0.grad.item(), run.stats["gB0_per_particle"], out.detach()
+
+
+def test_adjoint_matches_reference_gradient(O, G):
+    """Per-particle d(loss)/d(u0) and per-particle B0 contributions against
+    autograd of the oracle restatement (24^2 grid, 12 steps, checkpoints
+    every 5 steps so that the replay crosses segment boundaries)."""
+    import torch
+    import oracle.adjoint as A
+    w, ctx, F1, P = setup(O, G, 24, 400)
+    steps = 12
+    loss, gu, gB0, gB0_pp, out = gpu_gradients(w, ctx, F1, P, steps, every=5)
+    prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, ctx.dt, n_iter=w.n_iter)
+    Ph = {k: v.cpu().numpy() for k, v in P.items()}
+    st = A.state_from(Ph)
+    F1o = torch.from_numpy(O.fields_init_wald(prm, 1.0))
+    loss_o, gu_o, gB0_o, fin = A.gradients(prm, F1o, w.B0, st, steps)
+    assert abs(loss - loss_o) <= 1e-12 * abs(loss_o)
+    g, go = gu.cpu().numpy(), gu_o.numpy()
+    scale = np.abs(go).max(axis=1) + 1e-300
+    err = np.abs(g - go).max(axis=1) / scale
+    print(f"\n[adjoint vs reference] per-particle rel err: median {np.median(err):.3g} "
+          f"p99 {np.quantile(err, 0.99):.3g} max {err.max():.3g}; "
+          f"dL/dB0 {gB0:.12g} vs {gB0_o:.12g}")
+    assert np.quantile(err, 0.99) <= 1e-9
+    assert abs(gB0 - gB0_o) <= 1e-9 * abs(gB0_o)
+    # the final states of both forward passes agree
+    x1o = fin["i1"].double() + fin["dx1"]
+    assert (out[:, 0].cpu() - x1o).abs().max() <= 1e-10
+
+
+def cell_hash(P):
+    import torch
+    return (P["i1"].long() * 1000003 + P["i2"].long() * 7919 + (P["dx1"] >= 0.5).long() * 3 +
+            (P["dx2"] >= 0.5).long() * 5 + P["tag"].long() * 11)
+
+
+def forward_loss(w, ctx, F1, P, u0, B0, steps):
+    """GPU forward pass; returns per-particle final u_r and a running hash of
+    the visited (cell, half-cell) sequence."""
+    import torch
+    from paper_2511_17701_amd.adjoint import final_state
+    Q = {k: v.clone() for k, v in P.items()}
+    Q["u1"], Q["u2"], Q["u3"] = (u0[:, c].contiguous().clone() for c in range(3))
+    F = F1 * B0
+    h = torch.zeros_like(Q["i1"], dtype=torch.int64)
+    for s in range(steps):
+        ctx.push(F, Q)
+        h = h * 31 + cell_hash(Q)
+    out = final_state(Q)
+    dxi = math.log(w.r_max / w.r_min) / w.n_r
+    return out[:, 2] / (dxi * w.r_min * torch.exp(out[:, 0] * dxi)), h
+
+
+def test_adjoint_c4_against_central_differences(O, G):
+    """The C4 workload at full size (256^2, 1e6 particles, 50 steps,
+    checkpoints every 10): adjoint gradients against central differences
+    (h = 1e-6) of the GPU forward pass -- per particle for u0 on the particles
+    whose perturbed trajectories keep their cell sequence, and for B0."""
+    import torch
+    from paper_2511_17701_amd.workloads import WORKLOADS
+    wl = WORKLOADS["c4_256"]
+    w, ctx, F1, P = setup(O, G, None, wl.n_pairs)
+    n = P["tag"].numel()
+    loss, gu, gB0, _, _ = gpu_gradients(w, ctx, F1, P, w.steps, every=10)
+    h = 1e-6
+    u0 = torch.stack([P["u1"], P["u2"], P["u3"]], 1)
+    base_ur, base_h = forward_loss(w, ctx, F1, P, u0, w.B0, w.steps)
+    keep = torch.ones(n, dtype=torch.bool, device=u0.device)
+    fd = torch.zeros_like(u0)
+    for c in range(3):
+        urs = []
+        for sgn in (1, -1):
+            up = u0.clone()
+            up[:, c] += sgn * h
+            ur, hh = forward_loss(w, ctx, F1, P, up, w.B0, w.steps)
+            keep &= hh == base_h
+            urs.append(ur)
+        fd[:, c] = (urs[0] - urs[1]) / (2 * h) / n
+    scale = gu.abs().max(dim=1).values + 1e-300
+    err = ((gu - fd).abs().max(dim=1).values / scale)[keep]
+    frac = keep.double().mean().item()
+    # dL/dB0 over all particles (the loss is continuous; kinks only change slopes)
+    lp, _ = forward_loss(w, ctx, F1, P, u0, w.B0 + h, w.steps)
+    lm, _ = forward_loss(w, ctx, F1, P, u0, w.B0 - h, w.steps)
+    fd_b = ((lp - lm) / (2 * h)).mean().item()
+    print(f"\n[C4 adjoint vs FD] loss {loss:.12g}; kept {frac:.4f} of {n}; per-particle rel err "
+          f"median {err.median().item():.3g} p99 {err.quantile(0.99).item():.3g} "
+          f"max {err.max().item():.3g}; dL/dB0 {gB0:.12g} vs FD {fd_b:.12g} "
+          f"(rel {abs(gB0 - fd_b) / abs(fd_b):.3g})")
+    assert frac > 0.9
+    assert err.quantile(0.999).item() <= 1e-6
+    assert abs(gB0 - fd_b) <= 1e-6 * abs(fd_b)

@@ -1,0 +1,155 @@
+"""Pins of the reference gradient (oracle/adjoint.py) of the frozen-field push.
+
+1. Its forward map is the C oracle's push: same states after several steps
+   (charged and neutral particles, axis reflection, removal).
+2. Its derivatives are the derivatives of the C oracle's map: central
+   differences (h = 1e-6) of the C oracle for d(final u_r)/d(initial u_i) per
+   particle and for d(mean u_r)/dB0, on the particles whose perturbed
+   trajectories visit the same cells and half-cells (the gather is piecewise
+   bilinear, so a trajectory that crosses a cell or half-cell edge under the
+   perturbation sees a kink).
+3. Special cases fixed by the mathematics: a neutral particle's gradient with
+   respect to B0 is zero; in flat space (M = a = 0) with B0 = 0 the update is
+   free motion, whose u_3 = u_phi is conserved, so d(final u_3)/d(u_3) = 1 and
+   d(final u_3)/d(u_1) = 0 (to the rounding of the tetrad round trip).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2511_17701_amd.workloads import WORKLOADS
+
+
+def params(O, n=24, n_iter=30, **kw):
+    w = WORKLOADS["c4_256"].scaled(n, n)
+    prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, n, n, 0.0, n_iter=n_iter, **kw)
+    prm.dt = O.courant_dt(prm, 0.5)
+    return prm, w
+
+
+def particles(O, prm, n_pairs, seed, T=1.0):
+    P = O.particles_init(prm, n_pairs, 0, T, 0, seed)
+    P["tag"][::7] = 3            # some neutral particles
+    return P
+
+
+def c_run(O, prm, F, P, steps):
+    P = {k: v.copy() for k, v in P.items()}
+    cells = []
+    for _ in range(steps):
+        O.push(prm, F, P)
+        cells.append(np.stack([P["i1"], P["i2"], P["dx1"] >= 0.5, P["dx2"] >= 0.5,
+                               P["tag"]]).astype(np.int64))
+    return P, np.stack(cells)
+
+
+def c_ur(prm, P):
+    dxi = math.log(prm.r_max / prm.r_min) / prm.n_r
+    return P["u1"] / (dxi * prm.r_min * np.exp((P["i1"] + P["dx1"]) * dxi))
+
+
+def test_forward_is_the_c_oracle_push(O):
+    import oracle.adjoint as A
+    prm, w = params(O, n_iter=10)
+    F = O.fields_init_wald(prm, w.B0)
+    P = particles(O, prm, 3000, 5)
+    # a few particles next to each axis and the radial edges
+    P["i2"][:20] = 0
+    P["dx2"][:20] = 0.02
+    P["i2"][20:40] = prm.n_th - 1
+    P["dx2"][20:40] = 0.98
+    P["i1"][40:60] = 0
+    P["dx1"][40:60] = 0.05
+    P["u1"][40:60] = -abs(P["u1"][40:60]) - 0.5
+    st = A.state_from(P)
+    F1 = torch.from_numpy(O.fields_init_wald(prm, 1.0))
+    Pc = {k: v.copy() for k, v in P.items()}
+    for s in range(4):
+        st = A.step(prm, F1, torch.tensor(w.B0, dtype=torch.float64), st)
+        O.push(prm, F, Pc)
+        live = (Pc["tag"] != 0) & ((Pc["tag"] & 0x80) == 0)
+        np.testing.assert_array_equal(st["live"].numpy(), live, err_msg=f"step {s}")
+        moved = st["live"].numpy() | ((Pc["tag"] & 0x80) != 0)
+        for k in ("i1", "i2"):
+            np.testing.assert_array_equal(st[k].numpy()[moved], Pc[k][moved], err_msg=k)
+        for k in ("dx1", "dx2", "u1", "u2", "u3"):
+            a, b = st[k].detach().numpy()[moved], Pc[k][moved]
+            err = np.abs(a - b) / np.maximum(np.abs(b), 1e-3)
+            assert err.max() <= 1e-12, (s, k, err.max())
+    assert (P["i2"][:20] == 0).all()
+
+
+def test_gradients_match_central_differences_of_the_c_oracle(O):
+    import oracle.adjoint as A
+    prm, w = params(O)
+    steps, h = 6, 1e-6
+    F = O.fields_init_wald(prm, w.B0)
+    P = particles(O, prm, 150, 11)
+    n = len(P["tag"])
+    st = A.state_from(P)
+    F1 = torch.from_numpy(O.fields_init_wald(prm, 1.0))
+    loss, gu, gB0, _ = A.gradients(prm, F1, w.B0, st, steps)
+    _, ref_cells = c_run(O, prm, F, P, steps)
+    same = np.ones(n, bool)
+    fd = np.zeros((n, 3))
+    for c, k in enumerate(("u1", "u2", "u3")):
+        out = []
+        for sgn in (1, -1):
+            Q = {kk: v.copy() for kk, v in P.items()}
+            Q[k] = Q[k] + sgn * h
+            Qf, cells = c_run(O, prm, F, Q, steps)
+            same &= (cells == ref_cells).all(axis=(0, 1))
+            out.append(c_ur(prm, Qf))
+        fd[:, c] = (out[0] - out[1]) / (2 * h) / n
+    g = gu.numpy()
+    scale = np.abs(g).max(axis=1, keepdims=True) + 1e-30
+    err = np.abs(g - fd) / scale
+    assert same.mean() > 0.6, same.mean()
+    assert err[same].max() <= 1e-6, err[same].max()
+    # dL/dB0 on the particles that keep their cell sequence
+    outs = []
+    for sgn in (1, -1):
+        Fb = O.fields_init_wald(prm, w.B0 + sgn * h)
+        Qf, cells = c_run(O, prm, Fb, P, steps)
+        same_b = (cells == ref_cells).all(axis=(0, 1))
+        outs.append((c_ur(prm, Qf), same_b))
+    keep = same & outs[0][1] & outs[1][1]
+    fd_b = ((outs[0][0] - outs[1][0]) / (2 * h))[keep].sum() / n
+    # the same partial sum from autograd: per-particle B0 derivatives
+    st2 = A.state_from(P)
+    u0 = [st2[k].clone() for k in ("u1", "u2", "u3")]
+    b0 = torch.tensor(w.B0, dtype=torch.float64, requires_grad=True)
+    st2["u1"], st2["u2"], st2["u3"] = u0
+    fin = A.run(prm, F1, b0, st2, steps)
+    ur = A.u_r(prm, fin)
+    part = torch.autograd.grad(ur[torch.from_numpy(keep)].sum() / n, b0)[0].item()
+    assert abs(part - fd_b) <= 1e-6 * max(abs(fd_b), 1e-3), (part, fd_b)
+    assert np.isfinite(gB0) and np.isfinite(loss)
+
+
+def test_special_cases(O):
+    import oracle.adjoint as A
+    # neutral particles: no dependence on the field amplitude
+    prm, w = params(O)
+    P = particles(O, prm, 40, 2)
+    P["tag"][:] = 3
+    st = A.state_from(P)
+    F1 = torch.from_numpy(O.fields_init_wald(prm, 1.0))
+    _, _, gB0, _ = A.gradients(prm, F1, w.B0, st, 4)
+    assert gB0 == 0.0
+    # flat space, no field: u_phi is conserved exactly by the update
+    flat = O.Params.make(0.0, 0.0, 1.0, 20.0, 24, 24, 0.0, n_iter=30)
+    flat.dt = O.courant_dt(flat, 0.5)
+    P = O.particles_init(flat, 40, 0, 1.0, 0, 3)
+    st = A.state_from(P)
+    F1 = torch.from_numpy(O.fields_init_wald(flat, 1.0))
+    u0 = [st[k].clone().requires_grad_(True) for k in ("u1", "u2", "u3")]
+    st["u1"], st["u2"], st["u3"] = u0
+    fin = A.run(flat, F1, torch.tensor(0.0, dtype=torch.float64), st, 5)
+    live = fin["live"]
+    g = torch.autograd.grad(fin["u3"][live].sum(), u0)
+    assert live.sum() > 20
+    assert (g[2][live] - 1.0).abs().max() <= 1e-13   # exact up to the tetrad round trip
+    assert g[0][live].abs().max() <= 1e-13
