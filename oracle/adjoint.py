@@ -13,10 +13,11 @@ for automatic differentiation:
     taken by torch.autograd with create_graph, so the gradient of the step
     sees second derivatives of the metric without any hand-derived formula;
   - the two implicit-midpoint iterations (eq. discretized-geodesic-u and
-    eq. discretized-geodesic-x) run their fixed number of iterations and are
-    differentiated unrolled, which is the exact derivative of the discrete
-    map (and equals the implicit-function-theorem derivative once the
-    iterations have converged);
+    eq. discretized-geodesic-x) run their fixed number of iterations, or stop
+    once every iterate repeats exactly (the fixed point: the same values as
+    further iterations), and are differentiated unrolled, which is the exact
+    derivative of the discrete map (and equals the implicit-function-theorem
+    derivative once the iterations have converged);
   - positions are (int cell, FP64 offset) pairs as in the C oracle; the
     integer shift of a renormalisation carries no derivative;
   - the polar angle is clamped at small_angle in metric evaluations (a
@@ -165,8 +166,11 @@ def geodesic_momentum(p, m, u):
             quad = (m["dhu11"][i] * ub1 * ub1 + m["dhu22"][i] * ub2 * ub2 +
                     m["dhu33"][i] * u3 * u3 + 2.0 * m["dhu13"][i] * ub1 * u3)
             f.append(-gb * m["dalpha"][i] + ub1 * m["dbeta1"][i] - m["alpha"] / (2.0 * gb) * quad)
-        ut1 = us1 + p.dt * f[0]
-        ut2 = us2 + p.dt * f[1]
+        n1, n2 = us1 + p.dt * f[0], us2 + p.dt * f[1]
+        done = torch.equal(n1, ut1) and torch.equal(n2, ut2)
+        ut1, ut2 = n1, n2
+        if done:   # every iterate repeats: the fixed point (same values as more iterations)
+            break
     return [ut1, ut2, u3]
 
 
@@ -211,7 +215,11 @@ def step(p, F1, B0, st):
     for _ in range(p.n_iter):
         mb = metric(p, x1 + 0.5 * d1, x2 + 0.5 * d2)
         v1, v2 = velocity(mb, u)
-        d1, d2 = p.dt * v1, p.dt * v2
+        n1, n2 = p.dt * v1, p.dt * v2
+        done = torch.equal(n1, d1) and torch.equal(n2, d2)
+        d1, d2 = n1, n2
+        if done:
+            break
     n1, ndx1 = _renorm(i1, dx1 + d1)
     n2, ndx2 = _renorm(i2, dx2 + d2)
     # axis reflection (Sec. 3.3.3)

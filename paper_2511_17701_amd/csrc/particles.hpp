@@ -681,25 +681,6 @@ __device__ inline bool make_contrib(const Grid& g, const Tables& tab, const Move
   return true;
 }
 
-// Adds a contribution through `add(component, i, j, value)` (absolute node indices).
-template <class T, class Add>
-__device__ inline void scatter(const ContribT<T>& c, Add add) {
-  const int ia = c.ia, ja = c.ja, ib = c.ia + c.di, jb = c.ja + c.dj;
-  add(0, ia, ja, c.j1[0]);
-  add(0, ia, ja + 1, c.j1[1]);
-  add(0, ib, jb, c.j1[2]);
-  add(0, ib, jb + 1, c.j1[3]);
-  add(1, ia, ja, c.j2[0]);
-  add(1, ia + 1, ja, c.j2[1]);
-  add(1, ib, jb, c.j2[2]);
-  add(1, ib + 1, jb, c.j2[3]);
-  const int km = ia + c.km, lm = ja + c.lm;
-  add(2, km, lm, c.j3[0]);
-  add(2, km, lm + 1, c.j3[1]);
-  add(2, km + 1, lm, c.j3[2]);
-  add(2, km + 1, lm + 1, c.j3[3]);
-}
-
 // Runs of equal keys in consecutive lanes of a wavefront: `end` is the last
 // lane of this lane's run, `head` marks the first lane of a run; `longest` is
 // the longest run (wave-uniform).
@@ -741,14 +722,56 @@ __device__ inline T run_sum(T v, const Runs& r) {
   return v;
 }
 
+// Adds the contributions of the lanes of a wavefront through add(comp, i, j,
+// value) (absolute node indices).  Particles are cell-sorted, so lanes share
+// cells: the contributions of a run of lanes with the same cell are summed
+// across lanes first and the run's first lane adds them (atomics from many
+// lanes on one address would serialise).  Every lane of the wavefront must
+// call this (inactive lanes with act = false).
+template <class T, class Add>
+__device__ inline void add_runs(const Grid& g, bool act, const ContribT<T>& c, Add add) {
+  const T z = (T)0;
+  // segment 1 (previous cell), with segment 2 folded in when the particle stays in its cell
+  const bool stay = act && c.di == 0 && c.dj == 0;
+  const Runs sa = runs_of(act ? (c.ia + 2) * g.ld + (c.ja + 2) : -1);
+  const T a0 = run_sum(act ? c.j1[0] + (stay ? c.j1[2] : z) : z, sa);
+  const T a1 = run_sum(act ? c.j1[1] + (stay ? c.j1[3] : z) : z, sa);
+  const T a2 = run_sum(act ? c.j2[0] + (stay ? c.j2[2] : z) : z, sa);
+  const T a3 = run_sum(act ? c.j2[1] + (stay ? c.j2[3] : z) : z, sa);
+  // J^3 nodes around the path midpoint
+  const int km = c.ia + c.km, lm = c.ja + c.lm;
+  const Runs sm = runs_of(act ? (km + 2) * g.ld + (lm + 2) : -1);
+  const T m0 = run_sum(act ? c.j3[0] : z, sm);
+  const T m1 = run_sum(act ? c.j3[1] : z, sm);
+  const T m2 = run_sum(act ? c.j3[2] : z, sm);
+  const T m3 = run_sum(act ? c.j3[3] : z, sm);
+  if (act && sa.head) {
+    add(0, c.ia, c.ja, a0);
+    add(0, c.ia, c.ja + 1, a1);
+    add(1, c.ia, c.ja, a2);
+    add(1, c.ia + 1, c.ja, a3);
+  }
+  if (act && !stay) {  // segment 2 in the new cell
+    const int ib = c.ia + c.di, jb = c.ja + c.dj;
+    add(0, ib, jb, c.j1[2]);
+    add(0, ib, jb + 1, c.j1[3]);
+    add(1, ib, jb, c.j2[2]);
+    add(1, ib + 1, jb, c.j2[3]);
+  }
+  if (act && sm.head) {
+    add(2, km, lm, m0);
+    add(2, km, lm + 1, m1);
+    add(2, km + 1, lm, m2);
+    add(2, km + 1, lm + 1, m3);
+  }
+}
+
 // Block-level deposit: the 4 x 4 footprints of the block's particles are
 // accumulated in an LDS tile, then added to the planes with one global atomic
-// per touched node.  Particles are cell-sorted, so lanes of a wavefront share
-// cells: contributions of a run of lanes with the same cell are summed across
-// lanes first (one LDS atomic per run and node instead of one per lane, which
-// would serialise on the shared address).  A block whose footprint does not
-// fit the tile adds straight to the planes.  Every lane of the block must call
-// this.
+// per touched node.  A block whose footprint does not fit the tile (its cells
+// wrap from the end of one theta row to the next, or its particles have
+// spread) adds the run sums straight to the planes.  Every lane of the block
+// must call this.
 template <class T>
 __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp, bool act,
                                      const ContribT<T>& c) {
@@ -777,49 +800,14 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
   if (i0 == INT_MAX) return;  // no live charged particle in this block (uniform)
   const bool fits = (i1 - i0 < kTI) && (j1 - j0 < kTJ);
   if (!fits) {
-    if (act)
-      scatter(c, [&](int comp, int i, int j, T val) { atomic_add(cp.J[comp] + ix(g, i, j), val); });
+    add_runs(g, act, c, [&](int comp, int i, int j, T val) { atomic_add(cp.J[comp] + ix(g, i, j), val); });
     return;
   }
-  const T z = (T)0;
-  // segment 1 (previous cell), with segment 2 folded in when the particle stays in its cell
-  const bool stay = act && c.di == 0 && c.dj == 0;
-  const int ra = c.ia - i0, ca = c.ja - j0;
-  const Runs sa = runs_of(act ? ra * kTJ + ca : -1);
-  const T a0 = run_sum(act ? c.j1[0] + (stay ? c.j1[2] : z) : z, sa);
-  const T a1 = run_sum(act ? c.j1[1] + (stay ? c.j1[3] : z) : z, sa);
-  const T a2 = run_sum(act ? c.j2[0] + (stay ? c.j2[2] : z) : z, sa);
-  const T a3 = run_sum(act ? c.j2[1] + (stay ? c.j2[3] : z) : z, sa);
-  // J^3 nodes around the path midpoint
-  const int rm = ra + c.km, cm = ca + c.lm;
-  const Runs sm = runs_of(act ? rm * kTJ + cm : -1);
-  const T m0 = run_sum(act ? c.j3[0] : z, sm);
-  const T m1 = run_sum(act ? c.j3[1] : z, sm);
-  const T m2 = run_sum(act ? c.j3[2] : z, sm);
-  const T m3 = run_sum(act ? c.j3[3] : z, sm);
-  if (act && sa.head) {
-    atomicAdd(&tile[0][ra][ca], a0);
-    atomicAdd(&tile[0][ra][ca + 1], a1);
-    atomicAdd(&tile[1][ra][ca], a2);
-    atomicAdd(&tile[1][ra + 1][ca], a3);
-  }
-  if (act && !stay) {  // segment 2 in the new cell
-    const int rb = ra + c.di, cb = ca + c.dj;
-    atomicAdd(&tile[0][rb][cb], c.j1[2]);
-    atomicAdd(&tile[0][rb][cb + 1], c.j1[3]);
-    atomicAdd(&tile[1][rb][cb], c.j2[2]);
-    atomicAdd(&tile[1][rb + 1][cb], c.j2[3]);
-  }
-  if (act && sm.head) {
-    atomicAdd(&tile[2][rm][cm], m0);
-    atomicAdd(&tile[2][rm][cm + 1], m1);
-    atomicAdd(&tile[2][rm + 1][cm], m2);
-    atomicAdd(&tile[2][rm + 1][cm + 1], m3);
-  }
+  add_runs(g, act, c, [&](int comp, int i, int j, T val) { atomicAdd(&tile[comp][i - i0][j - j0], val); });
   __syncthreads();
   for (int e = threadIdx.x; e < 3 * kTI * kTJ; e += kDepBlock) {
     const T val = flat[e];
-    if (val != z) {
+    if (val != (T)0) {
       const int comp = e / (kTI * kTJ), rem = e % (kTI * kTJ);
       atomic_add(cp.J[comp] + ix(g, i0 + rem / kTJ, j0 + rem % kTJ), val);
     }
