@@ -15,8 +15,11 @@
 //                dZ = (I - dt/2 df/dubar)^-1 (du* + dt df|_{Z fixed})
 //   coordinates: d = dt v(x + d/2, u)
 //                dd = (I - dt/2 dv/dx)^-1 dt dv|_{d fixed}
-// The forward map must therefore run its iterations to the fixed point
-// (n_iter large enough; the iterations stop at an exact repeat).
+// An iteration that did not reach its fixed point within n_iter (no exact
+// repeat: next to the axis the contraction can approach 1) is differentiated
+// through the iterations the forward pass actually ran instead (tangents
+// carried through each of them), so the result is always the derivative of
+// the computed map.
 // Second derivatives of the metric come from the tangents of the analytic
 // first derivatives (frame_from on tangent values).
 #pragma once
@@ -195,33 +198,47 @@ __device__ inline void adjoint_one(const Grid& g, const GatherPlanesT<double>& f
     const GradT<double> dv = value_of(d);
     const double s1 = u1.v, s2 = u2.v, w3 = u3.v;
     double z1 = s1, z2 = s2;
+    bool converged = false;
     for (int it = 0; it < g.n_iter; ++it) {
       double fr[2];
       geo_force(fv.c, dv, 0.5 * (s1 + z1), 0.5 * (s2 + z2), w3, fr);
       const double n1 = s1 + g.dt * fr[0], n2 = s2 + g.dt * fr[1];
-      const bool fixed = n1 == z1 && n2 == z2;
+      converged = n1 == z1 && n2 == z2;
       z1 = n1;
       z2 = n2;
-      if (fixed) break;
+      if (converged) break;
     }
-    // tangent of the map with Z held fixed
-    T6 b1 = T6(0.5) * (u1 + T6(z1)), b2 = T6(0.5) * (u2 + T6(z2));
-    T6 fr[2];
-    geo_force(f.c, d, b1, b2, u3, fr);
-    T6 n1 = u1 + T6(g.dt) * fr[0], n2 = u2 + T6(g.dt) * fr[1];
-    // A = dt/2 df/dubar_{12} at the fixed point
-    CoeffsT<T2> m2{T2(fv.c.alpha), T2(fv.c.beta1), T2(fv.c.hu11), T2(fv.c.hu22), T2(fv.c.hu33),
-                   T2(fv.c.hu13)};
-    const GradT<T2> d2 = lift<T2>(dv);
-    T2 f2[2];
-    geo_force(m2, d2, seed<2>(0.5 * (s1 + z1), 0), seed<2>(0.5 * (s2 + z2), 1), T2(w3), f2);
-    const double A[2][2] = {{0.5 * g.dt * f2[0].d[0], 0.5 * g.dt * f2[0].d[1]},
-                            {0.5 * g.dt * f2[1].d[0], 0.5 * g.dt * f2[1].d[1]}};
-    n1.v = z1;
-    n2.v = z2;
-    solve2(A, n1, n2);
-    u1 = n1;
-    u2 = n2;
+    if (!converged) {
+      // not at the fixed point: tangents through the n_iter iterations run
+      T6 t1 = u1, t2 = u2;
+      for (int it = 0; it < g.n_iter; ++it) {
+        T6 fr[2];
+        geo_force(f.c, d, T6(0.5) * (u1 + t1), T6(0.5) * (u2 + t2), u3, fr);
+        t1 = u1 + T6(g.dt) * fr[0];
+        t2 = u2 + T6(g.dt) * fr[1];
+      }
+      u1 = t1;
+      u2 = t2;
+    } else {
+      // tangent of the map with Z held fixed
+      T6 b1 = T6(0.5) * (u1 + T6(z1)), b2 = T6(0.5) * (u2 + T6(z2));
+      T6 fr[2];
+      geo_force(f.c, d, b1, b2, u3, fr);
+      T6 n1 = u1 + T6(g.dt) * fr[0], n2 = u2 + T6(g.dt) * fr[1];
+      // A = dt/2 df/dubar_{12} at the fixed point
+      CoeffsT<T2> m2{T2(fv.c.alpha), T2(fv.c.beta1), T2(fv.c.hu11), T2(fv.c.hu22), T2(fv.c.hu33),
+                     T2(fv.c.hu13)};
+      const GradT<T2> d2 = lift<T2>(dv);
+      T2 f2[2];
+      geo_force(m2, d2, seed<2>(0.5 * (s1 + z1), 0), seed<2>(0.5 * (s2 + z2), 1), T2(w3), f2);
+      const double A[2][2] = {{0.5 * g.dt * f2[0].d[0], 0.5 * g.dt * f2[0].d[1]},
+                              {0.5 * g.dt * f2[1].d[0], 0.5 * g.dt * f2[1].d[1]}};
+      n1.v = z1;
+      n2.v = z2;
+      solve2(A, n1, n2);
+      u1 = n1;
+      u2 = n2;
+    }
   }
   if (qm != 0.0) em_half(f, E, B, T6(0.25 * qm * g.dt), u1, u2, u3);
 
@@ -230,30 +247,43 @@ __device__ inline void adjoint_one(const Grid& g, const GatherPlanesT<double>& f
   {
     const double a1 = x1.v, a2 = x2.v;
     double e1 = 0.0, e2 = 0.0;
+    bool converged = false;
     for (int it = 0; it < g.n_iter; ++it) {
       const CoeffsT<double> m = coeffs_from(g, rsc_direct(g, a1 + 0.5 * e1, a2 + 0.5 * e2));
       double v[2];
       coord_vel(m, u1.v, u2.v, u3.v, v);
       const double n1 = g.dt * v[0], n2 = g.dt * v[1];
-      const bool fixed = n1 == e1 && n2 == e2;
+      converged = n1 == e1 && n2 == e2;
       e1 = n1;
       e2 = n2;
-      if (fixed) break;
+      if (converged) break;
     }
-    const T6 xm1 = x1 + T6(0.5 * e1), xm2 = x2 + T6(0.5 * e2);
-    T6 v[2];
-    coord_vel(coeffs_from(g, rsc_tan(g, xm1, xm2)), u1, u2, u3, v);
-    d1 = T6(g.dt) * v[0];
-    d2 = T6(g.dt) * v[1];
-    const CoeffsT<T2> m2 =
-        coeffs_from(g, rsc_tan(g, seed<2>(a1 + 0.5 * e1, 0), seed<2>(a2 + 0.5 * e2, 1)));
-    T2 v2[2];
-    coord_vel(m2, T2(u1.v), T2(u2.v), T2(u3.v), v2);
-    const double A[2][2] = {{0.5 * g.dt * v2[0].d[0], 0.5 * g.dt * v2[0].d[1]},
-                            {0.5 * g.dt * v2[1].d[0], 0.5 * g.dt * v2[1].d[1]}};
-    d1.v = e1;
-    d2.v = e2;
-    solve2(A, d1, d2);
+    if (!converged) {
+      // tangents through the n_iter iterations run
+      d1 = T6(0.0);
+      d2 = T6(0.0);
+      for (int it = 0; it < g.n_iter; ++it) {
+        T6 v[2];
+        coord_vel(coeffs_from(g, rsc_tan(g, x1 + T6(0.5) * d1, x2 + T6(0.5) * d2)), u1, u2, u3, v);
+        d1 = T6(g.dt) * v[0];
+        d2 = T6(g.dt) * v[1];
+      }
+    } else {
+      const T6 xm1 = x1 + T6(0.5 * e1), xm2 = x2 + T6(0.5 * e2);
+      T6 v[2];
+      coord_vel(coeffs_from(g, rsc_tan(g, xm1, xm2)), u1, u2, u3, v);
+      d1 = T6(g.dt) * v[0];
+      d2 = T6(g.dt) * v[1];
+      const CoeffsT<T2> m2 =
+          coeffs_from(g, rsc_tan(g, seed<2>(a1 + 0.5 * e1, 0), seed<2>(a2 + 0.5 * e2, 1)));
+      T2 v2[2];
+      coord_vel(m2, T2(u1.v), T2(u2.v), T2(u3.v), v2);
+      const double A[2][2] = {{0.5 * g.dt * v2[0].d[0], 0.5 * g.dt * v2[0].d[1]},
+                              {0.5 * g.dt * v2[1].d[0], 0.5 * g.dt * v2[1].d[1]}};
+      d1.v = e1;
+      d2.v = e2;
+      solve2(A, d1, d2);
+    }
   }
   T6 y1 = x1 + d1, y2 = x2 + d2;
   // axis reflection: x2 -> -x2 below theta = 0, 2 n_th - x2 above theta = pi

@@ -89,33 +89,42 @@ def test_adjoint_matches_reference_gradient(O, G):
 
 
 def cell_hash(P):
-    import torch
+    """Cell, half-cell, tag (removal) and the sign of u_2 (an axis reflection
+    flips it) after a step."""
     return (P["i1"].long() * 1000003 + P["i2"].long() * 7919 + (P["dx1"] >= 0.5).long() * 3 +
-            (P["dx2"] >= 0.5).long() * 5 + P["tag"].long() * 11)
+            (P["dx2"] >= 0.5).long() * 5 + P["tag"].long() * 11 + (P["u2"] > 0).long() * 13)
 
 
 def forward_loss(w, ctx, F1, P, u0, B0, steps):
-    """GPU forward pass; returns per-particle final u_r and a running hash of
-    the visited (cell, half-cell) sequence."""
+    """GPU forward pass; returns per-particle final u_r, a running hash of the
+    visited (cell, half-cell) sequence, removals and axis reflections, and
+    whether the trajectory entered a cell row next to an axis."""
     import torch
     from paper_2511_17701_amd.adjoint import final_state
     Q = {k: v.clone() for k, v in P.items()}
     Q["u1"], Q["u2"], Q["u3"] = (u0[:, c].contiguous().clone() for c in range(3))
     F = F1 * B0
     h = torch.zeros_like(Q["i1"], dtype=torch.int64)
+    axis = (Q["i2"] == 0) | (Q["i2"] == w.n_th - 1)
     for s in range(steps):
         ctx.push(F, Q)
         h = h * 31 + cell_hash(Q)
+        axis |= (Q["i2"] == 0) | (Q["i2"] == w.n_th - 1)
     out = final_state(Q)
     dxi = math.log(w.r_max / w.r_min) / w.n_r
-    return out[:, 2] / (dxi * w.r_min * torch.exp(out[:, 0] * dxi)), h
+    return out[:, 2] / (dxi * w.r_min * torch.exp(out[:, 0] * dxi)), h, axis
 
 
 def test_adjoint_c4_against_central_differences(O, G):
     """The C4 workload at full size (256^2, 1e6 particles, 50 steps,
     checkpoints every 10): adjoint gradients against central differences
-    (h = 1e-6) of the GPU forward pass -- per particle for u0 on the particles
-    whose perturbed trajectories keep their cell sequence, and for B0."""
+    (h = 1e-6) of the GPU forward pass, per particle for u0 and summed for B0,
+    on the particles whose perturbed trajectories keep their cell sequence and
+    their removal and reflection events and stay clear of the cell rows next
+    to the axes.  (Passages through those rows make the implicit iterations
+    converge slowly, and the computed map carries ~1e-10 noise there, which
+    central differences at h = 1e-6 turn into ~1e-4 relative scatter; those
+    particles are compared exactly against the reference gradient above.)"""
     import torch
     from paper_2511_17701_amd.workloads import WORKLOADS
     wl = WORKLOADS["c4_256"]
@@ -124,33 +133,34 @@ def test_adjoint_c4_against_central_differences(O, G):
     loss, gu, gB0, gB0_pp, _ = gpu_gradients(w, ctx, F1, P, w.steps, every=10)
     h = 1e-6
     u0 = torch.stack([P["u1"], P["u2"], P["u3"]], 1)
-    base_ur, base_h = forward_loss(w, ctx, F1, P, u0, w.B0, w.steps)
-    keep = torch.ones(n, dtype=torch.bool, device=u0.device)
+    base_ur, base_h, axis = forward_loss(w, ctx, F1, P, u0, w.B0, w.steps)
+    keep = ~axis
     fd = torch.zeros_like(u0)
     for c in range(3):
         urs = []
         for sgn in (1, -1):
             up = u0.clone()
             up[:, c] += sgn * h
-            ur, hh = forward_loss(w, ctx, F1, P, up, w.B0, w.steps)
-            keep &= hh == base_h
+            ur, hh, ax = forward_loss(w, ctx, F1, P, up, w.B0, w.steps)
+            keep &= (hh == base_h) & ~ax
             urs.append(ur)
         fd[:, c] = (urs[0] - urs[1]) / (2 * h) / n
     scale = gu.abs().max(dim=1).values + 1e-300
     err = ((gu - fd).abs().max(dim=1).values / scale)[keep]
     frac = keep.double().mean().item()
-    # dL/dB0: a particle whose removal or axis reflection (u_2 -> -u_2) changes
-    # between B0 - h and B0 + h makes the loss jump, so both sides sum over
-    # the particles that keep their cell sequence
-    lp, hp = forward_loss(w, ctx, F1, P, u0, w.B0 + h, w.steps)
-    lm, hm = forward_loss(w, ctx, F1, P, u0, w.B0 - h, w.steps)
-    kb = (hp == base_h) & (hm == base_h)
+    lp, hp, ap = forward_loss(w, ctx, F1, P, u0, w.B0 + h, w.steps)
+    lm, hm, am = forward_loss(w, ctx, F1, P, u0, w.B0 - h, w.steps)
+    kb = (hp == base_h) & (hm == base_h) & ~(axis | ap | am)
+    fd_all = ((lp - lm) / (2 * h)).sum().item() / n
     fd_b = ((lp - lm) / (2 * h))[kb].sum().item() / n
     ad_b = gB0_pp[kb].sum().item()
-    print(f"\n[C4 adjoint vs FD] loss {loss:.12g}; kept {frac:.4f} of {n}; per-particle rel err "
+    print(f"\n[C4 adjoint vs FD] loss {loss:.12g}; u0: kept {frac:.4f} of {n}, per-particle rel err "
           f"median {err.median().item():.3g} p99 {err.quantile(0.99).item():.3g} "
-          f"max {err.max().item():.3g}; dL/dB0 (all) {gB0:.12g}; on the {kb.double().mean().item():.4f}"
-          f" kept: adjoint {ad_b:.12g} vs FD {fd_b:.12g} (rel {abs(ad_b - fd_b) / abs(fd_b):.3g})")
+          f"p99.9 {err.quantile(0.999).item():.3g} max {err.max().item():.3g}; "
+          f"dL/dB0: all particles adjoint {gB0:.12g} vs FD {fd_all:.12g}; on the "
+          f"{kb.double().mean().item():.4f} kept adjoint {ad_b:.12g} vs FD {fd_b:.12g} "
+          f"(rel {abs(ad_b - fd_b) / abs(fd_b):.3g})")
     assert frac > 0.9
     assert err.quantile(0.999).item() <= 1e-6
     assert abs(ad_b - fd_b) <= 1e-6 * abs(fd_b)
+    assert abs(gB0 - fd_all) <= 1e-5 * abs(fd_all)
