@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--iter-tol", type=float, default=0.0,
                     help="FP64 convergence test of the implicit iterations (0: fixed count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the timing of the other precision form")
     ap.add_argument("--copy-calibration", action="store_true")
