@@ -35,7 +35,7 @@ struct Grid {
   double sin_lo, cos_lo, sin_hi, cos_hi;
   int n_r, n_th, ng, ld;  // ld = n_th + 2 ng (row length of a plane)
   int n_iter, n_filter, n_absorb;
-  int fast;               // offsets small enough for the polynomial path
+  int ser;                // series used by the push for in-cell offsets (0 = library)
   int i_fp64;             // single-precision push: cells i1 < i_fp64 (r < 3 M, the
                           // horizon region) take the metric and its derivatives in FP64
   int64_t plane;          // reals per plane

@@ -211,20 +211,22 @@ grpic_status push_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particle
       gp.D[k] = (const float*)F->D[k];
       gp.B[k] = (const float*)F->B0[k];
     }
-    if (c->g.fast)
-      hipLaunchKernelGGL(push_kernel_f32<true>, grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<float>(P));
-    else
-      hipLaunchKernelGGL(push_kernel_f32<false>, grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<float>(P));
+    switch (c->g.ser) {
+      case 2: hipLaunchKernelGGL((push_kernel_f32<2>), grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<float>(P)); break;
+      case 1: hipLaunchKernelGGL((push_kernel_f32<1>), grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<float>(P)); break;
+      default: hipLaunchKernelGGL((push_kernel_f32<0>), grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<float>(P)); break;
+    }
   } else {
     GatherPlanesT<double> gp;
     for (int k = 0; k < 3; ++k) {
       gp.D[k] = (const double*)F->D[k];
       gp.B[k] = (const double*)F->B0[k];
     }
-    if (c->g.fast)
-      hipLaunchKernelGGL(push_kernel<true>, grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<double>(P));
-    else
-      hipLaunchKernelGGL(push_kernel<false>, grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<double>(P));
+    switch (c->g.ser) {
+      case 2: hipLaunchKernelGGL((push_kernel<2>), grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<double>(P)); break;
+      case 1: hipLaunchKernelGGL((push_kernel<1>), grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<double>(P)); break;
+      default: hipLaunchKernelGGL((push_kernel<0>), grid, dim3(kB), 0, s, c->g, c->tab, gp, arrays<double>(P)); break;
+    }
   }
   LAUNCH_CHECK("push");
   return GRPIC_OK;
@@ -239,12 +241,11 @@ grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_
       gp.B[k] = (const float*)F->B0[k];
     }
     CurrentPlanesT<float> cp{{(float*)F->J[0], (float*)F->J[1], (float*)F->J[2]}};
-    if (c->g.fast)
-      hipLaunchKernelGGL(push_deposit_kernel_f32<true>, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp,
-                         arrays<float>(P), cp);
-    else
-      hipLaunchKernelGGL(push_deposit_kernel_f32<false>, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp,
-                         arrays<float>(P), cp);
+    switch (c->g.ser) {
+      case 2: hipLaunchKernelGGL((push_deposit_kernel_f32<2>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
+      case 1: hipLaunchKernelGGL((push_deposit_kernel_f32<1>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
+      default: hipLaunchKernelGGL((push_deposit_kernel_f32<0>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
+    }
   } else {
     GatherPlanesT<double> gp;
     for (int k = 0; k < 3; ++k) {
@@ -252,12 +253,11 @@ grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_
       gp.B[k] = (const double*)F->B0[k];
     }
     CurrentPlanesT<double> cp{{(double*)F->J[0], (double*)F->J[1], (double*)F->J[2]}};
-    if (c->g.fast)
-      hipLaunchKernelGGL(push_deposit_kernel<true>, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp,
-                         arrays<double>(P), cp);
-    else
-      hipLaunchKernelGGL(push_deposit_kernel<false>, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp,
-                         arrays<double>(P), cp);
+    switch (c->g.ser) {
+      case 2: hipLaunchKernelGGL((push_deposit_kernel<2>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
+      case 1: hipLaunchKernelGGL((push_deposit_kernel<1>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
+      default: hipLaunchKernelGGL((push_deposit_kernel<0>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
+    }
   }
   LAUNCH_CHECK("push_deposit");
   return GRPIC_OK;
@@ -267,10 +267,11 @@ template <class T>
 grpic_status deposit_impl(grpic_ctx* c, const grpic_particles* P, const grpic_fields* F, hipStream_t s) {
   CurrentPlanesT<T> cp{{(T*)F->J[0], (T*)F->J[1], (T*)F->J[2]}};
   const dim3 grid((unsigned)((P->n + kDepBlock - 1) / kDepBlock));
-  if (c->g.fast)
-    hipLaunchKernelGGL((deposit_kernel<T, true>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp);
-  else
-    hipLaunchKernelGGL((deposit_kernel<T, false>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp);
+  switch (c->g.ser) {
+    case 2: hipLaunchKernelGGL((deposit_kernel<T, 2>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
+    case 1: hipLaunchKernelGGL((deposit_kernel<T, 1>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
+    default: hipLaunchKernelGGL((deposit_kernel<T, 0>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
+  }
   LAUNCH_CHECK("deposit");
   return GRPIC_OK;
 }
@@ -471,8 +472,12 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   g.sin_hi = std::sin(kPi - p->small_angle);
   g.cos_hi = std::cos(kPi - p->small_angle);
   // the push evaluates exp and sincos of in-cell offsets (at most 1.5 cells)
-  // by short series that are exact to rounding for arguments up to 0.11
-  g.fast = 1.5 * std::fmax(g.dxi, g.dth) <= 0.11 ? 1 : 0;
+  // by series that are exact to rounding for arguments up to 0.03 (short) or
+  // 0.11 (long)
+  {
+    const double off = 1.5 * std::fmax(g.dxi, g.dth);
+    g.ser = (off <= 0.03 && 4.0 * g.dth <= 0.03) ? 2 : (off <= 0.11 ? 1 : 0);
+  }
   // single-precision push: cells whose inner edge lies below r = 3 M keep the
   // metric and its derivatives in FP64 (the horizon region, where lapse and
   // shift vary fastest)

@@ -146,8 +146,9 @@ __device__ inline void geodesic_u(const Grid& g, const FrameT<R>& f, const GradT
     const R n1 = s1 + dt * fr[0], n2 = s2 + dt * fr[1];
     // exact repeat: the fixed point of the map; or the optional convergence
     // test, evaluated in FP64
-    const bool fixed = (n1 == t1 && n2 == t2) ||
-                       fabs((double)n1 - (double)t1) + fabs((double)n2 - (double)t2) <=
+    bool fixed = n1 == t1 && n2 == t2;
+    if (g.iter_tol > 0.0)
+      fixed = fixed || fabs((double)n1 - (double)t1) + fabs((double)n2 - (double)t2) <=
                            g.iter_tol * (fabs((double)n1) + fabs((double)n2));
     t1 = n1;
     t2 = n2;
@@ -201,38 +202,68 @@ __device__ inline void sincos_small(double x, double* s, double* c) {
   *c = fma(z, pc, 1.0);
 }
 
+// exp(t) for |t| <= 0.03: Taylor series to t^8 (remainder below 1e-19 relative)
+__device__ inline double exp_short(double t) {
+  double p = fma(t, 1.0 / 40320.0, 1.0 / 5040.0);
+  p = fma(t, p, 1.0 / 720.0);
+  p = fma(t, p, 1.0 / 120.0);
+  p = fma(t, p, 1.0 / 24.0);
+  p = fma(t, p, 1.0 / 6.0);
+  p = fma(t, p, 0.5);
+  p = fma(t, p, 1.0);
+  return fma(t, p, 1.0);
+}
+
+// sin and cos for |x| <= 0.03: Taylor series to x^7 and x^6 (remainders
+// below 2e-17 relative)
+__device__ inline void sincos_short(double x, double* s, double* c) {
+  const double z = x * x;
+  double ps = fma(z, -1.0 / 5040.0, 1.0 / 120.0);
+  ps = fma(z, ps, -1.0 / 6.0);
+  *s = fma(x * z, ps, x);
+  double pc = fma(z, -1.0 / 720.0, 1.0 / 24.0);
+  pc = fma(z, pc, -0.5);
+  *c = fma(z, pc, 1.0);
+}
+
 // pi - (pi rounded to double)
 constexpr double kPiLo = 1.2246467991473531772e-16;
 
 // r, sin, cos at code position (x1, x2) near cell (i1, i2) (|x - i| <= 1.5):
 // r = r_i exp((x1 - i1) dxi); the polar angle is first rounded and clamped as
 // theta = clamp(x2 dth), and the result is the sine and cosine of that double:
-// by the short series on theta itself within 0.11 of theta = 0, on
-// psi = pi - theta (exact subtraction plus the low part of pi) within 0.11 of
-// theta = pi, so that sin keeps its relative precision next to both axes, and
-// by angle addition from the tables elsewhere.  Library functions when the
-// grid is too coarse for the short series.
-template <bool FAST>
+// by a series on theta itself next to theta = 0, on psi = pi - theta (exact
+// subtraction plus the low part of pi) next to theta = pi, so that sin keeps
+// its relative precision next to both axes (within the band, angle addition
+// would cancel), and by angle addition from the tables elsewhere.
+// SER = 2: offsets |x - i| dxi, dth <= 0.03 and an axis band of 4 cells (its
+// angles <= 0.03): short series throughout.  SER = 1: offsets <= 0.11 and an
+// axis band of 0.11 rad: long series.  SER = 0: library functions.
+template <int SER>
 __device__ inline RSC rsc_near(const Grid& g, const Tables& t, int i1, double x1, int i2, double x2) {
-  if (!FAST) return rsc_direct(g, x1, x2);
+  if (SER == 0) return rsc_direct(g, x1, x2);
   RSC p;
-  p.r = t.r[0][i1 + g.ng] * exp_small((x1 - (double)i1) * g.dxi);
+  const double tr = (x1 - (double)i1) * g.dxi;
+  p.r = t.r[0][i1 + g.ng] * (SER == 2 ? exp_short(tr) : exp_small(tr));
   const double th = x2 * g.dth;
+  const double band = SER == 2 ? 4.0 * g.dth : 0.11;
   if (th <= g.small_angle) {
     p.s = g.sin_lo;
     p.c = g.cos_lo;
   } else if (th >= kPi - g.small_angle) {
     p.s = g.sin_hi;
     p.c = g.cos_hi;
-  } else if (th <= 0.11) {
-    sincos_small(th, &p.s, &p.c);
-  } else if (th >= kPi - 0.11) {
+  } else if (th <= band) {
+    if (SER == 2) sincos_short(th, &p.s, &p.c); else sincos_small(th, &p.s, &p.c);
+  } else if (th >= kPi - band) {
     double cq;
-    sincos_small((kPi - th) + kPiLo, &p.s, &cq);
+    if (SER == 2) sincos_short((kPi - th) + kPiLo, &p.s, &cq);
+    else sincos_small((kPi - th) + kPiLo, &p.s, &cq);
     p.c = -cq;
   } else {
     double sp, cp;
-    sincos_small(th - (double)i2 * g.dth, &sp, &cp);
+    if (SER == 2) sincos_short(th - (double)i2 * g.dth, &sp, &cp);
+    else sincos_small(th - (double)i2 * g.dth, &sp, &cp);
     const double sj = t.s[0][i2 + g.ng], cj = t.c[0][i2 + g.ng];
     p.s = fma(sj, cp, cj * sp);
     p.c = fma(cj, cp, -(sj * sp));
@@ -265,12 +296,12 @@ __device__ inline void sincos_small_f(float x, float* s, float* c) {
 // (i1, i2), |f| <= 1.5.  The polar angle is measured from the nearer axis,
 // theta = (i2 + f2) dth or pi - theta = (n_th - i2 - f2) dth, so that sin keeps
 // its relative precision next to either axis; clamped at small_angle.
-template <bool FAST>
+template <int SER>
 __device__ inline RSCT<float> rsc_near_f(const Grid& g, const Tables& t, int i1, float f1, int i2,
                                         float f2) {
   RSCT<float> p;
   const float dth = (float)g.dth, eps = (float)g.small_angle;
-  p.r = FAST ? t.rf[i1 + g.ng] * exp_small_f(f1 * (float)g.dxi)
+  p.r = SER > 0 ? t.rf[i1 + g.ng] * exp_small_f(f1 * (float)g.dxi)
              : t.rf[i1 + g.ng] * expf(f1 * (float)g.dxi);
   const bool upper = 2 * i2 >= g.n_th;
   const float ang = upper ? ((float)(g.n_th - i2) - f2) * dth : ((float)i2 + f2) * dth;
@@ -278,7 +309,7 @@ __device__ inline RSCT<float> rsc_near_f(const Grid& g, const Tables& t, int i1,
   if (ang <= eps) {
     s = (float)g.sin_lo;
     c = (float)g.cos_lo;
-  } else if (!FAST) {
+  } else if (SER == 0) {
     sincosf(ang, &s, &c);
   } else if (ang <= 0.11f) {
     sincos_small_f(ang, &s, &c);
@@ -310,7 +341,7 @@ struct Move {
 
 // FP64 particle update (Sec. 3.1 steps 1-11) of slot k; writes the new state
 // and returns the move for the deposit.
-template <bool FAST>
+template <int SER>
 __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const GatherPlanesT<double>& fp,
                                         const ParticleArrays& P, int64_t k) {
   Move<double> mv;
@@ -341,7 +372,7 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
   const double x1 = (double)i1 + dx1, x2 = (double)i2 + dx2;
   Frame f;
   Grad d;
-  frame_from(g, rsc_near<FAST>(g, tab, i1, x1, i2, x2), &f, &d);
+  frame_from(g, rsc_near<SER>(g, tab, i1, x1, i2, x2), &f, &d);
   const double qm = species_sign(t);
   if (qm != 0.0) {
     // D^i, B^i at x^n -> tetrad components, scaled by the lapse
@@ -366,24 +397,33 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
   // repeats exactly is the fixed point of the map, so stopping there gives the
   // same result as running all n_iter iterations (and with iter_tol > 0 the
   // loop also ends once the FP64 change is below the relative tolerance)
+  // The first iterate (d = 0) uses the coefficients at x^n already in hand.
   double d1 = 0.0, d2 = 0.0;
-  for (int it = 0; it < g.n_iter; ++it) {
-    const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
-    const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
-                                       m.hu33 * u3 * u3 + 2.0 * m.hu13 * u1 * u3);
+  Coeffs m = f.c;
+  double iu0;
+  bool repeat = false;
+  for (int it = 0;;) {
+    iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+                          2.0 * m.hu13 * u1 * u3);
     const double n1 = g.dt * ((m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1);
     const double n2 = g.dt * (m.hu22 * u2 * iu0);
-    const bool fixed = (n1 == d1 && n2 == d2) ||
-                       fabs(n1 - d1) + fabs(n2 - d2) <= g.iter_tol * (fabs(n1) + fabs(n2));
+    repeat = n1 == d1 && n2 == d2;
+    bool fixed = repeat;
+    if (g.iter_tol > 0.0)
+      fixed = fixed || fabs(n1 - d1) + fabs(n2 - d2) <= g.iter_tol * (fabs(n1) + fabs(n2));
     d1 = n1;
     d2 = n2;
-    if (fixed) break;
+    if (fixed || ++it >= g.n_iter) break;
+    m = coeffs_from(g, rsc_near<SER>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
   }
   {
-    // phi update and the phi velocity at the path midpoint (the J^3 of the deposit)
-    const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
-    const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
-                                       m.hu33 * u3 * u3 + 2.0 * m.hu13 * u1 * u3);
+    // phi update and the phi velocity at the path midpoint (the J^3 of the
+    // deposit); after an exact repeat the last coefficients are already there
+    if (!repeat) {
+      m = coeffs_from(g, rsc_near<SER>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
+      iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+                            2.0 * m.hu13 * u1 * u3);
+    }
     P.phi[k] += g.dt * (m.hu13 * u1 + m.hu33 * u3) * iu0;
     mv.vphi = (m.hu13 * u1 + m.hu33 * u3) * iu0;
   }
@@ -427,7 +467,7 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
 }
 
 // Single-precision form of the same update (see the file comment).
-template <bool FAST>
+template <int SER>
 __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, const GatherPlanesT<float>& fp,
                                            const ParticleArraysT<float>& P, int64_t k) {
   Move<float> mv;
@@ -461,7 +501,7 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
     // horizon region: metric and derivatives in FP64, then rounded
     Frame fd;
     Grad dd;
-    frame_from(g, rsc_near<FAST>(g, tab, i1, (double)i1 + dx1, i2, (double)i2 + dx2), &fd, &dd);
+    frame_from(g, rsc_near<SER>(g, tab, i1, (double)i1 + dx1, i2, (double)i2 + dx2), &fd, &dd);
     f.c = CoeffsT<float>{(float)fd.c.alpha, (float)fd.c.beta1, (float)fd.c.hu11,
                          (float)fd.c.hu22, (float)fd.c.hu33, (float)fd.c.hu13};
     f.s11 = (float)fd.s11;
@@ -478,7 +518,7 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
       d.hu13[q] = (float)dd.hu13[q];
     }
   } else {
-    frame_from(g, rsc_near_f<FAST>(g, tab, i1, dx1, i2, dx2), &f, &d);
+    frame_from(g, rsc_near_f<SER>(g, tab, i1, dx1, i2, dx2), &f, &d);
   }
   const float qm = (float)species_sign(t);
   if (qm != 0.0f) {
@@ -502,25 +542,30 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
   // implicit coordinate update with the displacement (d1, d2) in cells
   const float dt = (float)g.dt;
   float d1 = 0.0f, d2 = 0.0f;
-  for (int it = 0; it < g.n_iter; ++it) {
-    const CoeffsT<float> m =
-        coeffs_from(g, rsc_near_f<FAST>(g, tab, i1, dx1 + 0.5f * d1, i2, dx2 + 0.5f * d2));
-    const float iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
-                                      m.hu33 * u3 * u3 + 2.0f * m.hu13 * u1 * u3);
+  CoeffsT<float> m = f.c;
+  float iu0;
+  bool repeat = false;
+  for (int it = 0;;) {
+    iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+                          2.0f * m.hu13 * u1 * u3);
     const float n1 = dt * ((m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1);
     const float n2 = dt * (m.hu22 * u2 * iu0);
-    const bool fixed = (n1 == d1 && n2 == d2) ||
-                       fabs((double)n1 - (double)d1) + fabs((double)n2 - (double)d2) <=
+    repeat = n1 == d1 && n2 == d2;
+    bool fixed = repeat;
+    if (g.iter_tol > 0.0)
+      fixed = fixed || fabs((double)n1 - (double)d1) + fabs((double)n2 - (double)d2) <=
                            g.iter_tol * (fabs((double)n1) + fabs((double)n2));
     d1 = n1;
     d2 = n2;
-    if (fixed) break;
+    if (fixed || ++it >= g.n_iter) break;
+    m = coeffs_from(g, rsc_near_f<SER>(g, tab, i1, dx1 + 0.5f * d1, i2, dx2 + 0.5f * d2));
   }
   {
-    const CoeffsT<float> m =
-        coeffs_from(g, rsc_near_f<FAST>(g, tab, i1, dx1 + 0.5f * d1, i2, dx2 + 0.5f * d2));
-    const float iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 +
-                                      m.hu33 * u3 * u3 + 2.0f * m.hu13 * u1 * u3);
+    if (!repeat) {
+      m = coeffs_from(g, rsc_near_f<SER>(g, tab, i1, dx1 + 0.5f * d1, i2, dx2 + 0.5f * d2));
+      iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+                            2.0f * m.hu13 * u1 * u3);
+    }
     mv.vphi = (m.hu13 * u1 + m.hu33 * u3) * iu0;
     P.phi[k] += dt * mv.vphi;
   }
@@ -615,24 +660,24 @@ struct ContribT {
 };
 
 // lapse-weighted phi velocity alpha u^3 / gamma at the path midpoint (ia + xm, ja + ym)
-template <bool FAST>
+template <int SER>
 __device__ inline double vphi_mid(const Grid& g, const Tables& tab, int ia, double xm, int ja,
                                   double ym, double u1, double u2, double u3) {
-  const Coeffs m = coeffs_from(g, rsc_near<FAST>(g, tab, ia, (double)ia + xm, ja, (double)ja + ym));
+  const Coeffs m = coeffs_from(g, rsc_near<SER>(g, tab, ia, (double)ia + xm, ja, (double)ja + ym));
   const double iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
                                      2.0 * m.hu13 * u1 * u3);
   return (m.hu13 * u1 + m.hu33 * u3) * iu0;
 }
-template <bool FAST>
+template <int SER>
 __device__ inline float vphi_mid(const Grid& g, const Tables& tab, int ia, float xm, int ja,
                                  float ym, float u1, float u2, float u3) {
-  const CoeffsT<float> m = coeffs_from(g, rsc_near_f<FAST>(g, tab, ia, xm, ja, ym));
+  const CoeffsT<float> m = coeffs_from(g, rsc_near_f<SER>(g, tab, ia, xm, ja, ym));
   const float iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
                                     2.0f * m.hu13 * u1 * u3);
   return (m.hu13 * u1 + m.hu33 * u3) * iu0;
 }
 
-template <class T, bool FAST>
+template <class T, int SER>
 __device__ inline bool make_contrib(const Grid& g, const Tables& tab, const Move<T>& mv, ContribT<T>& c) {
   c.ia = c.ja = c.di = c.dj = c.km = c.lm = 0;
   if (!mv.dep) return false;
@@ -667,7 +712,7 @@ __device__ inline bool make_contrib(const Grid& g, const Tables& tab, const Move
   c.j2[2] = fy2 * (one - wx2);
   c.j2[3] = fy2 * wx2;
   const T xm = half * (xa + xb), ym = half * (ya + yb);
-  const T vphi = mv.mid ? mv.vphi : vphi_mid<FAST>(g, tab, ia, xm, ja, ym, mv.u1, mv.u2, mv.u3);
+  const T vphi = mv.mid ? mv.vphi : vphi_mid<SER>(g, tab, ia, xm, ja, ym, mv.u1, mv.u2, mv.u3);
   const T fm = floor(xm), gm = floor(ym);
   const T w1 = xm - fm, w2 = ym - gm;
   const T c3 = q * vphi;
@@ -815,46 +860,51 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
 }
 
 // ------------------------------------------------------------------ kernels
+// The FP64 push kernels are held to 128 VGPRs (4 wavefronts per SIMD; a few
+// spilled registers): on gfx950 the push is latency- and issue-bound, and the
+// fourth wavefront hides more than the spills cost (the compiler's own choice,
+// ~160 VGPRs, gives 3 wavefronts and a 10-15 % slower pass).
+#define GRPIC_FP64_PUSH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4)))
 
-template <bool FAST>
-__global__ void __launch_bounds__(256) push_kernel(Grid g, Tables tab, GatherPlanesT<double> fp,
-                                                   ParticleArrays P) {
-  (void)push_one<FAST>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+template <int SER>
+__global__ void __launch_bounds__(256) GRPIC_FP64_PUSH_OCCUPANCY
+push_kernel(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P) {
+  (void)push_one<SER>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-template <bool FAST>
+template <int SER>
 __global__ void __launch_bounds__(256) push_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
                                                        ParticleArraysT<float> P) {
-  (void)push_one_f32<FAST>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  (void)push_one_f32<SER>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-template <class T, bool FAST>
+template <class T, int SER>
 __global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, ParticleArraysT<T> P,
                                                             CurrentPlanesT<T> cp) {
   const Move<T> mv = load_move(g, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   ContribT<T> c;
-  const bool act = make_contrib<T, FAST>(g, tab, mv, c);
+  const bool act = make_contrib<T, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
 }
 
 // Push and deposit in one pass: the deposit takes the move from registers and
 // J^3 from the push's own midpoint metric.
-template <bool FAST>
-__global__ void __launch_bounds__(kDepBlock) push_deposit_kernel(Grid g, Tables tab, GatherPlanesT<double> fp,
-                                                                 ParticleArrays P, CurrentPlanes cp) {
-  const Move<double> mv = push_one<FAST>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+template <int SER>
+__global__ void __launch_bounds__(kDepBlock) GRPIC_FP64_PUSH_OCCUPANCY
+push_deposit_kernel(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp) {
+  const Move<double> mv = push_one<SER>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   ContribT<double> c;
-  const bool act = make_contrib<double, FAST>(g, tab, mv, c);
+  const bool act = make_contrib<double, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
 }
 
-template <bool FAST>
+template <int SER>
 __global__ void __launch_bounds__(kDepBlock) push_deposit_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
                                                                      ParticleArraysT<float> P,
                                                                      CurrentPlanesT<float> cp) {
-  const Move<float> mv = push_one_f32<FAST>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const Move<float> mv = push_one_f32<SER>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   ContribT<float> c;
-  const bool act = make_contrib<float, FAST>(g, tab, mv, c);
+  const bool act = make_contrib<float, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
 }
 
