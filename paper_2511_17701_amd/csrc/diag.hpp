@@ -134,13 +134,4 @@ __global__ void gauss_kernel(Grid g, Tables t, const T* __restrict__ D1,
   }
 }
 
-// even-parity theta ghosts of a node-located scalar plane
-template <class T>
-__global__ void scalar_axis_kernel(Grid g, T* __restrict__ C) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
-  if (i >= g.n_r + g.ng) return;
-  for (int k = 1; k <= g.ng; ++k) C[ix(g, i, -k)] = C[ix(g, i, k)];
-  for (int k = 1; k < g.ng; ++k) C[ix(g, i, g.n_th + k)] = C[ix(g, i, g.n_th - k)];
-}
-
 }  // namespace grpic

@@ -36,6 +36,45 @@ __device__ inline Cell cell_tab(const Grid& g, const Tables& t, int i, int o1, i
   return e;
 }
 
+// ---------------------------------------------------------------- weights
+// Solver weights at one staggered point (i + o1/2, j + o2/2).  With
+// S2 = Sigma + 2 M r and k = 1/sqrt(Sigma S2), the lapse is Sigma k,
+// 1/Sigma = S2 k^2, 1/S2 = Sigma k^2 and sqrt(h)/sin(theta) = R dtheta / k
+// (R = dxi r), so one reciprocal square root gives every factor of the
+// closed forms of App. A (the same quantities as cell_tab).
+struct FW {
+  double alpha;                   // lapse
+  double hl11, hl22, hl33;        // lower spatial metric, code components
+  double w13;                     // sqrt(h)/sin * h_13       (radial-average weight)
+  double wb;                      // sqrt(h)/sin * sqrt(h) * beta^1
+  double h_sht;                   // 1 / (2 sqrt(h)/sin)      (radial-average norm)
+  double ish;                     // 1 / sqrt(h)              (0 on the axis)
+};
+
+__device__ inline FW fw_tab(const Grid& g, const Tables& t, int i, int o1, int j, int o2) {
+  const double r = t.r[o1][i + g.ng], ird = t.ird[o1][i + g.ng];
+  const double s = t.s[o2][j + g.ng], c = t.c[o2][j + g.ng], is = t.is[o2][j + g.ng];
+  const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r, s2 = s * s;
+  const double Sig = r2 + a2 * c * c;
+  const double S2 = Sig + tMr;
+  const double ra = r2 + a2;
+  const double A = ra * ra - a2 * (ra - tMr) * s2;
+  const double R = g.dxi * r;
+  const double k = rsqrt(Sig * S2);
+  const double k2 = k * k;
+  const double S2k = S2 * k;
+  FW e;
+  e.alpha = Sig * k;
+  e.hl11 = S2k * S2k * R * R;
+  e.hl22 = Sig * g.dth * g.dth;
+  e.hl33 = A * s2 * S2 * k2;
+  e.w13 = -g.a * g.dth * R * R * s2 * S2 * S2k;
+  e.wb = R * g.dth * g.dth * s * tMr * Sig;
+  e.h_sht = 0.5 * k * ird;
+  e.ish = k * ird * is;
+  return e;
+}
+
 template <class T>
 struct TriT {
   T* __restrict__ p[3];
@@ -63,216 +102,265 @@ __device__ inline void add_to(T* __restrict__ X, T* __restrict__ L, int64_t o, d
   }
 }
 
+// Whole-plane thread index (ghosts included): j along theta, i along r.
+struct PlaneIdx {
+  int i, j;
+  bool ok;
+};
+__device__ inline PlaneIdx plane_idx(const Grid& g) {
+  PlaneIdx q;
+  q.j = (int)(blockIdx.x * blockDim.x + threadIdx.x) - g.ng;
+  q.i = (int)(blockIdx.y * blockDim.y + threadIdx.y) - g.ng;
+  q.ok = q.j < g.n_th + g.ng && q.i < g.n_r + g.ng;
+  return q;
+}
+
 // ---------------------------------------------------------------- aux E, H
 // eq. discretized-auxE/-auxH with the volume-weighted radial averages of
 // Sec. 3.3.1 (weights sqrt(h)/sin(theta)); for i in [-1, n_r], j in [0, n_th].
-
-template <class T>
-__global__ void aux_e_kernel(Grid g, Tables t, CTriT<T> Bs, CTriT<T> Ds, TriT<T> E) {
+// kE / kH select the outputs; both read the same B, D and share the weights.
+template <class T, bool kE, bool kH>
+__global__ void aux_kernel(Grid g, Tables t, CTriT<T> Bs, CTriT<T> Ds, TriT<T> E, TriT<T> H) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y - 1;
   if (j > g.n_th || i > g.n_r) return;
-  const int64_t o = ix(g, i, j);
-  {  // E_1 (i+1/2, j)
-    const Cell c = cell_tab(g, t, i, 1, j, 0);
-    const Cell m0 = cell_tab(g, t, i, 0, j, 0), m1 = cell_tab(g, t, i + 1, 0, j, 0);
-    const double av = (m0.sqrt_ht * m0.hl13 * Ds.p[2][o] + m1.sqrt_ht * m1.hl13 * Ds.p[2][o + g.ld]) /
-                      (2.0 * c.sqrt_ht);
-    E.p[0][o] = c.alpha * (c.hl11 * Ds.p[0][o] + av);
-  }
-  {  // E_3 (i, j)
-    const Cell c = cell_tab(g, t, i, 0, j, 0);
-    const Cell m0 = cell_tab(g, t, i - 1, 1, j, 0), m1 = cell_tab(g, t, i, 1, j, 0);
-    const double w0 = m0.sqrt_ht, w1 = m1.sqrt_ht, iw = 1.0 / (2.0 * c.sqrt_ht);
-    const double a1 = (w0 * m0.hl13 * Ds.p[0][o - g.ld] + w1 * m1.hl13 * Ds.p[0][o]) * iw;
-    const double a2 = (w0 * m0.sqrt_h * m0.beta1 * Bs.p[1][o - g.ld] +
-                       w1 * m1.sqrt_h * m1.beta1 * Bs.p[1][o]) * iw;
-    E.p[2][o] = c.alpha * (c.hl33 * Ds.p[2][o] + a1) + a2;
-  }
-  if (j < g.n_th) {  // E_2 (i, j+1/2)
-    const Cell c = cell_tab(g, t, i, 0, j, 1);
-    const Cell m0 = cell_tab(g, t, i - 1, 1, j, 1), m1 = cell_tab(g, t, i, 1, j, 1);
-    const double a3 = (m0.sqrt_ht * m0.sqrt_h * m0.beta1 * Bs.p[2][o - g.ld] +
-                       m1.sqrt_ht * m1.sqrt_h * m1.beta1 * Bs.p[2][o]) / (2.0 * c.sqrt_ht);
-    E.p[1][o] = c.alpha * c.hl22 * Ds.p[1][o] - a3;
-  }
-}
-
-template <class T>
-__global__ void aux_h_kernel(Grid g, Tables t, CTriT<T> Bs, CTriT<T> Ds, TriT<T> H) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y - 1;
-  if (j > g.n_th || i > g.n_r) return;
-  const int64_t o = ix(g, i, j);
-  {  // H_2 (i+1/2, j)
-    const Cell c = cell_tab(g, t, i, 1, j, 0);
-    const Cell m0 = cell_tab(g, t, i, 0, j, 0), m1 = cell_tab(g, t, i + 1, 0, j, 0);
-    const double a1 = (m0.sqrt_ht * m0.sqrt_h * m0.beta1 * Ds.p[2][o] +
-                       m1.sqrt_ht * m1.sqrt_h * m1.beta1 * Ds.p[2][o + g.ld]) / (2.0 * c.sqrt_ht);
-    H.p[1][o] = c.alpha * c.hl22 * Bs.p[1][o] + a1;
-  }
-  if (j < g.n_th) {
-    {  // H_1 (i, j+1/2)
-      const Cell c = cell_tab(g, t, i, 0, j, 1);
-      const Cell m0 = cell_tab(g, t, i - 1, 1, j, 1), m1 = cell_tab(g, t, i, 1, j, 1);
-      const double a2 = (m0.sqrt_ht * m0.hl13 * Bs.p[2][o - g.ld] + m1.sqrt_ht * m1.hl13 * Bs.p[2][o]) /
-                        (2.0 * c.sqrt_ht);
-      H.p[0][o] = c.alpha * (c.hl11 * Bs.p[0][o] + a2);
+  const int64_t o = ix(g, i, j), ld = g.ld;
+  const bool half = j < g.n_th;  // theta-staggered components exist
+  // weights at the points the stencils touch (unused ones are not computed)
+  const FW n00 = fw_tab(g, t, i, 0, j, 0);       // (i, j)
+  const FW n10 = fw_tab(g, t, i + 1, 0, j, 0);   // (i+1, j)
+  const FW h00 = fw_tab(g, t, i, 1, j, 0);       // (i+1/2, j)
+  const FW hm0 = fw_tab(g, t, i - 1, 1, j, 0);   // (i-1/2, j)
+  const FW n01 = fw_tab(g, t, i, 0, j, 1);       // (i, j+1/2)
+  const FW n11 = fw_tab(g, t, i + 1, 0, j, 1);   // (i+1, j+1/2)
+  const FW h01 = fw_tab(g, t, i, 1, j, 1);       // (i+1/2, j+1/2)
+  const FW hm1 = fw_tab(g, t, i - 1, 1, j, 1);   // (i-1/2, j+1/2)
+  if (kE) {
+    {  // E_1 (i+1/2, j)
+      const double av = (n00.w13 * Ds.p[2][o] + n10.w13 * Ds.p[2][o + ld]) * h00.h_sht;
+      E.p[0][o] = h00.alpha * (h00.hl11 * Ds.p[0][o] + av);
     }
-    {  // H_3 (i+1/2, j+1/2)
-      const Cell c = cell_tab(g, t, i, 1, j, 1);
-      const Cell m0 = cell_tab(g, t, i, 0, j, 1), m1 = cell_tab(g, t, i + 1, 0, j, 1);
-      const double iw = 1.0 / (2.0 * c.sqrt_ht);
-      const double a3 = (m0.sqrt_ht * m0.hl13 * Bs.p[0][o] + m1.sqrt_ht * m1.hl13 * Bs.p[0][o + g.ld]) * iw;
-      const double a4 = (m0.sqrt_ht * m0.sqrt_h * m0.beta1 * Ds.p[1][o] +
-                         m1.sqrt_ht * m1.sqrt_h * m1.beta1 * Ds.p[1][o + g.ld]) * iw;
-      H.p[2][o] = c.alpha * (c.hl33 * Bs.p[2][o] + a3) - a4;
+    {  // E_3 (i, j)
+      const double a1 = (hm0.w13 * Ds.p[0][o - ld] + h00.w13 * Ds.p[0][o]) * n00.h_sht;
+      const double a2 = (hm0.wb * Bs.p[1][o - ld] + h00.wb * Bs.p[1][o]) * n00.h_sht;
+      E.p[2][o] = n00.alpha * (n00.hl33 * Ds.p[2][o] + a1) + a2;
+    }
+    if (half) {  // E_2 (i, j+1/2)
+      const double a3 = (hm1.wb * Bs.p[2][o - ld] + h01.wb * Bs.p[2][o]) * n01.h_sht;
+      E.p[1][o] = n01.alpha * n01.hl22 * Ds.p[1][o] - a3;
+    }
+  }
+  if (kH) {
+    {  // H_2 (i+1/2, j)
+      const double a1 = (n00.wb * Ds.p[2][o] + n10.wb * Ds.p[2][o + ld]) * h00.h_sht;
+      H.p[1][o] = h00.alpha * h00.hl22 * Bs.p[1][o] + a1;
+    }
+    if (half) {
+      {  // H_1 (i, j+1/2)
+        const double a2 = (hm1.w13 * Bs.p[2][o - ld] + h01.w13 * Bs.p[2][o]) * n01.h_sht;
+        H.p[0][o] = n01.alpha * (n01.hl11 * Bs.p[0][o] + a2);
+      }
+      {  // H_3 (i+1/2, j+1/2)
+        const double a3 = (n01.w13 * Bs.p[0][o] + n11.w13 * Bs.p[0][o + ld]) * h01.h_sht;
+        const double a4 = (n01.wb * Ds.p[1][o] + n11.wb * Ds.p[1][o + ld]) * h01.h_sht;
+        H.p[2][o] = h01.alpha * (h01.hl33 * Bs.p[2][o] + a3) - a4;
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------- Faraday
-// eq. discretized-faraday on the evolved ranges (thread (i, j), i in [0, n_r],
-// j in [0, n_th]).
-template <class T>
-__global__ void faraday_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> E) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (j > g.n_th || i > g.n_r) return;
+// eq. discretized-faraday on the evolved ranges i in [0, n_r], j in [0, n_th].
+// With kSave the grid spans the whole plane and X0 <- X (the field before the
+// update, ghosts included) is taken in the same pass.
+template <class T, bool kSave>
+__global__ void faraday_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> E, TriT<T> X0) {
+  int i, j;
+  if (kSave) {
+    const PlaneIdx q = plane_idx(g);
+    if (!q.ok) return;
+    i = q.i;
+    j = q.j;
+  } else {
+    j = blockIdx.x * blockDim.x + threadIdx.x;
+    i = blockIdx.y * blockDim.y + threadIdx.y;
+  }
   const int64_t o = ix(g, i, j);
+  if (kSave) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) X0.p[c][o] = X.p[c][o];
+  }
+  if (i < 0 || j < 0 || j > g.n_th || i > g.n_r) return;
   if (j < g.n_th) {
-    const Cell c = cell_tab(g, t, i, 0, j, 1);
-    add_to(X.p[0], L.p[0], o, -(g.dt * (E.p[2][o + 1] - E.p[2][o]) / c.sqrt_h));
+    const double ish = fw_tab(g, t, i, 0, j, 1).ish;
+    add_to(X.p[0], L.p[0], o, -(g.dt * (E.p[2][o + 1] - E.p[2][o]) * ish));
   }
   if (i < g.n_r && j >= 1 && j < g.n_th) {
-    const Cell c = cell_tab(g, t, i, 1, j, 0);
-    add_to(X.p[1], L.p[1], o, g.dt * (E.p[2][o + g.ld] - E.p[2][o]) / c.sqrt_h);
+    const double ish = fw_tab(g, t, i, 1, j, 0).ish;
+    add_to(X.p[1], L.p[1], o, g.dt * (E.p[2][o + g.ld] - E.p[2][o]) * ish);
   }
   if (i < g.n_r && j < g.n_th) {
-    const Cell c = cell_tab(g, t, i, 1, j, 1);
+    const double ish = fw_tab(g, t, i, 1, j, 1).ish;
     const double curl = (E.p[1][o + g.ld] - E.p[1][o]) - (E.p[0][o + 1] - E.p[0][o]);
-    add_to(X.p[2], L.p[2], o, -(g.dt * curl / c.sqrt_h));
+    add_to(X.p[2], L.p[2], o, -(g.dt * curl * ish));
   }
 }
 
 // ---------------------------------------------------------------- Ampere
-// eq. discretized-ampere with J = wa Ja + wb Jb; D^1 on the axis rows from the
-// polar-cap integral form (Sec. 3.3.2): cap area A_{i+1/2}; the theta = pi cap
-// has the opposite orientation, and the one-sided axis-row current enters
-// with 4 pi.
-template <class T>
-__global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H, CTriT<T> Ja, CTriT<T> Jb, double wa,
-                              double wb, double polar_k) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (j > g.n_th || i > g.n_r) return;
+// eq. discretized-ampere with the current J = wa Ja + wb Jb; D^1 on the axis
+// rows from the polar-cap integral form (Sec. 3.3.2): cap area A_{i+1/2}; the
+// theta = pi cap has the opposite orientation, and the one-sided axis-row
+// current enters with 4 pi.
+// kFinal (the last half of the step): the grid spans the whole plane, the
+// current is Ja alone, and the same pass takes X0 <- X before the update and
+// rotates the currents, Jb <- Ja and Ja <- 0, after it.
+template <class T, bool kFinal>
+__global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H, TriT<T> Ja, TriT<T> Jb, double wa,
+                              double wb, double polar_k, TriT<T> X0) {
+  int i, j;
+  if (kFinal) {
+    const PlaneIdx q = plane_idx(g);
+    if (!q.ok) return;
+    i = q.i;
+    j = q.j;
+  } else {
+    j = blockIdx.x * blockDim.x + threadIdx.x;
+    i = blockIdx.y * blockDim.y + threadIdx.y;
+  }
   const int64_t o = ix(g, i, j);
-  const double fpi = 4.0 * kPi;
-  if (i < g.n_r) {
-    const double J1 = wa * Ja.p[0][o] + wb * Jb.p[0][o];
+  if (kFinal) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) X0.p[c][o] = X.p[c][o];
+  }
+  if (!(i < 0 || j < 0 || j > g.n_th || i > g.n_r)) {
+    const double fpi = 4.0 * kPi;
+    auto cur = [&](int c) -> double {
+      return kFinal ? (double)Ja.p[c][o] : wa * Ja.p[c][o] + wb * Jb.p[c][o];
+    };
+    if (i < g.n_r) {
+      const double J1 = cur(0);
+      if (j >= 1 && j < g.n_th) {
+        const double ish = fw_tab(g, t, i, 1, j, 0).ish;
+        add_to(X.p[0], L.p[0], o, g.dt * ((H.p[2][o] - H.p[2][o - 1]) - fpi * J1) * ish);
+      } else {
+        const double r = t.r[1][i + g.ng];
+        const double ra = r * r + g.a * g.a;
+        const double Ap = g.dxi * r * ra * sqrt(1.0 + 2.0 * g.M * r / ra) * polar_k;
+        const double h3 = (j == 0) ? H.p[2][o] : -H.p[2][o - 1];
+        add_to(X.p[0], L.p[0], o, g.dt * (h3 - fpi * J1) / Ap);
+      }
+    }
+    if (j < g.n_th) {
+      const double ish = fw_tab(g, t, i, 0, j, 1).ish;
+      const double J2 = cur(1);
+      add_to(X.p[1], L.p[1], o, g.dt * (-(H.p[2][o] - H.p[2][o - g.ld]) - fpi * J2) * ish);
+    }
     if (j >= 1 && j < g.n_th) {
-      const Cell c = cell_tab(g, t, i, 1, j, 0);
-      add_to(X.p[0], L.p[0], o, g.dt * ((H.p[2][o] - H.p[2][o - 1]) - fpi * J1) / c.sqrt_h);
-    } else {
-      const double r = t.r[1][i + g.ng];
-      const double ra = r * r + g.a * g.a;
-      const double Ap = g.dxi * r * ra * sqrt(1.0 + 2.0 * g.M * r / ra) * polar_k;
-      const double h3 = (j == 0) ? H.p[2][o] : -H.p[2][o - 1];
-      add_to(X.p[0], L.p[0], o, g.dt * (h3 - fpi * J1) / Ap);
+      const double ish = fw_tab(g, t, i, 0, j, 0).ish;
+      const double J3 = cur(2);
+      const double curl = (H.p[1][o] - H.p[1][o - g.ld]) - (H.p[0][o] - H.p[0][o - 1]);
+      add_to(X.p[2], L.p[2], o, g.dt * (curl - fpi * J3) * ish);
     }
   }
-  if (j < g.n_th) {
-    const Cell c = cell_tab(g, t, i, 0, j, 1);
-    const double J2 = wa * Ja.p[1][o] + wb * Jb.p[1][o];
-    add_to(X.p[1], L.p[1], o, g.dt * (-(H.p[2][o] - H.p[2][o - g.ld]) - fpi * J2) / c.sqrt_h);
-  }
-  if (j >= 1 && j < g.n_th) {
-    const Cell c = cell_tab(g, t, i, 0, j, 0);
-    const double J3 = wa * Ja.p[2][o] + wb * Jb.p[2][o];
-    const double curl = (H.p[1][o] - H.p[1][o - g.ld]) - (H.p[0][o] - H.p[0][o - 1]);
-    add_to(X.p[2], L.p[2], o, g.dt * (curl - fpi * J3) / c.sqrt_h);
+  if (kFinal) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Jb.p[c][o] = Ja.p[c][o];
+      Ja.p[c][o] = 0.0;
+    }
   }
 }
 
 // ---------------------------------------------------------------- boundaries
-// Constant layer inside the horizon (i in [-ng, n_f] takes row n_f + 1) and the
-// absorbing layer (F <- F - lambda (F - F_init), lambda a cubic ramp over the
-// last n_absorb cells); whole plane incl. ghosts.  half1[c] = staggering of
-// component c in x1.
+// One block per plane row i in [-ng, n_r + ng - 1], the radial conditions
+// first, then the axis:
+//  - constant layer inside the horizon (rows i <= n_f take row n_f + 1) and
+//    the absorbing layer (F <- F - lambda (F - F_init), lambda a cubic ramp
+//    over the last n_absorb cells), on every column;  half1[c] = staggering of
+//    component c in x1;
+//  - axis reflection (Sec. 3.3.3): r-components even, theta and phi
+//    components odd, ghost columns from the row's own updated values; with
+//    zero_comp, the theta component of B (B^2) or the phi component of D (D^3)
+//    vanishes on the axis rows.  half2[c] = staggering in x2.
+// Rows i <= n_f read row n_f + 1, which neither layer changes; the axis pass of
+// that row may run first and only rewrites entries that each row's own axis
+// pass rewrites again.
+// With radial = 0 only the axis reflection is applied (initial data).
 template <class T>
-__global__ void bc_radial_kernel(Grid g, TriT<T> X, TriT<T> L, CTriT<T> X0, int3 half1) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y - g.ng;
-  if (j >= g.n_th + g.ng || i >= g.n_r + g.ng) return;
-  const int64_t o = ix(g, i, j);
-  const int hs[3] = {half1.x, half1.y, half1.z};
+__global__ void bc_kernel(Grid g, TriT<T> X, TriT<T> L, CTriT<T> X0, int3 half1, int3 half2, int zero_comp,
+                          int radial) {
+  const int i = (int)blockIdx.x - g.ng;
+  const int h1[3] = {half1.x, half1.y, half1.z};
+  const int h2[3] = {half2.x, half2.y, half2.z};
+  const bool comp = sizeof(T) == 4 && L.p[0];
+  const bool horizon = i <= g.n_filter;
+  const double x0 = (double)(g.n_r - g.n_absorb);
+  if (radial && (horizon || (g.n_absorb > 0 && (double)i + 0.5 > x0))) {
+    for (int j = (int)threadIdx.x - g.ng; j < g.n_th + g.ng; j += blockDim.x) {
+      const int64_t o = ix(g, i, j);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (i <= g.n_filter) {
-      X.p[c][o] = X.p[c][ix(g, g.n_filter + 1, j)];
-      if (sizeof(T) == 4 && L.p[c]) L.p[c][o] = L.p[c][ix(g, g.n_filter + 1, j)];
-    } else if (g.n_absorb > 0) {
-      const double x = (double)i + 0.5 * hs[c];
-      const double x0 = (double)(g.n_r - g.n_absorb);
-      if (x > x0) {
-        const double s = fmin((x - x0) / g.n_absorb, 1.0);
-        const double lam = s * s * s;
-        if (sizeof(T) == 4 && L.p[c]) {
-          const double v = (double)X.p[c][o] + (double)L.p[c][o];
-          const double w = v - lam * (v - X0.p[c][o]);
-          const T h = (T)w;
-          X.p[c][o] = h;
-          L.p[c][o] = (T)(w - (double)h);
+      for (int c = 0; c < 3; ++c) {
+        if (horizon) {
+          const int64_t src = ix(g, g.n_filter + 1, j);
+          X.p[c][o] = X.p[c][src];
+          if (comp) L.p[c][o] = L.p[c][src];
         } else {
-          X.p[c][o] = X.p[c][o] - lam * (X.p[c][o] - X0.p[c][o]);
+          const double x = (double)i + 0.5 * h1[c];
+          if (x > x0) {
+            const double sr = fmin((x - x0) / g.n_absorb, 1.0);
+            const double lam = sr * sr * sr;
+            if (comp) {
+              const double v = (double)X.p[c][o] + (double)L.p[c][o];
+              const double w = v - lam * (v - X0.p[c][o]);
+              const T h = (T)w;
+              X.p[c][o] = h;
+              L.p[c][o] = (T)(w - (double)h);
+            } else {
+              X.p[c][o] = X.p[c][o] - lam * (X.p[c][o] - X0.p[c][o]);
+            }
+          }
         }
       }
     }
   }
-}
-
-// Axis reflection (Sec. 3.3.3): r-components even, theta and phi components
-// odd; with zero_axis, the theta component of B (B^2) or the phi component of
-// D (D^3) vanishes on the axis rows.  half2[c] = staggering in x2.
-template <class T>
-__global__ void bc_axis_kernel(Grid g, TriT<T> X, TriT<T> L, int3 half2, int zero_comp) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
-  if (i >= g.n_r + g.ng) return;
-  const int hs[3] = {half2.x, half2.y, half2.z};
-  const double par[3] = {1.0, -1.0, -1.0};
+  __syncthreads();
+  if (threadIdx.x >= 3) return;
+  const int c = threadIdx.x;
+  const double par = c == 0 ? 1.0 : -1.0;
   const int n = g.n_th;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    T* C = X.p[c];
-    if (!hs[c]) {
-      if (c == zero_comp) {
-        C[ix(g, i, 0)] = 0.0;
-        C[ix(g, i, n)] = 0.0;
-        if (sizeof(T) == 4 && L.p[c]) {
-          L.p[c][ix(g, i, 0)] = 0.0;
-          L.p[c][ix(g, i, n)] = 0.0;
-        }
+  T* C = X.p[c];
+  if (!h2[c]) {
+    if (c == zero_comp) {
+      C[ix(g, i, 0)] = 0.0;
+      C[ix(g, i, n)] = 0.0;
+      if (comp) {
+        L.p[c][ix(g, i, 0)] = 0.0;
+        L.p[c][ix(g, i, n)] = 0.0;
       }
-      // node rows run 0..n: ng ghost rows below the axis, ng - 1 above
-      for (int k = 1; k <= g.ng; ++k) C[ix(g, i, -k)] = par[c] * C[ix(g, i, k)];
-      for (int k = 1; k < g.ng; ++k) C[ix(g, i, n + k)] = par[c] * C[ix(g, i, n - k)];
-    } else {
-      for (int k = 1; k <= g.ng; ++k) {
-        C[ix(g, i, -k)] = par[c] * C[ix(g, i, k - 1)];
-        C[ix(g, i, n - 1 + k)] = par[c] * C[ix(g, i, n - k)];
-      }
+    }
+    // node rows run 0..n: ng ghost rows below the axis, ng - 1 above
+    for (int k = 1; k <= g.ng; ++k) C[ix(g, i, -k)] = par * C[ix(g, i, k)];
+    for (int k = 1; k < g.ng; ++k) C[ix(g, i, n + k)] = par * C[ix(g, i, n - k)];
+  } else {
+    for (int k = 1; k <= g.ng; ++k) {
+      C[ix(g, i, -k)] = par * C[ix(g, i, k - 1)];
+      C[ix(g, i, n - 1 + k)] = par * C[ix(g, i, n - k)];
     }
   }
 }
 
 // ---------------------------------------------------------------- misc
-// elementwise over ncomp planes (whole planes incl. ghosts)
+// elementwise over whole planes (ghosts included)
 template <class T>
-__global__ void average_kernel(int64_t n, TriT<T> A, CTriT<T> B) {  // A <- (A + B) / 2
+__global__ void average_kernel(int64_t n, TriT<T> A, CTriT<T> B, TriT<T> C, CTriT<T> D) {
+  // A <- (A + B) / 2, C <- (C + D) / 2
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) A.p[c][k] = 0.5 * (A.p[c][k] + B.p[c][k]);
+  for (int c = 0; c < 3; ++c) {
+    A.p[c][k] = 0.5 * (A.p[c][k] + B.p[c][k]);
+    C.p[c][k] = 0.5 * (C.p[c][k] + D.p[c][k]);
+  }
 }
 
 template <class T>
@@ -284,37 +372,51 @@ __global__ void copy_kernel(int64_t n, TriT<T> A, CTriT<T> B) {  // A <- B
 }
 
 template <class T>
-__global__ void rotate_currents_kernel(int64_t n, TriT<T> J0, TriT<T> J) {  // J0 <- J, J <- 0
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    J0.p[c][k] = J.p[c][k];
-    J.p[c][k] = 0.0;
-  }
-}
-
-template <class T>
 __global__ void fill_kernel(int64_t n, T* __restrict__ p, double v) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
 }
 
-// One binomial pass (1,2,1)/4 x (1,2,1)/4 from S into X for i in
-// [1 - ng, n_r + ng - 2], j in [0, n_th - half2[c]].
+// Column j reflected across the axis for a component of x2-staggering hs
+// (node rows run 0..n, half rows 0..n-1); interior columns map to themselves.
+__device__ inline int axis_mirror(int j, int n, int hs) {
+  if (j < 0) return hs ? -1 - j : -j;
+  if (j > n - hs) return hs ? 2 * n - 1 - j : 2 * n - j;
+  return j;
+}
+
+// One binomial pass (1,2,1)/4 x (1,2,1)/4 of S into X (Sec. 3.3.4) over the
+// whole plane.  Ghost columns of S are read as their axis reflections
+// (parity par[c]) instead of being stored first; X receives the filtered
+// values for i in [1 - ng, n_r + ng - 2] on the evolved columns, the
+// reflections of S on its ghost columns, and S itself on the two outermost
+// rows.  Passes alternate between two plane sets.
 template <class T>
-__global__ void filter_kernel(Grid g, TriT<T> X, CTriT<T> S, int3 half2, int ncomp) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y + 1 - g.ng;
-  if (j > g.n_th || i > g.n_r + g.ng - 2) return;
+__global__ void filter_kernel(Grid g, TriT<T> X, CTriT<T> S, int3 half2, int3 parity, int ncomp) {
+  const PlaneIdx q = plane_idx(g);
+  if (!q.ok) return;
+  const int i = q.i, j = q.j, n = g.n_th;
   const int hs[3] = {half2.x, half2.y, half2.z};
-  const int64_t o = ix(g, i, j);
+  const int ps[3] = {parity.x, parity.y, parity.z};
+  const int64_t o = ix(g, i, j), ld = g.ld;
+  const bool inner = i >= 1 - g.ng && i <= g.n_r + g.ng - 2;
   for (int c = 0; c < ncomp; ++c) {
-    if (j > g.n_th - hs[c]) continue;
     const T* s = S.p[c];
-    const double r0 = s[o - g.ld - 1] + 2.0 * s[o - g.ld] + s[o - g.ld + 1];
-    const double r1 = s[o - 1] + 2.0 * s[o] + s[o + 1];
-    const double r2 = s[o + g.ld - 1] + 2.0 * s[o + g.ld] + s[o + g.ld + 1];
+    const double par = (double)ps[c];
+    if (j < 0 || j > n - hs[c]) {
+      X.p[c][o] = (T)(par * (double)s[ix(g, i, axis_mirror(j, n, hs[c]))]);
+      continue;
+    }
+    if (!inner) {
+      X.p[c][o] = s[o];
+      continue;
+    }
+    const int jm = axis_mirror(j - 1, n, hs[c]), jp = axis_mirror(j + 1, n, hs[c]);
+    const double pm = jm == j - 1 ? 1.0 : par, pp = jp == j + 1 ? 1.0 : par;
+    const int64_t om = ix(g, i, jm), op = ix(g, i, jp);
+    const double r0 = pm * (double)s[om - ld] + 2.0 * s[o - ld] + pp * (double)s[op - ld];
+    const double r1 = pm * (double)s[om] + 2.0 * s[o] + pp * (double)s[op];
+    const double r2 = pm * (double)s[om + ld] + 2.0 * s[o + ld] + pp * (double)s[op + ld];
     X.p[c][o] = 0.0625 * (r0 + 2.0 * r1 + r2);
   }
 }

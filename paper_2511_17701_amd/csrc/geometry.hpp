@@ -51,6 +51,8 @@ struct Tables {
   const double* __restrict__ r[2];
   const double* __restrict__ s[2];
   const double* __restrict__ c[2];
+  const double* __restrict__ ird[2];  // 1 / (dxi r dtheta) at integer / half-integer x1
+  const double* __restrict__ is[2];   // 1 / sin(theta) (0 on the axis) at integer / half-integer x2
   const float* __restrict__ rf;
   const float* __restrict__ sf;
   const float* __restrict__ cf;

@@ -145,14 +145,34 @@ const int3 kStagB1 = {0, 1, 1}, kStagB2 = {1, 0, 1};  // x1 / x2 staggering of B
 
 // boundaries of an updated triple: horizon layer + absorbing layer, then axis
 template <class T>
-grpic_status field_bc(grpic_ctx* c, TriT<T> X, TriT<T> L, CTriT<T> X0, bool is_B, hipStream_t s) {
+grpic_status field_bc(grpic_ctx* c, TriT<T> X, TriT<T> L, CTriT<T> X0, bool is_B, hipStream_t s,
+                      int radial = 1) {
   const Grid& g = c->g;
-  hipLaunchKernelGGL(bc_radial_kernel<T>, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, X,
-                     L, X0, is_B ? kStagB1 : kStagD1);
-  LAUNCH_CHECK("bc_radial");
-  hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, X, L,
-                     is_B ? kStagB2 : kStagD2, is_B ? 1 : 2);
-  LAUNCH_CHECK("bc_axis");
+  hipLaunchKernelGGL(bc_kernel<T>, dim3(g.n_r + 2 * g.ng), dim3(kB), 0, s, g, X, L, X0,
+                     is_B ? kStagB1 : kStagD1, is_B ? kStagB2 : kStagD2, is_B ? 1 : 2, radial);
+  LAUNCH_CHECK("bc");
+  return GRPIC_OK;
+}
+
+// n_f binomial passes over ncomp planes, alternating between A and B and
+// ending in A (an odd count starts with one copy A -> B).
+template <class T>
+grpic_status filter_passes(grpic_ctx* c, TriT<T> A, TriT<T> B, int ncomp, int3 half2, int3 parity,
+                           hipStream_t s) {
+  const Grid& g = c->g;
+  const int n = g.n_filter;
+  if (n % 2)
+    for (int k = 0; k < ncomp; ++k)
+      HIP_TRY(hipMemcpyAsync(B.p[k], A.p[k], g.plane * sizeof(T), hipMemcpyDeviceToDevice, s));
+  const dim3 gpl2 = grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng);
+  for (int p = 0; p < n; ++p) {
+    const bool from_A = (n - p) % 2 == 0;
+    TriT<T> dst = from_A ? B : A;
+    TriT<T> src = from_A ? A : B;
+    CTriT<T> srcc{{src.p[0], src.p[1], src.p[2]}};
+    hipLaunchKernelGGL(filter_kernel<T>, gpl2, kBlock2, 0, s, g, dst, srcc, half2, parity, ncomp);
+    LAUNCH_CHECK("filter");
+  }
   return GRPIC_OK;
 }
 
@@ -187,12 +207,9 @@ grpic_status wald_impl(grpic_ctx* c, const grpic_fields* F, double B0, hipStream
   hipLaunchKernelGGL(wald_kernel<T>, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, c->tab,
                      tri<T>(F->D), tri<T>(F->B), B0);
   LAUNCH_CHECK("wald");
-  hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g,
-                     tri<T>(F->D), none<T>(), kStagD2, 2);
-  LAUNCH_CHECK("bc_axis");
-  hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g,
-                     tri<T>(F->B), none<T>(), kStagB2, 1);
-  LAUNCH_CHECK("bc_axis");
+  grpic_status st;
+  if ((st = field_bc<T>(c, tri<T>(F->D), none<T>(), ctri<T>(F->Dinit), false, s, 0))) return st;
+  if ((st = field_bc<T>(c, tri<T>(F->B), none<T>(), ctri<T>(F->Binit), true, s, 0))) return st;
   void* const* dst[4] = {F->D0, F->B0, F->Dinit, F->Binit};
   void* const* src[4] = {F->D, F->B, F->D, F->B};
   for (int k = 0; k < 4; ++k) {
@@ -303,59 +320,44 @@ grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t sta
   const Grid& g = c->g;
   const dim3 gaux = grid2(g.n_r + 2, g.n_th + 1);   // i in [-1, n_r], j in [0, n_th]
   const dim3 gupd = grid2(g.n_r + 1, g.n_th + 1);   // i in [0, n_r],  j in [0, n_th]
-  const dim3 gpl(blocks(g.plane));
+  const dim3 gpl2 = grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng);  // whole plane
   if (stage == GRPIC_FIELDS_PRE_PUSH) {
-    hipLaunchKernelGGL(average_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->B0), ctri<T>(F->B));
+    // B0 <- (B0 + B)/2, D0 <- (D0 + D)/2; E from (B, D0); B0 += Faraday(E)
+    hipLaunchKernelGGL(average_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri<T>(F->B0),
+                       ctri<T>(F->B), tri<T>(F->D0), ctri<T>(F->D));
     LAUNCH_CHECK("average");
-    hipLaunchKernelGGL(average_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->D0), ctri<T>(F->D));
-    LAUNCH_CHECK("average");
-    hipLaunchKernelGGL(aux_e_kernel<T>, gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B), ctri<T>(F->D0),
-                       tri<T>(F->E));
+    hipLaunchKernelGGL((aux_kernel<T, true, false>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B),
+                       ctri<T>(F->D0), tri<T>(F->E), none<T>());
     LAUNCH_CHECK("aux_e");
-    hipLaunchKernelGGL(faraday_kernel<T>, gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->B0), none<T>(),
-                       ctri<T>(F->E));
+    hipLaunchKernelGGL((faraday_kernel<T, false>), gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->B0), none<T>(),
+                       ctri<T>(F->E), none<T>());
     LAUNCH_CHECK("faraday");
     return field_bc<T>(c, tri<T>(F->B0), none<T>(), ctri<T>(F->Binit), true, s);
   }
-  // current filter (n_f passes) on the freshly deposited J^{n+1/2}
-  for (int pass = 0; pass < g.n_filter; ++pass) {
-    hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g,
-                       tri<T>(F->J), none<T>(), kStagD2, -1);
-    LAUNCH_CHECK("bc_axis");
-    hipLaunchKernelGGL(copy_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->T), ctri<T>(F->J));
-    LAUNCH_CHECK("copy");
-    hipLaunchKernelGGL(filter_kernel<T>, grid2(g.n_r + 2 * g.ng - 2, g.n_th + 1), kBlock2, 0, s, g,
-                       tri<T>(F->J), ctri<T>(F->T), kStagD2, 3);
-    LAUNCH_CHECK("filter");
-  }
-  hipLaunchKernelGGL(aux_e_kernel<T>, gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B0), ctri<T>(F->D),
-                     tri<T>(F->E));
-  LAUNCH_CHECK("aux_e");
-  hipLaunchKernelGGL(aux_h_kernel<T>, gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B0), ctri<T>(F->D),
-                     tri<T>(F->H));
-  LAUNCH_CHECK("aux_h");
-  hipLaunchKernelGGL(copy_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->B0), ctri<T>(F->B));
-  LAUNCH_CHECK("copy");
-  hipLaunchKernelGGL(faraday_kernel<T>, gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->B), comp<T>(c, F->Bc),
-                     ctri<T>(F->E));
+  // current filter (n_f passes) on the freshly deposited J^{n+1/2}, T as the
+  // second plane set
+  if ((st = filter_passes<T>(c, tri<T>(F->J), tri<T>(F->T), 3, kStagD2, int3{1, -1, -1}, s))) return st;
+  // E, H from (B0, D); B0 <- B and B += Faraday(E)
+  hipLaunchKernelGGL((aux_kernel<T, true, true>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B0),
+                     ctri<T>(F->D), tri<T>(F->E), tri<T>(F->H));
+  LAUNCH_CHECK("aux_eh");
+  hipLaunchKernelGGL((faraday_kernel<T, true>), gpl2, kBlock2, 0, s, g, c->tab, tri<T>(F->B), comp<T>(c, F->Bc),
+                     ctri<T>(F->E), tri<T>(F->B0));
   LAUNCH_CHECK("faraday");
   if ((st = field_bc<T>(c, tri<T>(F->B), comp<T>(c, F->Bc), ctri<T>(F->Binit), true, s))) return st;
-  hipLaunchKernelGGL(ampere_kernel<T>, gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->D0), none<T>(),
-                     ctri<T>(F->H), ctri<T>(F->J0), ctri<T>(F->J), 0.5, 0.5, c->polar_k);
+  // D0 += Ampere(H, (J0 + J)/2)
+  hipLaunchKernelGGL((ampere_kernel<T, false>), gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->D0), none<T>(),
+                     ctri<T>(F->H), tri<T>(F->J0), tri<T>(F->J), 0.5, 0.5, c->polar_k, none<T>());
   LAUNCH_CHECK("ampere");
   if ((st = field_bc<T>(c, tri<T>(F->D0), none<T>(), ctri<T>(F->Dinit), false, s))) return st;
-  hipLaunchKernelGGL(aux_h_kernel<T>, gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B), ctri<T>(F->D0),
-                     tri<T>(F->H));
+  // H from (B, D0); D0 <- D, D += Ampere(H, J), J0 <- J, J <- 0
+  hipLaunchKernelGGL((aux_kernel<T, false, true>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B),
+                     ctri<T>(F->D0), none<T>(), tri<T>(F->H));
   LAUNCH_CHECK("aux_h");
-  hipLaunchKernelGGL(copy_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->D0), ctri<T>(F->D));
-  LAUNCH_CHECK("copy");
-  hipLaunchKernelGGL(ampere_kernel<T>, gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->D), comp<T>(c, F->Dc),
-                     ctri<T>(F->H), ctri<T>(F->J), ctri<T>(F->J), 1.0, 0.0, c->polar_k);
+  hipLaunchKernelGGL((ampere_kernel<T, true>), gpl2, kBlock2, 0, s, g, c->tab, tri<T>(F->D), comp<T>(c, F->Dc),
+                     ctri<T>(F->H), tri<T>(F->J), tri<T>(F->J0), 1.0, 0.0, c->polar_k, tri<T>(F->D0));
   LAUNCH_CHECK("ampere");
-  if ((st = field_bc<T>(c, tri<T>(F->D), comp<T>(c, F->Dc), ctri<T>(F->Dinit), false, s))) return st;
-  hipLaunchKernelGGL(rotate_currents_kernel<T>, gpl, dim3(kB), 0, s, g.plane, tri<T>(F->J0), tri<T>(F->J));
-  LAUNCH_CHECK("rotate_currents");
-  return GRPIC_OK;
+  return field_bc<T>(c, tri<T>(F->D), comp<T>(c, F->Dc), ctri<T>(F->Dinit), false, s);
 }
 
 template <class T>
@@ -376,15 +378,10 @@ grpic_status diagnostics_impl(grpic_ctx* c, const grpic_fields* F, const grpic_p
     hipLaunchKernelGGL(charge_kernel<T>, dim3(blocks(P->n)), dim3(kB), 0, s, g, arrays<T>(P), Q);
     LAUNCH_CHECK("charge");
   }
-  for (int pass = 0; pass < g.n_filter; ++pass) {
-    hipLaunchKernelGGL(scalar_axis_kernel<T>, dim3((g.n_r + 2 * g.ng + 63) / 64), dim3(64), 0, s, g, Q);
-    LAUNCH_CHECK("scalar_axis");
-    HIP_TRY(hipMemcpyAsync(tmp, Q, g.plane * sizeof(T), hipMemcpyDeviceToDevice, s));
-    TriT<T> X{{Q, nullptr, nullptr}};
-    CTriT<T> Sv{{tmp, nullptr, nullptr}};
-    hipLaunchKernelGGL(filter_kernel<T>, grid2(g.n_r + 2 * g.ng - 2, g.n_th + 1), kBlock2, 0, s, g, X, Sv,
-                       int3{0, 0, 0}, 1);
-    LAUNCH_CHECK("filter");
+  {
+    grpic_status st;
+    TriT<T> A{{Q, nullptr, nullptr}}, B{{tmp, nullptr, nullptr}};
+    if ((st = filter_passes<T>(c, A, B, 1, int3{0, 0, 0}, int3{1, 1, 1}, s))) return st;
   }
   if (gauss_res) {
     hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (T*)gauss_res, 0.0);
@@ -489,7 +486,7 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
 
   hipError_t e = hipGetDevice(&c->device);
   const int nr = p->n_r + 2 * p->n_ghost, nt = p->n_th + 2 * p->n_ghost;
-  const size_t nt_all = 2 * (size_t)nr + 4 * (size_t)nt;
+  const size_t nt_all = 4 * (size_t)nr + 6 * (size_t)nt;  // r, 1/(dxi r dtheta); sin, cos, 1/sin
   const size_t nf_all = (size_t)nr + 2 * (size_t)nt;  // float r, sin, cos at integer nodes
   const size_t bytes = nt_all * sizeof(double) + nf_all * sizeof(float);
   if (e == hipSuccess) e = hipMalloc(&c->tables, bytes);
@@ -523,9 +520,15 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   double* ps1 = ps0 + nt;
   double* pc0 = ps1 + nt;
   double* pc1 = pc0 + nt;
+  double* pq0 = pc1 + nt;  // 1 / (dxi r dtheta)
+  double* pq1 = pq0 + nr;
+  double* pi0 = pq1 + nr;  // 1 / sin
+  double* pi1 = pi0 + nt;
   for (int i = 0; i < nr; ++i) {
     pr0[i] = std::exp(g.xi_min + (double)(i - g.ng) * g.dxi);
     pr1[i] = std::exp(g.xi_min + ((double)(i - g.ng) + 0.5) * g.dxi);
+    pq0[i] = 1.0 / (g.dxi * pr0[i] * g.dth);
+    pq1[i] = 1.0 / (g.dxi * pr1[i] * g.dth);
   }
   for (int j = 0; j < nt; ++j) {
     const double t0 = (double)(j - g.ng) * g.dth, t1 = ((double)(j - g.ng) + 0.5) * g.dth;
@@ -533,6 +536,8 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     pc0[j] = std::cos(t0);
     ps1[j] = std::sin(t1);
     pc1[j] = std::cos(t1);
+    pi0[j] = (j == g.ng || j == g.ng + p->n_th) ? 0.0 : 1.0 / ps0[j];  // no inverse on the axis
+    pi1[j] = 1.0 / ps1[j];
   }
   float* hf = reinterpret_cast<float*>(h + nt_all);
   for (int i = 0; i < nr; ++i) hf[i] = (float)pr0[i];
@@ -555,6 +560,10 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   c->tab.s[1] = c->tab.s[0] + nt;
   c->tab.c[0] = c->tab.s[1] + nt;
   c->tab.c[1] = c->tab.c[0] + nt;
+  c->tab.ird[0] = c->tab.c[1] + nt;
+  c->tab.ird[1] = c->tab.ird[0] + nr;
+  c->tab.is[0] = c->tab.ird[1] + nr;
+  c->tab.is[1] = c->tab.is[0] + nt;
   const float* tf = reinterpret_cast<const float*>(c->tables + nt_all);
   c->tab.rf = tf;
   c->tab.sf = tf + nr;
