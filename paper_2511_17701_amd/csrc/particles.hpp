@@ -9,6 +9,8 @@
 // horizon region (cells i1 < i_fp64).
 #pragma once
 
+#include <type_traits>
+
 #include <climits>
 
 #include "geometry.hpp"
@@ -811,16 +813,41 @@ __device__ inline void add_runs(const Grid& g, bool act, const ContribT<T>& c, A
   }
 }
 
+// Adds the contributions of this lane alone through add(comp, i, j, value);
+// a particle that stays in its cell folds its second segment into the first.
+template <class T, class Add>
+__device__ inline void add_lane(bool act, const ContribT<T>& c, Add add) {
+  if (!act) return;
+  const bool stay = c.di == 0 && c.dj == 0;
+  const T z = (T)0;
+  add(0, c.ia, c.ja, c.j1[0] + (stay ? c.j1[2] : z));
+  add(0, c.ia, c.ja + 1, c.j1[1] + (stay ? c.j1[3] : z));
+  add(1, c.ia, c.ja, c.j2[0] + (stay ? c.j2[2] : z));
+  add(1, c.ia + 1, c.ja, c.j2[1] + (stay ? c.j2[3] : z));
+  if (!stay) {
+    const int ib = c.ia + c.di, jb = c.ja + c.dj;
+    add(0, ib, jb, c.j1[2]);
+    add(0, ib, jb + 1, c.j1[3]);
+    add(1, ib, jb, c.j2[2]);
+    add(1, ib + 1, jb, c.j2[3]);
+  }
+  const int km = c.ia + c.km, lm = c.ja + c.lm;
+  add(2, km, lm, c.j3[0]);
+  add(2, km, lm + 1, c.j3[1]);
+  add(2, km + 1, lm, c.j3[2]);
+  add(2, km + 1, lm + 1, c.j3[3]);
+}
+
 // Block-level deposit: the 4 x 4 footprints of the block's particles are
-// accumulated in an LDS tile, then added to the planes with one global atomic
-// per touched node.  A block whose footprint does not fit the tile (its cells
+// accumulated in an LDS tile, then the tile rows the footprint covers are
+// added to the planes with one global atomic per touched node.  A block whose footprint does not fit the tile (its cells
 // wrap from the end of one theta row to the next, or its particles have
 // spread) adds the run sums straight to the planes.  Every lane of the block
 // must call this.
 template <class T>
 __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp, bool act,
                                      const ContribT<T>& c) {
-  __shared__ T tile[3][kTI][kTJ];
+  __shared__ __align__(16) T tile[3][kTI][kTJ];
   __shared__ int bound[4][kDepBlock / 64];
   // block footprint: union of [ia-1, ia+2] x [ja-1, ja+2]
   int v[4] = {act ? c.ia - 1 : INT_MAX, act ? -(c.ia + 2) : INT_MAX, act ? c.ja - 1 : INT_MAX,
@@ -831,9 +858,14 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
     for (int off = 32; off > 0; off >>= 1) v[q] = min(v[q], __shfl_down(v[q], off, 64));
     if (lane == 0) bound[q][wv] = v[q];
   }
-  // zero the tile while the bounds settle
+  // zero the tile (16-byte stores) while the bounds settle
   T* flat = &tile[0][0][0];
-  for (int e = threadIdx.x; e < 3 * kTI * kTJ; e += kDepBlock) flat[e] = (T)0;
+  {
+    constexpr int kVec = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    V* fv = reinterpret_cast<V*>(flat);
+    for (int e = threadIdx.x; e < 3 * kTI * kTJ / kVec; e += kDepBlock) fv[e] = V{};
+  }
   __syncthreads();
   int b[4];
 #pragma unroll
@@ -848,13 +880,23 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
     add_runs(g, act, c, [&](int comp, int i, int j, T val) { atomic_add(cp.J[comp] + ix(g, i, j), val); });
     return;
   }
-  add_runs(g, act, c, [&](int comp, int i, int j, T val) { atomicAdd(&tile[comp][i - i0][j - j0], val); });
+  // into the tile: FP64 lanes add their own values (ds_add_f64 absorbs the
+  // same-address conflicts of a cell's run faster than the cross-lane sums
+  // cost); FP32 lanes add run sums
+  const auto to_tile = [&](int comp, int i, int j, T val) { atomicAdd(&tile[comp][i - i0][j - j0], val); };
+  if (sizeof(T) == 8)
+    add_lane(act, c, to_tile);
+  else
+    add_runs(g, act, c, to_tile);
   __syncthreads();
-  for (int e = threadIdx.x; e < 3 * kTI * kTJ; e += kDepBlock) {
-    const T val = flat[e];
-    if (val != (T)0) {
-      const int comp = e / (kTI * kTJ), rem = e % (kTI * kTJ);
-      atomic_add(cp.J[comp] + ix(g, i0 + rem / kTJ, j0 + rem % kTJ), val);
+  // flush the footprint rows only
+  const int rows = (i1 - i0 + 1) * kTJ;
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    const T* tc = &tile[comp][0][0];
+    for (int e = threadIdx.x; e < rows; e += kDepBlock) {
+      const T val = tc[e];
+      if (val != (T)0) atomic_add(cp.J[comp] + ix(g, i0 + e / kTJ, j0 + e % kTJ), val);
     }
   }
 }
