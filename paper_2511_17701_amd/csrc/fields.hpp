@@ -324,28 +324,24 @@ __global__ void bc_kernel(Grid g, TriT<T> X, TriT<T> L, CTriT<T> X0, int3 half1,
     }
   }
   __syncthreads();
-  if (threadIdx.x >= 3) return;
-  const int c = threadIdx.x;
-  const double par = c == 0 ? 1.0 : -1.0;
+  // one lane per (component, ghost column): the 2 ng ghost columns of each
+  // component, each the reflection of its mirror column (node rows run 0..n,
+  // half rows 0..n-1); the mirrors are interior columns, which this pass only
+  // zeroes at j = 0, n for zero_comp, and never reads
+  const int t = threadIdx.x;
+  if (t >= 3 * 2 * g.ng) return;
+  const int c = t / (2 * g.ng), q = t % (2 * g.ng);
   const int n = g.n_th;
   T* C = X.p[c];
-  if (!h2[c]) {
-    if (c == zero_comp) {
-      C[ix(g, i, 0)] = 0.0;
-      C[ix(g, i, n)] = 0.0;
-      if (comp) {
-        L.p[c][ix(g, i, 0)] = 0.0;
-        L.p[c][ix(g, i, n)] = 0.0;
-      }
-    }
-    // node rows run 0..n: ng ghost rows below the axis, ng - 1 above
-    for (int k = 1; k <= g.ng; ++k) C[ix(g, i, -k)] = par * C[ix(g, i, k)];
-    for (int k = 1; k < g.ng; ++k) C[ix(g, i, n + k)] = par * C[ix(g, i, n - k)];
-  } else {
-    for (int k = 1; k <= g.ng; ++k) {
-      C[ix(g, i, -k)] = par * C[ix(g, i, k - 1)];
-      C[ix(g, i, n - 1 + k)] = par * C[ix(g, i, n - k)];
-    }
+  const int j = q < g.ng ? -1 - q : n - h2[c] + 1 + (q - g.ng);  // ghost column
+  const bool exists = j < n + g.ng;
+  const int m = j < 0 ? (h2[c] ? -1 - j : -j) : (h2[c] ? 2 * n - 1 - j : 2 * n - j);
+  const T v = exists ? C[ix(g, i, m)] : (T)0;
+  if (exists) C[ix(g, i, j)] = (c == 0 ? 1.0 : -1.0) * v;
+  if (!h2[c] && c == zero_comp && (q == 0 || q == g.ng)) {
+    const int jz = q == 0 ? 0 : n;
+    C[ix(g, i, jz)] = 0.0;
+    if (comp) L.p[c][ix(g, i, jz)] = 0.0;
   }
 }
 

@@ -855,8 +855,8 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    for (int off = 32; off > 0; off >>= 1) v[q] = min(v[q], __shfl_down(v[q], off, 64));
-    if (lane == 0) bound[q][wv] = v[q];
+    const int m = __reduce_min_sync(~0ull, v[q]);  // wavefront minimum
+    if (lane == 0) bound[q][wv] = m;
   }
   // zero the tile (16-byte stores) while the bounds settle
   T* flat = &tile[0][0][0];

@@ -121,30 +121,52 @@ __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArray
                                                            int* __restrict__ off) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int key = k < S.n ? sort_key(g, S, k) : -1;
+  const bool live = key >= 0 && key < g.n_r * g.n_th;
+  // the slot is read before its cell offset is claimed, so that the loads
+  // overlap the atomic's round trip
+  int i1 = 0, i2 = 0, i1p = 0, i2p = 0;
+  T dx1 = 0, dx2 = 0, u1 = 0, u2 = 0, u3 = 0, w = 0, phi = 0, dx1p = 0, dx2p = 0;
+  uint8_t tag = 0;
+  if (live) {
+    i1 = S.i1[k];
+    i2 = S.i2[k];
+    dx1 = S.dx1[k];
+    dx2 = S.dx2[k];
+    u1 = S.u1[k];
+    u2 = S.u2[k];
+    u3 = S.u3[k];
+    w = S.w[k];
+    phi = S.phi[k];
+    i1p = S.i1p[k];
+    i2p = S.i2p[k];
+    dx1p = S.dx1p[k];
+    dx2p = S.dx2p[k];
+    tag = S.tag[k];
+  }
   const Run r = wave_run(key);
   int base = 0;
   if (r.first && key >= 0) base = atomicAdd(off + key, r.len);
   base = __shfl(base, r.head, 64);
   if (key < 0) return;
   const int64_t o = (int64_t)base + ((threadIdx.x & 63) - r.head);
-  if (key == g.n_r * g.n_th) {
+  if (!live) {
     D.tag[o] = 0;
     return;
   }
-  D.i1[o] = S.i1[k];
-  D.i2[o] = S.i2[k];
-  D.dx1[o] = S.dx1[k];
-  D.dx2[o] = S.dx2[k];
-  D.u1[o] = S.u1[k];
-  D.u2[o] = S.u2[k];
-  D.u3[o] = S.u3[k];
-  D.w[o] = S.w[k];
-  D.phi[o] = S.phi[k];
-  D.i1p[o] = S.i1p[k];
-  D.i2p[o] = S.i2p[k];
-  D.dx1p[o] = S.dx1p[k];
-  D.dx2p[o] = S.dx2p[k];
-  D.tag[o] = S.tag[k];
+  D.i1[o] = i1;
+  D.i2[o] = i2;
+  D.dx1[o] = dx1;
+  D.dx2[o] = dx2;
+  D.u1[o] = u1;
+  D.u2[o] = u2;
+  D.u3[o] = u3;
+  D.w[o] = w;
+  D.phi[o] = phi;
+  D.i1p[o] = i1p;
+  D.i2p[o] = i2p;
+  D.dx1p[o] = dx1p;
+  D.dx2p[o] = dx2p;
+  D.tag[o] = tag;
 }
 
 }  // namespace grpic
