@@ -85,23 +85,40 @@ diag_particles_kernel(Grid g, ParticleArraysT<T> P, double B0, T* __restrict__ E
   }
 }
 
-// first-order charge sqrt(h) rho = sum q S at the nodes around the current positions
+// first-order charge sqrt(h) rho = sum q S at the nodes around the current
+// positions; the lanes of a wavefront that share a cell add their run sum
+// once (every lane reaches the run sums: no early return before them)
 template <class T>
-__global__ void charge_kernel(Grid g, ParticleArraysT<T> P, T* __restrict__ Q) {
+__global__ void __launch_bounds__(256) charge_kernel(Grid g, ParticleArraysT<T> P, T* __restrict__ Q) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= P.n) return;
-  const uint8_t t = P.tag[k];
-  if (!is_live(t)) return;
-  const double sg = species_sign(t);
-  if (sg == 0.0) return;
-  const double q = sg * g.charge_scale * P.w[k];
-  const double w1 = P.dx1[k], w2 = P.dx2[k];
-  if (!in_deposit_range(g, P.i1[k], w1, P.i2[k], w2)) return;
-  T* p = Q + ix(g, P.i1[k], P.i2[k]);
-  atomic_add(p, (T)(q * (1.0 - w1) * (1.0 - w2)));
-  atomic_add(p + 1, (T)(q * (1.0 - w1) * w2));
-  atomic_add(p + g.ld, (T)(q * w1 * (1.0 - w2)));
-  atomic_add(p + g.ld + 1, (T)(q * w1 * w2));
+  bool act = false;
+  int i1 = 0, i2 = 0;
+  double q = 0.0, w1 = 0.0, w2 = 0.0;
+  if (k < P.n) {
+    const uint8_t t = P.tag[k];
+    const double sg = is_live(t) ? species_sign(t) : 0.0;
+    if (sg != 0.0) {
+      i1 = P.i1[k];
+      i2 = P.i2[k];
+      w1 = P.dx1[k];
+      w2 = P.dx2[k];
+      act = in_deposit_range(g, i1, w1, i2, w2);
+      q = sg * g.charge_scale * P.w[k];
+    }
+  }
+  const T z = (T)0;
+  const Runs r = runs_of(act ? (i1 + 2) * g.ld + (i2 + 2) : -1);
+  const T s00 = run_sum(act ? (T)(q * (1.0 - w1) * (1.0 - w2)) : z, r);
+  const T s01 = run_sum(act ? (T)(q * (1.0 - w1) * w2) : z, r);
+  const T s10 = run_sum(act ? (T)(q * w1 * (1.0 - w2)) : z, r);
+  const T s11 = run_sum(act ? (T)(q * w1 * w2) : z, r);
+  if (act && r.head) {
+    T* p = Q + ix(g, i1, i2);
+    atomic_add(p, s00);
+    atomic_add(p + 1, s01);
+    atomic_add(p + g.ld, s10);
+    atomic_add(p + g.ld + 1, s11);
+  }
 }
 
 // residual div D - 4 pi rho at nodes i in [n_f + 2, n_r - n_absorb), j in [1, n_th)
