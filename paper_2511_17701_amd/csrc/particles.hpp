@@ -653,6 +653,7 @@ __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 // gamma goes to the four nodes around the path midpoint.
 constexpr int kDepBlock = 256;
 constexpr int kTI = 8, kTJ = 48;
+constexpr int kDepRep = 2;  // copies of the deposit tile
 
 template <class T>
 struct ContribT {
@@ -838,16 +839,20 @@ __device__ inline void add_lane(bool act, const ContribT<T>& c, Add add) {
   add(2, km + 1, lm + 1, c.j3[3]);
 }
 
-// Block-level deposit: the 4 x 4 footprints of the block's particles are
-// accumulated in an LDS tile, then the tile rows the footprint covers are
-// added to the planes with one global atomic per touched node.  A block whose footprint does not fit the tile (its cells
-// wrap from the end of one theta row to the next, or its particles have
-// spread) adds the run sums straight to the planes.  Every lane of the block
-// must call this.
+// Block-level deposit: every lane adds its contributions (12 values, 8 when it
+// stays in its cell) to an LDS tile over the block's footprint with LDS
+// atomics, then the tile rows the footprint covers are added to the planes
+// with one global atomic per touched node.  A block whose footprint does not
+// fit the tile (its cells wrap from the end of one theta row to the next, or
+// its particles have spread) adds wavefront run sums straight to the planes.
+// Every lane of the block must call this.
 template <class T>
 __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp, bool act,
                                      const ContribT<T>& c) {
-  __shared__ __align__(16) T tile[3][kTI][kTJ];
+  // kRep copies of the tile: lane l adds into copy l % kRep, which divides the
+  // same-address conflicts of a cell's run of lanes by kRep
+  constexpr int kRep = kDepRep;
+  __shared__ __align__(16) T tile[kRep][3][kTI][kTJ];
   __shared__ int bound[4][kDepBlock / 64];
   // block footprint: union of [ia-1, ia+2] x [ja-1, ja+2]
   int v[4] = {act ? c.ia - 1 : INT_MAX, act ? -(c.ia + 2) : INT_MAX, act ? c.ja - 1 : INT_MAX,
@@ -859,12 +864,11 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
     if (lane == 0) bound[q][wv] = m;
   }
   // zero the tile (16-byte stores) while the bounds settle
-  T* flat = &tile[0][0][0];
   {
     constexpr int kVec = 16 / sizeof(T);
     using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
-    V* fv = reinterpret_cast<V*>(flat);
-    for (int e = threadIdx.x; e < 3 * kTI * kTJ / kVec; e += kDepBlock) fv[e] = V{};
+    V* fv = reinterpret_cast<V*>(&tile[0][0][0][0]);
+    for (int e = threadIdx.x; e < kRep * 3 * kTI * kTJ / kVec; e += kDepBlock) fv[e] = V{};
   }
   __syncthreads();
   int b[4];
@@ -880,22 +884,17 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
     add_runs(g, act, c, [&](int comp, int i, int j, T val) { atomic_add(cp.J[comp] + ix(g, i, j), val); });
     return;
   }
-  // into the tile: FP64 lanes add their own values (ds_add_f64 absorbs the
-  // same-address conflicts of a cell's run faster than the cross-lane sums
-  // cost); FP32 lanes add run sums
-  const auto to_tile = [&](int comp, int i, int j, T val) { atomicAdd(&tile[comp][i - i0][j - j0], val); };
-  if (sizeof(T) == 8)
-    add_lane(act, c, to_tile);
-  else
-    add_runs(g, act, c, to_tile);
+  const int rep = lane % kRep;
+  add_lane(act, c, [&](int comp, int i, int j, T val) { atomicAdd(&tile[rep][comp][i - i0][j - j0], val); });
   __syncthreads();
-  // flush the footprint rows only
+  // flush the footprint rows only, the copies summed in a fixed order
   const int rows = (i1 - i0 + 1) * kTJ;
 #pragma unroll
   for (int comp = 0; comp < 3; ++comp) {
-    const T* tc = &tile[comp][0][0];
     for (int e = threadIdx.x; e < rows; e += kDepBlock) {
-      const T val = tc[e];
+      T val = (&tile[0][comp][0][0])[e];
+#pragma unroll
+      for (int r = 1; r < kRep; ++r) val += (&tile[r][comp][0][0])[e];
       if (val != (T)0) atomic_add(cp.J[comp] + ix(g, i0 + e / kTJ, j0 + e % kTJ), val);
     }
   }
