@@ -38,10 +38,10 @@ PEAK_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector (= non-packed FP32 vector)
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per particle of the fused pass (FP64): reads tag (1),
-# i1 i2 (8), dx1 dx2 (16), u (24), w (8), phi (8) = 65; writes previous
-# position (24), i dx (24), u (24), phi (8), tag (1) = 81.  FP32 form: 4-byte
-# reals: reads 1 + 8 + 8 + 12 + 4 + 4 = 37, writes 16 + 16 + 12 + 4 + 1 = 49.
-FUSED_BYTES = {"fp64": 65 + 81, "fp32": 37 + 49}
+# i1 i2 (8), dx1 dx2 (16), u (24), w (8), phi (8) = 65; writes i dx (24),
+# u (24), phi (8), tag (1) = 57.  FP32 form: 4-byte reals: reads
+# 1 + 8 + 8 + 12 + 4 + 4 = 37, writes 16 + 12 + 4 + 1 = 33.
+FUSED_BYTES = {"fp64": 65 + 57, "fp32": 37 + 33}
 
 
 def parse():

@@ -34,7 +34,8 @@
  * Particle storage (Sec. 3, code units): structure of arrays; position = cell
  * index (i1, i2) plus offset (dx1, dx2) in [0, 1); covariant code components
  * u_1 = u_r dr/dx1, u_2 = u_theta dth/dx2, u_3 = u_phi; previous position
- * (i1p, i2p, dx1p, dx2p) written by the push for the deposit (Sec. 3.2).
+ * (i1p, i2p, dx1p, dx2p): scratch written by grpic_push for grpic_deposit
+ * (Sec. 3.2), not written by grpic_push_deposit and not carried by grpic_sort.
  * tag: 0 = empty slot, 1 = positron (q/m = +1), 2 = electron (q/m = -1),
  * 3 = neutral test particle (q = 0); bit 0x80 = left the domain this step
  * (deposited once more, emptied by the next push); tag 0x40 = dropped by a
@@ -178,8 +179,8 @@ grpic_status grpic_deposit(grpic_ctx* ctx, const grpic_particles* P, const grpic
 /* grpic_push followed by grpic_deposit in one pass over the particles (same
  * arguments, same results up to rounding order): the deposit takes each move
  * from registers and J^3 from the push's own evaluation of the phi velocity
- * at the path midpoint (Sec. 3.1 step 10, Sec. 3.2), so the previous
- * positions are written but not read back. */
+ * at the path midpoint (Sec. 3.1 step 10, Sec. 3.2); the previous-position
+ * arrays are left as they were. */
 grpic_status grpic_push_deposit(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,
                                 void* stream);
 
@@ -210,7 +211,9 @@ grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t 
 /* Cell sort (a layout device, not part of the paper's method): writes the
  * slots of src into dst ordered by cell c = i1 * n_th + i2; empty slots and
  * slots with the leaving bit (already deposited) go last, emptied (tag 0).
- * The order of particles within one cell is unspecified.  src and dst must
+ * The order of particles within one cell is unspecified.  The previous-
+ * position arrays of dst are left as they were (call it after the deposit
+ * that reads them, not between grpic_push and grpic_deposit).  src and dst must
  * have the same n and must not alias.  If n_live is non-null, waits for the
  * stream and stores the number of live slots (they occupy dst[0 .. n_live)).
  * Uses scratch owned by the context (n_r n_th + 1 counters). */

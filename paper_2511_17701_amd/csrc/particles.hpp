@@ -343,7 +343,7 @@ struct Move {
 
 // FP64 particle update (Sec. 3.1 steps 1-11) of slot k; writes the new state
 // and returns the move for the deposit.
-template <int SER>
+template <int SER, bool kPrev = true>
 __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const GatherPlanesT<double>& fp,
                                         const ParticleArrays& P, int64_t k) {
   Move<double> mv;
@@ -362,10 +362,12 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
     return mv;
   }
   double u1 = P.u1[k], u2 = P.u2[k], u3 = P.u3[k];
-  P.i1p[k] = i1;
-  P.i2p[k] = i2;
-  P.dx1p[k] = dx1;
-  P.dx2p[k] = dx2;
+  if (kPrev) {  // the previous position, for a separate deposit
+    P.i1p[k] = i1;
+    P.i2p[k] = i2;
+    P.dx1p[k] = dx1;
+    P.dx2p[k] = dx2;
+  }
   mv.ia = i1;
   mv.ja = i2;
   mv.xa = dx1;
@@ -469,7 +471,7 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
 }
 
 // Single-precision form of the same update (see the file comment).
-template <int SER>
+template <int SER, bool kPrev = true>
 __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, const GatherPlanesT<float>& fp,
                                            const ParticleArraysT<float>& P, int64_t k) {
   Move<float> mv;
@@ -488,10 +490,12 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
     return mv;
   }
   float u1 = P.u1[k], u2 = P.u2[k], u3 = P.u3[k];
-  P.i1p[k] = i1;
-  P.i2p[k] = i2;
-  P.dx1p[k] = dx1;
-  P.dx2p[k] = dx2;
+  if (kPrev) {  // the previous position, for a separate deposit
+    P.i1p[k] = i1;
+    P.i2p[k] = i2;
+    P.dx1p[k] = dx1;
+    P.dx2p[k] = dx2;
+  }
   mv.ia = i1;
   mv.ja = i2;
   mv.xa = dx1;
@@ -929,11 +933,12 @@ __global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, 
 }
 
 // Push and deposit in one pass: the deposit takes the move from registers and
-// J^3 from the push's own midpoint metric.
+// J^3 from the push's own midpoint metric; the previous position is not
+// stored.
 template <int SER>
 __global__ void __launch_bounds__(kDepBlock) GRPIC_FP64_PUSH_OCCUPANCY
 push_deposit_kernel(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp) {
-  const Move<double> mv = push_one<SER>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const Move<double> mv = push_one<SER, false>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   ContribT<double> c;
   const bool act = make_contrib<double, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
@@ -943,7 +948,7 @@ template <int SER>
 __global__ void __launch_bounds__(kDepBlock) push_deposit_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
                                                                      ParticleArraysT<float> P,
                                                                      CurrentPlanesT<float> cp) {
-  const Move<float> mv = push_one_f32<SER>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const Move<float> mv = push_one_f32<SER, false>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   ContribT<float> c;
   const bool act = make_contrib<float, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);

@@ -114,7 +114,8 @@ __global__ void scan_add_kernel(int* __restrict__ a, int64_t n, const int* __res
 }
 
 // Moves slot k of S to its cell's next free slots in D; emptied slots get tag
-// 0.  A run of equal keys in a wavefront takes consecutive slots in lane order;
+// 0.  The previous position (scratch between a push and its deposit) is not
+// carried.  A run of equal keys in a wavefront takes consecutive slots in lane order;
 // the order of runs of one cell follows the order of the atomics.
 template <class T>
 __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArraysT<T> S, ParticleArraysT<T> D,
@@ -124,8 +125,8 @@ __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArray
   const bool live = key >= 0 && key < g.n_r * g.n_th;
   // the slot is read before its cell offset is claimed, so that the loads
   // overlap the atomic's round trip
-  int i1 = 0, i2 = 0, i1p = 0, i2p = 0;
-  T dx1 = 0, dx2 = 0, u1 = 0, u2 = 0, u3 = 0, w = 0, phi = 0, dx1p = 0, dx2p = 0;
+  int i1 = 0, i2 = 0;
+  T dx1 = 0, dx2 = 0, u1 = 0, u2 = 0, u3 = 0, w = 0, phi = 0;
   uint8_t tag = 0;
   if (live) {
     i1 = S.i1[k];
@@ -137,10 +138,6 @@ __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArray
     u3 = S.u3[k];
     w = S.w[k];
     phi = S.phi[k];
-    i1p = S.i1p[k];
-    i2p = S.i2p[k];
-    dx1p = S.dx1p[k];
-    dx2p = S.dx2p[k];
     tag = S.tag[k];
   }
   const Run r = wave_run(key);
@@ -162,10 +159,6 @@ __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArray
   D.u3[o] = u3;
   D.w[o] = w;
   D.phi[o] = phi;
-  D.i1p[o] = i1p;
-  D.i2p[o] = i2p;
-  D.dx1p[o] = dx1p;
-  D.dx2p[o] = dx2p;
   D.tag[o] = tag;
 }
 

@@ -189,7 +189,8 @@ def test_fp32_push_deposit_fused_equals_separate(G):
         c32.push_deposit(Fb, Pb)
     torch.cuda.synchronize()
     for k in P32:
-        assert torch.equal(P32[k], Pb[k]), k
+        if k not in ("i1p", "i2p", "dx1p", "dx2p"):  # not written by the fused pass
+            assert torch.equal(P32[k], Pb[k]), k
     errs = plane_errors(Fb, F32.double(), [18, 19, 20])
     print(f"\n[fp32] fused vs separate J rel max err: {errs}")
     assert max(errs) <= 1e-5
