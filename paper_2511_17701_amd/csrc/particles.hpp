@@ -658,6 +658,10 @@ __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 constexpr int kDepBlock = 256;
 constexpr int kTI = 8, kTJ = 48;
 constexpr int kDepRep = 2;  // copies of the deposit tile
+// lane-folding levels before the LDS atomics: quads in FP32, pairs in FP64
+// (measured: FP32 LDS atomics are the costlier, FP64 gains nothing past pairs)
+template <class T>
+constexpr int dep_fold() { return sizeof(T) == 4 ? 2 : 1; }
 
 template <class T>
 struct ContribT {
@@ -818,43 +822,105 @@ __device__ inline void add_runs(const Grid& g, bool act, const ContribT<T>& c, A
   }
 }
 
-// Adds the contributions of this lane alone through add(comp, i, j, value);
-// a particle that stays in its cell folds its second segment into the first.
-template <class T, class Add>
-__device__ inline void add_lane(bool act, const ContribT<T>& c, Add add) {
-  if (!act) return;
-  const bool stay = c.di == 0 && c.dj == 0;
+// Lane exchange inside aligned groups by DPP quad permutation (a VALU move, no
+// LDS traffic): level 1 swaps lanes 2k <-> 2k+1, level 2 swaps the pairs of a
+// quad (4k, 4k+1 <-> 4k+2, 4k+3).  Every lane of the wavefront must execute it.
+template <int L>
+__device__ inline int lane_swap(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, L == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int L>
+__device__ inline float lane_swap(float v) {
+  return __int_as_float(lane_swap<L>(__float_as_int(v)));
+}
+template <int L>
+__device__ inline double lane_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_swap<L>((int)(b & 0xffffffffll)), hi = lane_swap<L>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// Adds the contributions of each lane through add(comp, i, j, value) (absolute
+// node indices; a particle that stays in its cell folds its second segment into
+// the first), with the segment-1 and J^3 values of neighbouring lanes that
+// share the same nodes summed first (kFold levels: pairs, then quads): the first lane
+// of a folded group adds the group's sum, the others skip those adds.  Cell-
+// sorted particles put runs of one cell in consecutive lanes, so this divides
+// the LDS atomics on one address by up to 2^kFold.  Every lane of the
+// wavefront must call this (inactive lanes with act = false).
+template <class T, int kFold, class Add>
+__device__ inline void add_lane_folded(const Grid& g, bool act, const ContribT<T>& c, Add add) {
+  const int lane = threadIdx.x & 63;
   const T z = (T)0;
-  add(0, c.ia, c.ja, c.j1[0] + (stay ? c.j1[2] : z));
-  add(0, c.ia, c.ja + 1, c.j1[1] + (stay ? c.j1[3] : z));
-  add(1, c.ia, c.ja, c.j2[0] + (stay ? c.j2[2] : z));
-  add(1, c.ia + 1, c.ja, c.j2[1] + (stay ? c.j2[3] : z));
-  if (!stay) {
+  const bool stay = act && c.di == 0 && c.dj == 0;
+  const int km = c.ia + c.km, lm = c.ja + c.lm;
+  T a[4] = {act ? c.j1[0] + (stay ? c.j1[2] : z) : z, act ? c.j1[1] + (stay ? c.j1[3] : z) : z,
+            act ? c.j2[0] + (stay ? c.j2[2] : z) : z, act ? c.j2[1] + (stay ? c.j2[3] : z) : z};
+  T m[4] = {act ? c.j3[0] : z, act ? c.j3[1] : z, act ? c.j3[2] : z, act ? c.j3[3] : z};
+  const int ka = act ? (c.ia + 2) * g.ld + (c.ja + 2) : -1;
+  const int kb = act ? (km + 2) * g.ld + (lm + 2) : -1;
+  bool own_a = act, own_m = act;
+  bool fa = false, fm = false;  // this lane's pair folded
+  if (kFold >= 1) {
+    const bool first = (lane & 1) == 0;
+    fa = ka >= 0 && lane_swap<1>(ka) == ka;
+    fm = kb >= 0 && lane_swap<1>(kb) == kb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T oa = lane_swap<1>(a[q]), om = lane_swap<1>(m[q]);
+      if (fa && first) a[q] += oa;
+      if (fm && first) m[q] += om;
+    }
+    if (fa && !first) own_a = false;
+    if (fm && !first) own_m = false;
+  }
+  if (kFold >= 2) {
+    const bool first = (lane & 2) == 0;
+    const bool qa = fa && lane_swap<2>((int)fa) != 0 && lane_swap<2>(ka) == ka;
+    const bool qm = fm && lane_swap<2>((int)fm) != 0 && lane_swap<2>(kb) == kb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T oa = lane_swap<2>(a[q]), om = lane_swap<2>(m[q]);
+      if (qa && first) a[q] += oa;
+      if (qm && first) m[q] += om;
+    }
+    if (qa && !first) own_a = false;
+    if (qm && !first) own_m = false;
+  }
+  if (own_a) {
+    add(0, c.ia, c.ja, a[0]);
+    add(0, c.ia, c.ja + 1, a[1]);
+    add(1, c.ia, c.ja, a[2]);
+    add(1, c.ia + 1, c.ja, a[3]);
+  }
+  if (act && !stay) {
     const int ib = c.ia + c.di, jb = c.ja + c.dj;
     add(0, ib, jb, c.j1[2]);
     add(0, ib, jb + 1, c.j1[3]);
     add(1, ib, jb, c.j2[2]);
     add(1, ib + 1, jb, c.j2[3]);
   }
-  const int km = c.ia + c.km, lm = c.ja + c.lm;
-  add(2, km, lm, c.j3[0]);
-  add(2, km, lm + 1, c.j3[1]);
-  add(2, km + 1, lm, c.j3[2]);
-  add(2, km + 1, lm + 1, c.j3[3]);
+  if (own_m) {
+    add(2, km, lm, m[0]);
+    add(2, km, lm + 1, m[1]);
+    add(2, km + 1, lm, m[2]);
+    add(2, km + 1, lm + 1, m[3]);
+  }
 }
 
-// Block-level deposit: every lane adds its contributions (12 values, 8 when it
-// stays in its cell) to an LDS tile over the block's footprint with LDS
-// atomics, then the tile rows the footprint covers are added to the planes
-// with one global atomic per touched node.  A block whose footprint does not
+// Block-level deposit: the lanes add their contributions (12 values, 8 when a
+// particle stays in its cell; neighbouring lanes on the same nodes folded
+// first) to an LDS tile over the block's footprint with LDS atomics, then the
+// tile rows the footprint covers are added to the planes with one global
+// atomic per touched node.  A block whose footprint does not
 // fit the tile (its cells wrap from the end of one theta row to the next, or
 // its particles have spread) adds wavefront run sums straight to the planes.
 // Every lane of the block must call this.
 template <class T>
 __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp, bool act,
                                      const ContribT<T>& c) {
-  // kRep copies of the tile: lane l adds into copy l % kRep, which divides the
-  // same-address conflicts of a cell's run of lanes by kRep
+  // kRep copies of the tile: the adding lanes alternate between copies, which
+  // divides the same-address conflicts of a cell's run of lanes by kRep
   constexpr int kRep = kDepRep;
   __shared__ __align__(16) T tile[kRep][3][kTI][kTJ];
   __shared__ int bound[4][kDepBlock / 64];
@@ -888,8 +954,9 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
     add_runs(g, act, c, [&](int comp, int i, int j, T val) { atomic_add(cp.J[comp] + ix(g, i, j), val); });
     return;
   }
-  const int rep = lane % kRep;
-  add_lane(act, c, [&](int comp, int i, int j, T val) { atomicAdd(&tile[rep][comp][i - i0][j - j0], val); });
+  const int rep = (lane >> dep_fold<T>()) % kRep;
+  add_lane_folded<T, dep_fold<T>()>(g, act, c,
+                               [&](int comp, int i, int j, T val) { atomicAdd(&tile[rep][comp][i - i0][j - j0], val); });
   __syncthreads();
   // flush the footprint rows only, the copies summed in a fixed order
   const int rows = (i1 - i0 + 1) * kTJ;
