@@ -299,7 +299,8 @@ grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_par
   const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
   const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
   const ParticleArraysT<T> a = arrays<T>(src), b = arrays<T>(dst);
-  hipLaunchKernelGGL(sort_count_kernel<T>, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, c->sort_off);
+  const dim3 gsort((unsigned)((src->n + (int64_t)kB * kSortPer - 1) / ((int64_t)kB * kSortPer)));
+  hipLaunchKernelGGL(sort_count_kernel<T>, gsort, dim3(kB), 0, s, g, a, c->sort_off);
   LAUNCH_CHECK("sort_count");
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, c->sort_off, nkeys, c->sort_sums);
   LAUNCH_CHECK("scan_blocks");
@@ -309,7 +310,7 @@ grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_par
   LAUNCH_CHECK("scan_add");
   hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, c->sort_off + (nkeys - 1), c->sort_live);
   LAUNCH_CHECK("copy_int");
-  hipLaunchKernelGGL(sort_scatter_kernel<T>, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, b, c->sort_off);
+  hipLaunchKernelGGL(sort_scatter_kernel<T>, gsort, dim3(kB), 0, s, g, a, b, c->sort_off);
   LAUNCH_CHECK("sort_scatter");
   return GRPIC_OK;
 }

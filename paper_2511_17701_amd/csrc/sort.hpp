@@ -45,13 +45,27 @@ __device__ inline Run wave_run(int key) {
   return r;
 }
 
+// Each wavefront takes kSortPer consecutive chunks of 64 slots (one slot per
+// lane in each), so that one round trip of its cell-offset atomics covers
+// kSortPer chunks.
+constexpr int kSortPer = 4;
+
+__device__ inline int64_t sort_first_slot() {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  return wave * 64 * kSortPer + (threadIdx.x & 63);
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) sort_count_kernel(Grid g, ParticleArraysT<T> P,
                                                          int* __restrict__ counts) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int key = k < P.n ? sort_key(g, P, k) : -1;  // -1: past the end (own run)
-  const Run r = wave_run(key);
-  if (r.first && key >= 0) atomicAdd(counts + key, r.len);
+  const int64_t k0 = sort_first_slot();
+#pragma unroll
+  for (int c = 0; c < kSortPer; ++c) {
+    const int64_t k = k0 + 64 * c;
+    const int key = k < P.n ? sort_key(g, P, k) : -1;  // -1: past the end (own run)
+    const Run r = wave_run(key);
+    if (r.first && key >= 0) atomicAdd(counts + key, r.len);
+  }
 }
 
 // Exclusive scan of n ints in place, three phases: per-block scan (block sums
@@ -115,51 +129,70 @@ __global__ void scan_add_kernel(int* __restrict__ a, int64_t n, const int* __res
 
 // Moves slot k of S to its cell's next free slots in D; emptied slots get tag
 // 0.  The previous position (scratch between a push and its deposit) is not
-// carried.  A run of equal keys in a wavefront takes consecutive slots in lane order;
-// the order of runs of one cell follows the order of the atomics.
+// carried.  A run of equal keys in a chunk takes consecutive slots in lane
+// order; the order of runs of one cell follows the order of the atomics.  All
+// of a wavefront's slots are read, and all its offsets claimed, before the
+// first offset is waited for.
+template <class T>
+struct SlotT {
+  int i1, i2;
+  T dx1, dx2, u1, u2, u3, w, phi;
+  uint8_t tag;
+};
+
 template <class T>
 __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArraysT<T> S, ParticleArraysT<T> D,
                                                            int* __restrict__ off) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int key = k < S.n ? sort_key(g, S, k) : -1;
-  const bool live = key >= 0 && key < g.n_r * g.n_th;
-  // the slot is read before its cell offset is claimed, so that the loads
-  // overlap the atomic's round trip
-  int i1 = 0, i2 = 0;
-  T dx1 = 0, dx2 = 0, u1 = 0, u2 = 0, u3 = 0, w = 0, phi = 0;
-  uint8_t tag = 0;
-  if (live) {
-    i1 = S.i1[k];
-    i2 = S.i2[k];
-    dx1 = S.dx1[k];
-    dx2 = S.dx2[k];
-    u1 = S.u1[k];
-    u2 = S.u2[k];
-    u3 = S.u3[k];
-    w = S.w[k];
-    phi = S.phi[k];
-    tag = S.tag[k];
+  const int64_t k0 = sort_first_slot();
+  const int ncell = g.n_r * g.n_th;
+  int key[kSortPer];
+  SlotT<T> v[kSortPer];
+#pragma unroll
+  for (int c = 0; c < kSortPer; ++c) {
+    const int64_t k = k0 + 64 * c;
+    key[c] = k < S.n ? sort_key(g, S, k) : -1;
+    v[c] = SlotT<T>{};
+    if (key[c] >= 0 && key[c] < ncell) {
+      v[c].i1 = S.i1[k];
+      v[c].i2 = S.i2[k];
+      v[c].dx1 = S.dx1[k];
+      v[c].dx2 = S.dx2[k];
+      v[c].u1 = S.u1[k];
+      v[c].u2 = S.u2[k];
+      v[c].u3 = S.u3[k];
+      v[c].w = S.w[k];
+      v[c].phi = S.phi[k];
+      v[c].tag = S.tag[k];
+    }
   }
-  const Run r = wave_run(key);
-  int base = 0;
-  if (r.first && key >= 0) base = atomicAdd(off + key, r.len);
-  base = __shfl(base, r.head, 64);
-  if (key < 0) return;
-  const int64_t o = (int64_t)base + ((threadIdx.x & 63) - r.head);
-  if (!live) {
-    D.tag[o] = 0;
-    return;
+  Run r[kSortPer];
+  int base[kSortPer];
+#pragma unroll
+  for (int c = 0; c < kSortPer; ++c) {
+    r[c] = wave_run(key[c]);
+    base[c] = 0;
+    if (r[c].first && key[c] >= 0) base[c] = atomicAdd(off + key[c], r[c].len);
   }
-  D.i1[o] = i1;
-  D.i2[o] = i2;
-  D.dx1[o] = dx1;
-  D.dx2[o] = dx2;
-  D.u1[o] = u1;
-  D.u2[o] = u2;
-  D.u3[o] = u3;
-  D.w[o] = w;
-  D.phi[o] = phi;
-  D.tag[o] = tag;
+#pragma unroll
+  for (int c = 0; c < kSortPer; ++c) {
+    const int b = __shfl(base[c], r[c].head, 64);
+    if (key[c] < 0) continue;
+    const int64_t o = (int64_t)b + ((threadIdx.x & 63) - r[c].head);
+    if (key[c] == ncell) {
+      D.tag[o] = 0;
+      continue;
+    }
+    D.i1[o] = v[c].i1;
+    D.i2[o] = v[c].i2;
+    D.dx1[o] = v[c].dx1;
+    D.dx2[o] = v[c].dx2;
+    D.u1[o] = v[c].u1;
+    D.u2[o] = v[c].u2;
+    D.u3[o] = v[c].u3;
+    D.w[o] = v[c].w;
+    D.phi[o] = v[c].phi;
+    D.tag[o] = v[c].tag;
+  }
 }
 
 }  // namespace grpic
