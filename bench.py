@@ -75,6 +75,46 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+class HipEvents:
+    """HIP timing events recorded on torch's current stream, created with
+    hipEventDisableSystemFence: a record then neither writes back nor
+    invalidates the caches, so timing a kernel does not slow the work around
+    it (the host reads results only after a device synchronisation)."""
+
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self):
+        import ctypes
+        import torch
+        # the HIP runtime torch (and libgrpic) already use in this process
+        path = next(line.split()[-1] for line in open("/proc/self/maps") if "libamdhip64" in line)
+        self.c = ctypes
+        self.lib = ctypes.CDLL(path)
+        self.torch = torch
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} failed with HIP error {rc}")
+
+    def create(self):
+        ev = self.c.c_void_p()
+        self._check(self.lib.hipEventCreateWithFlags(self.c.byref(ev), self.c.c_uint(self.DISABLE_SYSTEM_FENCE)),
+                    "hipEventCreateWithFlags")
+        return ev
+
+    def record(self, ev):
+        stream = self.c.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+        self._check(self.lib.hipEventRecord(ev, stream), "hipEventRecord")
+
+    def elapsed(self, a, b):
+        ms = self.c.c_float()
+        self._check(self.lib.hipEventElapsedTime(self.c.byref(ms), a, b), "hipEventElapsedTime")
+        return ms.value
+
+    def destroy(self, ev):
+        self._check(self.lib.hipEventDestroy(ev), "hipEventDestroy")
+
+
 def profile_figures(name):
     """key: value lines of a committed profile summary (empty if absent)."""
     path = os.path.join(ROOT, "profiles", name)
@@ -158,17 +198,17 @@ class Run:
         if w.full_step:
             ctx.field_advance(F, self.G.PRE_PUSH)
         if ev is not None:
-            ev[0].record()
+            ev[0]()
         if ARGS.unfused:
             ctx.push(F, P)
         else:
             ctx.push_deposit(F, P)
         if ev is not None:
-            ev[1].record()
+            ev[1]()
         if ARGS.unfused:
             ctx.deposit(P, F)
-        if ev is not None:
-            ev[2].record()
+            if ev is not None:
+                ev[2]()
         if w.full_step:
             ctx.field_advance(F, self.G.POST_DEPOSIT)
         self.n += 1
@@ -184,18 +224,26 @@ class Run:
         for _ in range(warmup):
             self.step()
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
+        he = HipEvents()
+        evs = [[he.create() for _ in range(3 if ARGS.unfused else 2)] for _ in range(steps)]
+        for e in evs:
+            if not ARGS.unfused:
+                e.append(e[1])  # no second kernel: the deposit interval is empty
+        t0, t1 = he.create(), he.create()
         torch.cuda.synchronize()
-        t0.record()
+        he.record(t0)
         for k in range(steps):
-            self.step(evs[k])
-        t1.record()
+            self.step([lambda e=e: he.record(e) for e in evs[k]])
+        he.record(t1)
         torch.cuda.synchronize()
-        total = t0.elapsed_time(t1)
-        k1 = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
-        k2 = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+        total = he.elapsed(t0, t1)
+        k1 = sum(he.elapsed(e[0], e[1]) for e in evs) / steps
+        k2 = sum(he.elapsed(e[1], e[2]) for e in evs) / steps if ARGS.unfused else 0.0
+        for e in evs:
+            for x in e[:3 if ARGS.unfused else 2]:
+                he.destroy(x)
+        he.destroy(t0)
+        he.destroy(t1)
         d1 = self.ctx.diagnostics(self.F, self.P, self.w.B0)
         assert d1["n_nonfinite"] == 0, "non-finite particles after the run"
         return total / steps, k1, k2, live0, sum(d1["n_alive"])
