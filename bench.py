@@ -67,11 +67,18 @@ def parse():
 
 
 def source_hash():
+    """Hash of the kernel sources with comments and blank space removed, so
+    that a counter summary stays valid across comment-only edits."""
+    import re
     h = hashlib.sha256()
     files = sorted(glob.glob(os.path.join(ROOT, "paper_2511_17701_amd", "csrc", "*")))
     for f in files:
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        text = " ".join(text.split())
+        h.update(os.path.basename(f).encode() + b"\0" + text.encode())
     return h.hexdigest()[:16]
 
 

@@ -2,12 +2,12 @@
 //
 // Kernels are templated on the storage type T of the planes (double, or float
 // in the single-precision form); the metric weights and the update arithmetic
-// are FP64 and each result is rounded once on store.  The solver is bound by
-// plane traffic, so the FP64 arithmetic costs nothing.
+// are FP64 and each result is rounded once on store.
 //
 // Threads run along theta (the contiguous index of a plane), blocks along r.
-// Geometry at staggered grid points is assembled from 1-D tables of r at
-// integer / half-integer x1 and of sin, cos at integer / half-integer x2.
+// Geometry at staggered grid points is assembled from 1-D tables of r and
+// 1/(dxi r dtheta) at integer / half-integer x1 and of sin, cos and 1/sin at
+// integer / half-integer x2, with one reciprocal square root per point.
 #pragma once
 
 #include "geometry.hpp"

@@ -779,11 +779,13 @@ __device__ inline T run_sum(T v, const Runs& r) {
 }
 
 // Adds the contributions of the lanes of a wavefront through add(comp, i, j,
-// value) (absolute node indices).  Particles are cell-sorted, so lanes share
-// cells: the contributions of a run of lanes with the same cell are summed
-// across lanes first and the run's first lane adds them (atomics from many
-// lanes on one address would serialise).  Every lane of the wavefront must
-// call this (inactive lanes with act = false).
+// value) (absolute node indices), for blocks whose footprint does not fit the
+// LDS tile (the values then go straight to the planes as global atomics).
+// Particles are cell-sorted, so lanes share cells: the contributions of a run
+// of lanes with the same cell are summed across lanes first and the run's
+// first lane adds them (global atomics from many lanes on one address would
+// serialise).  Every lane of the wavefront must call this (inactive lanes
+// with act = false).
 template <class T, class Add>
 __device__ inline void add_runs(const Grid& g, bool act, const ContribT<T>& c, Add add) {
   const T z = (T)0;
