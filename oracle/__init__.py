@@ -109,6 +109,7 @@ def lib():
         L.orc_wald_fields.argtypes = [P, c_double, c_double, c_double, D, D]
         L.orc_field_advance.argtypes = [P, D, c_int]
         L.orc_fields_init_wald.argtypes = [P, D, c_double]
+        L.orc_fields_init_monopole.argtypes = [P, D, c_double]
         L.orc_philox4x32_10.argtypes = [POINTER(c_uint32), POINTER(c_uint32), POINTER(c_uint32)]
         L.orc_particles_init.argtypes = [P, PP, c_int64, c_int32, c_double, c_int64, c_uint64]
         L.orc_energy_momentum.argtypes = [P, PP, c_double, D, D]
@@ -189,6 +190,13 @@ def new_particles(n: int) -> dict:
 def fields_init_wald(prm: Params, B0: float) -> np.ndarray:
     F = new_fields(prm)
     lib().orc_fields_init_wald(ctypes.byref(prm), _dp(F), B0)
+    return F
+
+
+def fields_init_monopole(prm: Params, B0: float) -> np.ndarray:
+    """Monopole initial data of the BZ test: A_phi = -B0 cos(theta), D = 0."""
+    F = new_fields(prm)
+    lib().orc_fields_init_monopole(ctypes.byref(prm), _dp(F), B0)
     return F
 
 

@@ -1072,6 +1072,37 @@ void orc_fields_init_wald(const orc_params* p, double* F, double B0v)
   memcpy(F + P_BI * pl, B, sizeof(double) * 3 * pl);
 }
 
+/* Monopole initial data of the BZ test (Sec. "BZ monopole", eq. for A_phi):
+ * A_phi = -B0 cos(theta), so the discrete curl (eq. EB-set) gives
+ * B^1 (i, j+1/2) = (A_3(j+1) - A_3(j)) / sqrt(h) and B^2 = B^3 = 0; D = 0.
+ * The last ghost column has no j+1 node and takes the analytic value
+ * B^1 = dth B0 sin(theta) / sqrt(h) (the axis pass then overwrites it). */
+void orc_fields_init_monopole(const orc_params* p, double* F, double B0v)
+{
+  const int64_t pl = g_plane(p);
+  const int ng = p->ng;
+  const double dth = g_dth(p);
+  memset(F, 0, sizeof(double) * ORC_NPLANE * pl);
+  double *D = F + P_D * pl, *B = F + P_B * pl;
+  for (int i = -ng; i < p->n_r + ng; ++i)
+    for (int j = -ng; j < p->n_th + ng; ++j) {
+      orc_metric m;
+      orc_metric_at(p, i, j + 0.5, 0, &m);
+      if (j < p->n_th + ng - 1) {
+        const double a3 = -B0v * cos(j * dth), b3 = -B0v * cos((j + 1) * dth);
+        B[IX(p, i, j)] = (b3 - a3) / m.sqrt_h;
+      } else {
+        B[IX(p, i, j)] = dth * B0v * sin((j + 0.5) * dth) / m.sqrt_h;
+      }
+    }
+  axis_bc(p, D, 0);
+  axis_bc(p, B, 1);
+  memcpy(F + P_D0 * pl, D, sizeof(double) * 3 * pl);
+  memcpy(F + P_B0 * pl, B, sizeof(double) * 3 * pl);
+  memcpy(F + P_DI * pl, D, sizeof(double) * 3 * pl);
+  memcpy(F + P_BI * pl, B, sizeof(double) * 3 * pl);
+}
+
 /* ------------------------------------------------------ Philox, loading */
 
 /* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11):

@@ -262,3 +262,74 @@ def test_equatorial_mirror_symmetry(O):
     for k in ("u1", "u2", "u3"):
         np.testing.assert_allclose(P[k][alive], Pb[k][alive], rtol=1e-10,
                                    atol=1e-12 * np.abs(P[k]).max())
+
+
+# ------------------------------------------------------------- BZ monopole
+
+def monopole_params(O, n):
+    """The BZ test's geometry (a = 0.2, r in [r_g, 10 r_g]) on an n x n grid."""
+    prm = O.Params.make(0.2, 1.0, 1.0, 10.0, n, n, 0.0)
+    prm.dt = O.courant_dt(prm, 0.5)
+    return prm
+
+
+def test_monopole_flux_through_every_sphere_is_2_B0(O):
+    """sqrt(h) B^1 summed over the n theta faces of any radius telescopes to
+    A_3(pi) - A_3(0) = 2 B0 for A_phi = -B0 cos(theta): a sign, staggering or
+    potential mistake in the discrete curl changes the total."""
+    n, B0 = 32, 1.7
+    prm = monopole_params(O, n)
+    F = O.fields_init_monopole(prm, B0)
+    g = prm.ng
+    for i in (-2, 0, 7, n - 1, n + 1):
+        flux = sum(O.metric_at(prm, i, j + 0.5, clamp=False)["sqrt_h"] * F[3][i + g, j + g]
+                   for j in range(n))
+        assert abs(flux - 2.0 * B0) <= 1e-13 * B0, (i, flux)
+
+
+def test_monopole_face_flux_closed_form(O):
+    """sqrt(h) B^1 at (i, j+1/2) equals 2 B0 sin(theta_{j+1/2}) sin(dth/2), the
+    product form of cos(theta_j) - cos(theta_{j+1}), to a few ulp of B0."""
+    n, B0 = 48, 1.0
+    prm = monopole_params(O, n)
+    F = O.fields_init_monopole(prm, B0)
+    g, dth = prm.ng, math.pi / n
+    for i in (0, 5, n - 1):
+        for j in range(n):
+            sh = O.metric_at(prm, i, j + 0.5, clamp=False)["sqrt_h"]
+            exact = 2.0 * B0 * math.sin((j + 0.5) * dth) * math.sin(0.5 * dth)
+            assert abs(sh * F[3][i + g, j + g] - exact) <= 4e-16 * B0, (i, j)
+
+
+def test_monopole_only_radial_B_and_axis_parity(O):
+    """D = 0 and B^2 = B^3 = 0 everywhere; B^1 is even across both axes
+    (ghost column j = -1 mirrors j = 0, j = n mirrors n - 1); the time-centred
+    and absorbing-target copies equal the initial fields."""
+    n = 32
+    prm = monopole_params(O, n)
+    F = O.fields_init_monopole(prm, 1.0)
+    g = prm.ng
+    for c in (0, 1, 2, 4, 5):
+        assert not np.any(F[c]), c
+    B1 = F[3]
+    np.testing.assert_array_equal(B1[:, g - 1], B1[:, g])
+    np.testing.assert_array_equal(B1[:, g - 2], B1[:, g + 1])
+    np.testing.assert_array_equal(B1[:, g + n], B1[:, g + n - 1])
+    np.testing.assert_array_equal(B1[:, g + n + 1], B1[:, g + n - 2])
+    assert (B1[:, g:g + n] > 0).all()
+    np.testing.assert_array_equal(F[6:12], F[0:6])
+    np.testing.assert_array_equal(F[24:30], F[0:6])
+
+
+def test_monopole_discrete_divergence_free(O):
+    """Delta_i(sqrt(h) B^1) vanishes to round-off in every cell (B^2 = 0)."""
+    n = 32
+    prm = monopole_params(O, n)
+    F = O.fields_init_monopole(prm, 1.0)
+    g = prm.ng
+    worst = 0.0
+    for j in range(n):
+        col = [O.metric_at(prm, i, j + 0.5, clamp=False)["sqrt_h"] * F[3][i + g, j + g]
+               for i in range(-1, n + 1)]
+        worst = max(worst, max(abs(b - a) for a, b in zip(col, col[1:])) / max(abs(x) for x in col))
+    assert worst <= 1e-15
