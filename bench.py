@@ -144,7 +144,7 @@ def cpu_baseline(w, dt):
     prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, dt, n_iter=w.n_iter,
                         small_angle=w.small_angle, charge_scale=w.charge_scale,
                         n_filter=w.n_filter, n_absorb=w.n_absorb)
-    F = O.fields_init_wald(prm, w.B0)
+    F = O.fields_init_monopole(prm, w.B0) if w.init == "monopole" else O.fields_init_wald(prm, w.B0)
     big = w.n_particles > 2 ** 23
     if big:
         P = O.particles_init(prm, 2 ** 22, 0, w.T, w.n_geo, w.seed)
@@ -192,7 +192,10 @@ class Run:
                                  precision=grpic.GRPIC_FP32 if precision == "fp32"
                                  else grpic.GRPIC_FP64)
         self.F = self.ctx.new_fields(dev)
-        self.ctx.fields_init_wald(self.F, w.B0)
+        if w.init == "monopole":
+            self.ctx.fields_init_monopole(self.F, w.B0)
+        else:
+            self.ctx.fields_init_wald(self.F, w.B0)
         self.P = self.ctx.new_particles(w.n_particles, dev)
         self.ctx.particles_init(self.P, w.n_pairs_total if w.ppc == 0 else 0, w.ppc, w.T,
                                 w.n_geo, w.seed)

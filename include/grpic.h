@@ -163,6 +163,13 @@ grpic_status grpic_particles_init(grpic_ctx* ctx, const grpic_particles* P, int6
 grpic_status grpic_fields_init_wald(grpic_ctx* ctx, const grpic_fields* F, double B0,
                                     void* stream);
 
+/* Monopole initial data of the BZ test (Sec. "BZ monopole", eq. for A_phi):
+ * A_phi = -B0 cos(theta), so B^1 (B^r) is the discrete curl of A_3 (eq.
+ * EB-set) and every other component, D included, is zero; fills D, B, D0, B0,
+ * Dinit, Binit and zeroes the other planes, like grpic_fields_init_wald. */
+grpic_status grpic_fields_init_monopole(grpic_ctx* ctx, const grpic_fields* F, double B0,
+                                        void* stream);
+
 /* Particle update of Sec. 3.1 (steps 1-11) for every slot: interpolate D (plane
  * D) and B (plane B0) to x^n, EM half push in the tetrad frame, implicit
  * geodesic momentum update, EM half push, implicit coordinate update, phi

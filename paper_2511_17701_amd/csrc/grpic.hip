@@ -220,6 +220,30 @@ grpic_status wald_impl(grpic_ctx* c, const grpic_fields* F, double B0, hipStream
   return GRPIC_OK;
 }
 
+template <class T>
+grpic_status monopole_impl(grpic_ctx* c, const grpic_fields* F, double B0, hipStream_t s) {
+  const Grid& g = c->g;
+  void* const* pl = &F->D[0];
+  for (int k = 0; k < (c->f32 ? 39 : 33); ++k) {
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (T*)pl[k], 0.0);
+    LAUNCH_CHECK("fill");
+  }
+  hipLaunchKernelGGL(monopole_kernel<T>, grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng), kBlock2, 0, s, g, c->tab,
+                     (T*)F->B[0], B0);
+  LAUNCH_CHECK("monopole");
+  grpic_status st;
+  if ((st = field_bc<T>(c, tri<T>(F->D), none<T>(), ctri<T>(F->Dinit), false, s, 0))) return st;
+  if ((st = field_bc<T>(c, tri<T>(F->B), none<T>(), ctri<T>(F->Binit), true, s, 0))) return st;
+  void* const* dst[4] = {F->D0, F->B0, F->Dinit, F->Binit};
+  void* const* src[4] = {F->D, F->B, F->D, F->B};
+  for (int k = 0; k < 4; ++k) {
+    hipLaunchKernelGGL(copy_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri<T>(dst[k]),
+                       ctri<T>(src[k]));
+    LAUNCH_CHECK("copy");
+  }
+  return GRPIC_OK;
+}
+
 grpic_status push_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, hipStream_t s) {
   const dim3 grid(blocks(P->n));
   if (c->f32) {
@@ -605,6 +629,12 @@ grpic_status grpic_particles_init(grpic_ctx* c, const grpic_particles* P, int64_
     return fail(GRPIC_EINVAL, "test geodesics need r in [6, 15] inside the grid and M > 0");
   return c->f32 ? particles_init_impl<float>(c, P, n_pairs, ppc, T, n_geo, seed, S(stream))
                 : particles_init_impl<double>(c, P, n_pairs, ppc, T, n_geo, seed, S(stream));
+}
+
+grpic_status grpic_fields_init_monopole(grpic_ctx* c, const grpic_fields* F, double B0, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F))) return st;
+  return c->f32 ? monopole_impl<float>(c, F, B0, S(stream)) : monopole_impl<double>(c, F, B0, S(stream));
 }
 
 grpic_status grpic_fields_init_wald(grpic_ctx* c, const grpic_fields* F, double B0, void* stream) {

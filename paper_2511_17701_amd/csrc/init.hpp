@@ -292,4 +292,25 @@ __global__ void wald_kernel(Grid g, Tables t, TriT<T> D, TriT<T> B, double B0) {
   }
 }
 
+// Monopole initial data of the BZ test: A_phi = -B0 cos(theta), so B^1 at
+// (i, j+1/2) is the difference of A_3 between the nodes j and j+1 over sqrt(h)
+// (eq. EB-set) and every other component is zero (the caller zeroes the
+// planes).  The last column (no node j+1) takes the analytic
+// B^1 = dth B0 sin(theta) / sqrt(h); the axis pass overwrites it.
+template <class T>
+__global__ void monopole_kernel(Grid g, Tables t, T* __restrict__ B1, double B0) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y - g.ng;
+  if (j >= g.n_th + g.ng || i >= g.n_r + g.ng) return;
+  const double sqrt_h = cell_tab(g, t, i, 0, j, 1).sqrt_h;
+  double v;
+  if (j < g.n_th + g.ng - 1) {
+    const double a3 = -B0 * t.c[0][j + g.ng], b3 = -B0 * t.c[0][j + 1 + g.ng];
+    v = (b3 - a3) / sqrt_h;
+  } else {
+    v = g.dth * B0 * t.s[1][j + g.ng] / sqrt_h;
+  }
+  B1[ix(g, i, j)] = (T)v;
+}
+
 }  // namespace grpic

@@ -75,6 +75,7 @@ _sigs = {
     "grpic_particles_init": ([c_void_p, _PP, c_int64, c_int32, c_double, c_int64, c_uint64,
                               c_void_p], c_int32),
     "grpic_fields_init_wald": ([c_void_p, _F, c_double, c_void_p], c_int32),
+    "grpic_fields_init_monopole": ([c_void_p, _F, c_double, c_void_p], c_int32),
     "grpic_push": ([c_void_p, _F, _PP, c_void_p], c_int32),
     "grpic_deposit": ([c_void_p, _PP, _F, c_void_p], c_int32),
     "grpic_push_deposit": ([c_void_p, _F, _PP, c_void_p], c_int32),
@@ -203,6 +204,10 @@ class Context:
     def fields_init_wald(self, F: torch.Tensor, B0: float):
         _check(_lib.grpic_fields_init_wald(self._h, ctypes.byref(self._fields(F)), B0, _stream()),
                "grpic_fields_init_wald")
+
+    def fields_init_monopole(self, F: torch.Tensor, B0: float):
+        _check(_lib.grpic_fields_init_monopole(self._h, ctypes.byref(self._fields(F)), B0, _stream()),
+               "grpic_fields_init_monopole")
 
     def push(self, F: torch.Tensor, P: dict):
         _check(_lib.grpic_push(self._h, ctypes.byref(self._fields(F)),

@@ -20,7 +20,13 @@ c2_512    0.9    512^2   50         16 ppc + 1e3 neutral geodesics, T=1   100   
 c3_2048   0.99   2048^2  100        32 ppc, T = 1, B0 = 10                100    FP32 vs FP64
 c4_256    0.9    256^2   20         1e6, T = 1, frozen Wald, B0 learnable 50     adjoint (*)
 c5_4096   0.95   4096^2  200        16 ppc (pairs), T = 1, B0 = 10        200    FP32 full step
+c6_mono   0.2    2048^2  10         90 ppc (pairs), T = 0.5, B0 = 1       100    FP64 full step
 ========  =====  ======  =========  ====================================  =====  =========
+
+c6_monopole is the paper's own benchmark shape: the BZ monopole test
+(A_phi = -B0 cos theta, D = 0) on a 2048^2 log-r x theta mesh with 90 particles
+per cell, r from r_g to 10 r_g with an absorbing layer 1 r_g thick (94 cells),
+pairs at the test's injection temperature T = 0.5.
 
 (*) the differentiation form runs the implicit iterations to their fixed
 points (up to 200 iterations, stopping at an exact repeat), as its
@@ -59,6 +65,8 @@ class Workload:
     charge_scale: float = 1e-8
     ng: int = 2
     full_step: bool = False    # field_advance inside the step
+    init: str = "wald"         # initial field: "wald" | "monopole"
+    r_inner: float = 0.0       # inner radius (0: 0.9 r_h)
 
     @property
     def r_h(self) -> float:
@@ -66,7 +74,7 @@ class Workload:
 
     @property
     def r_min(self) -> float:
-        return 0.9 * self.r_h
+        return self.r_inner if self.r_inner > 0 else 0.9 * self.r_h
 
     @property
     def n_particles(self) -> int:
@@ -100,6 +108,9 @@ WORKLOADS = {
     "c5_4096": Workload("c5_4096", a=0.95, n_r=4096, n_th=4096, r_max=200.0, B0=10.0, T=1.0,
                         n_pairs=0, ppc=16, n_geo=0, steps=200, precision="fp32",
                         n_filter=4, n_absorb=32, full_step=True),
+    "c6_monopole": Workload("c6_monopole", a=0.2, n_r=2048, n_th=2048, r_max=10.0, B0=1.0, T=0.5,
+                            n_pairs=0, ppc=90, n_geo=0, steps=100, precision="fp64",
+                            n_absorb=94, full_step=True, init="monopole", r_inner=1.0),
 }
 
 

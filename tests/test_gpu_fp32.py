@@ -137,6 +137,18 @@ def test_fp32_wald_is_rounded_fp64(G, name):
     assert not F32[33:].any()      # compensation planes start at zero
 
 
+def test_fp32_monopole_is_rounded_fp64(G):
+    import torch
+    w = wl("c6_monopole", 128)
+    c32, c64 = contexts(G, w)
+    F32, F64 = c32.new_fields(), c64.new_fields()
+    c32.fields_init_monopole(F32, w.B0)
+    c64.fields_init_monopole(F64, w.B0)
+    torch.cuda.synchronize()
+    assert torch.equal(F32[:33], F64.to(torch.float32))
+    assert not F32[33:].any()
+
+
 # ---------------------------------------------------------------- one stage
 
 def loaded(G, w, c32, c64):

@@ -167,6 +167,34 @@ def test_fields_init_wald_parity(O, G, name, n):
     assert_fields(Fo, Fg.cpu().numpy(), range(12, 24), what="wald zero planes")
 
 
+@pytest.mark.parametrize("n", [48, 96])
+def test_fields_init_monopole_parity(O, G, n):
+    """Monopole initial data of the BZ test (a = 0.2, r in [r_g, 10 r_g]):
+    every plane against the oracle (B^1 is the difference of A_3 = -B0 cos(theta)
+    at two nodes over sqrt(h); the rest is zero)."""
+    w = wl("c6_monopole", n, n_absorb=6)
+    prm, ctx = pair(O, G, w)
+    Fo = O.fields_init_monopole(prm, w.B0)
+    Fg = ctx.new_fields()
+    ctx.fields_init_monopole(Fg, w.B0)
+    assert_fields(Fo, Fg.cpu().numpy(), range(0, 33), what="monopole")
+
+
+def test_full_step_parity_monopole(O, G):
+    """Full PIC steps from the monopole state (the BZ test's geometry on a
+    48^2 grid, cell-ordered pairs, an absorbing layer): fused pass and both
+    field stages against the oracle's step."""
+    w = wl("c6_monopole", 48, n_absorb=6)
+    prm, ctx = pair(O, G, w, charge_scale=0.02)
+    F, P = _sorted_state(O, prm, w, ppc=8)
+    for step in range(4):
+        Fg, Pg = up({"F": F})["F"], up(P)
+        O.step(prm, F, P)
+        ctx.step(Fg, Pg, fused=True)
+        assert_fields(F, Fg.cpu().numpy(), list(range(0, 24)), what=f"monopole step {step}")
+        assert_particles(prm, P, down(Pg), what=f"monopole step {step}", prev=False)
+
+
 # ---------------------------------------------------------------- push
 
 def _state(O, prm, w, n_pairs=None, n_geo=0, seed=None):
@@ -243,14 +271,14 @@ def test_deposit_parity(O, G):
 def _sorted_state(O, prm, w, ppc=16):
     """Cell-ordered loading (pairs of cell c at slots of c): lanes of a
     wavefront share cells, as after the cell sort."""
-    F = O.fields_init_wald(prm, w.B0)
+    F = O.fields_init_monopole(prm, w.B0) if w.init == "monopole" else O.fields_init_wald(prm, w.B0)
     P = O.particles_init(prm, 0, ppc, w.T, 0, w.seed)
     return F, P
 
 
 def test_deposit_parity_cell_ordered(O, G):
-    """Deposit of cell-ordered particles: the LDS-tile path with the
-    wavefront run sums (C2 recipe, 64^2, 16 ppc)."""
+    """Deposit of cell-ordered particles: the LDS-tile path with lanes on the
+    same nodes folded before the LDS atomics (C2 recipe, 64^2, 16 ppc)."""
     w = wl("c2_512", 64)
     prm, ctx = pair(O, G, w, charge_scale=0.3)
     F, P = _sorted_state(O, prm, w)
