@@ -23,7 +23,6 @@ FETCH_SIZE / WRITE_SIZE calibration) and exits.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -59,7 +58,8 @@ def parse():
     ap.add_argument("--iter-tol", type=float, default=0.0,
                     help="FP64 convergence test of the implicit iterations (0: fixed count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps of the CPU baseline (0: 8, or 2 above 2^23 particles)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the timing of the other precision form")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -67,11 +67,12 @@ def parse():
 
 
 def source_hash():
-    """Hash of the kernel sources with comments and blank space removed, so
-    that a counter summary stays valid across comment-only edits."""
+    """Hash of the sources of the fused push + deposit kernels (particles.hpp,
+    geometry.hpp) with comments and blank space removed: a counter summary of
+    that kernel stays valid across comment-only edits and changes elsewhere."""
     import re
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2511_17701_amd", "csrc", "*")))
+    files = [os.path.join(ROOT, "paper_2511_17701_amd", "csrc", f) for f in ("geometry.hpp", "particles.hpp")]
     for f in files:
         with open(f, encoding="utf-8") as fh:
             text = fh.read()
@@ -137,9 +138,9 @@ def profile_figures(name):
 
 def cpu_baseline(w, dt):
     """The oracle (FP64 C, OpenMP over particles) timed on the host cores on a
-    bounded sample of the workload: `cpu_steps` full steps; workloads above
-    2^23 particles keep their grid and fields but load 2^22 pairs in uniformly
-    drawn cells."""
+    bounded sample of the workload: `cpu_steps` full steps (8; 2 above 2^23
+    particles); workloads above 2^23 particles keep their grid and fields but
+    load 2^22 pairs in uniformly drawn cells."""
     import oracle as O
     prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, dt, n_iter=w.n_iter,
                         small_angle=w.small_angle, charge_scale=w.charge_scale,
@@ -152,7 +153,7 @@ def cpu_baseline(w, dt):
         P = O.particles_init(prm, w.n_pairs_total if w.ppc == 0 else 0, w.ppc, w.T, w.n_geo,
                              w.seed)
     n = int((P["tag"] != 0).sum())
-    steps = ARGS.cpu_steps
+    steps = ARGS.cpu_steps or (8 if not big else 2)
     t0 = time.perf_counter()
     for _ in range(steps):
         if w.full_step:
