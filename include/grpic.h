@@ -34,10 +34,16 @@
  * Particle storage (Sec. 3, code units): structure of arrays; position = cell
  * index (i1, i2) plus offset (dx1, dx2) in [0, 1); covariant code components
  * u_1 = u_r dr/dx1, u_2 = u_theta dth/dx2, u_3 = u_phi; previous position
- * (i1p, i2p, dx1p, dx2p): scratch written by grpic_push for grpic_deposit
- * (Sec. 3.2), not written by grpic_push_deposit and not carried by grpic_sort.
+ * (i1p, i2p, dx1p, dx2p): written by grpic_push for grpic_deposit (Sec. 3.2)
+ * and read by grpic_diagnostics (time-centred E, L); grpic_push_deposit does
+ * not write it and grpic_sort does not carry it, so a step whose E, L are
+ * wanted is taken with grpic_push and grpic_deposit (same particle state bit
+ * for bit, same currents to rounding order).
  * tag: 0 = empty slot, 1 = positron (q/m = +1), 2 = electron (q/m = -1),
- * 3 = neutral test particle (q = 0); bit 0x80 = left the domain this step
+ * 3 = neutral test particle (q = 0); 7 = massless neutral particle (species 3
+ * with bit 0x04: gamma = sqrt(h^ij u_i u_j) of Sec. 2.3, the EM stage
+ * skipped; its momentum must be non-zero, else the update divides by zero and
+ * the slot turns non-finite); bit 0x80 = left the domain this step
  * (deposited once more, emptied by the next push); tag 0x40 = dropped by a
  * bounds guard (a position outside the grid or a move of a cell or more,
  * which the deposit cannot represent), never used again and counted as
@@ -122,7 +128,8 @@ typedef struct {
 
 /* Summary filled by grpic_diagnostics. */
 typedef struct {
-  int64_t n_alive[4];   /* by species tag 0..3 (index 0 unused)              */
+  int64_t n_alive[4];   /* by species tag & 3 (index 0 unused; 3 counts the
+                           massive and massless neutral slots together)      */
   int64_t n_leaving;    /* slots with the leaving bit                       */
   int64_t n_empty;      /* tag == 0                                          */
   int64_t n_nonfinite;  /* live slots with a non-finite offset or momentum   */
@@ -227,8 +234,9 @@ grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t 
 grpic_status grpic_sort(grpic_ctx* ctx, const grpic_particles* src, const grpic_particles* dst,
                         int64_t* n_live, void* stream);
 
-/* Diagnostics (Sec. 2.3 conserved E, L at the time-centred position; Gauss's
- * law Sec. 3.2).  E_out, L_out: optional device arrays of P->n reals (NaN for
+/* Diagnostics (Sec. 2.3 conserved E, L at the time-centred position, the
+ * midpoint of the previous position recorded by the last grpic_push and the
+ * current one; Gauss's law Sec. 3.2).  E_out, L_out: optional device arrays of P->n reals (NaN for
  * empty slots); gauss_res: optional device plane for the residual.  Waits for
  * the stream; fills *out. */
 grpic_status grpic_diagnostics(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,

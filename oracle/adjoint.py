@@ -91,8 +91,10 @@ def metric_with_derivatives(p, x1, x2):
     return m
 
 
-def gamma(m, u1, u2, u3):
-    return torch.sqrt(1.0 + m["hu11"] * u1 * u1 + m["hu22"] * u2 * u2 + m["hu33"] * u3 * u3 +
+def gamma(m, u1, u2, u3, m2=1.0):
+    """u^0 alpha = sqrt(m^2 + h^ij u_i u_j) per unit mass (Sec. 2.3); m2 = 0
+    for massless particles."""
+    return torch.sqrt(m2 + m["hu11"] * u1 * u1 + m["hu22"] * u2 * u2 + m["hu33"] * u3 * u3 +
                       2.0 * m["hu13"] * u1 * u3)
 
 
@@ -153,14 +155,14 @@ def em_half(p, m, Dc, Bc, qm, u):
     return [uh[0] / s11 + k13 * s33 * uh[2], s22 * uh[1], s33 * uh[2]]
 
 
-def geodesic_momentum(p, m, u):
+def geodesic_momentum(p, m, u, m2=1.0):
     """eq. discretized-geodesic-u: n_iter fixed-point iterations on u_1, u_2
     at fixed x^n with contravariant metric derivatives (R5); u_3 unchanged."""
     us1, us2, u3 = u
     ut1, ut2 = us1, us2
     for _ in range(p.n_iter):
         ub1, ub2 = 0.5 * (us1 + ut1), 0.5 * (us2 + ut2)
-        gb = gamma(m, ub1, ub2, u3)
+        gb = gamma(m, ub1, ub2, u3, m2)
         f = []
         for i in range(2):
             quad = (m["dhu11"][i] * ub1 * ub1 + m["dhu22"][i] * ub2 * ub2 +
@@ -174,9 +176,9 @@ def geodesic_momentum(p, m, u):
     return [ut1, ut2, u3]
 
 
-def velocity(m, u):
+def velocity(m, u, m2=1.0):
     """dx^i/dt = alpha h^ij u_j / gamma - beta^i (i = 1, 2)."""
-    iu0 = m["alpha"] / gamma(m, *u)
+    iu0 = m["alpha"] / gamma(m, *u, m2)
     return ((m["hu11"] * u[0] + m["hu13"] * u[2]) * iu0 - m["beta1"], m["hu22"] * u[1] * iu0)
 
 
@@ -190,12 +192,14 @@ def _renorm(i, dx):
 
 def step(p, F1, B0, st):
     """One frozen-field particle update.  st: dict of tensors i1, i2 (int64),
-    dx1, dx2, u1, u2, u3 (float64), qm (float64 +-1 or 0), live (bool).
+    dx1, dx2, u1, u2, u3 (float64), qm (float64 +-1 or 0), m2 (float64 squared
+    rest mass, 1 or 0 for massless neutral particles), live (bool).
     F1: (n_planes, n_r + 2 ng, n_th + 2 ng) unit-amplitude field (planes
     D = 0..2 and B = 9..11, the B^n the push reads); B0: amplitude."""
     i1, i2, dx1, dx2 = st["i1"], st["i2"], st["dx1"], st["dx2"]
     u = [st["u1"], st["u2"], st["u3"]]
     qm, live = st["qm"], st["live"]
+    m2 = st.get("m2", 1.0)
     x1 = i1.to(DT) + dx1
     x2 = i2.to(DT) + dx2
     m = metric_with_derivatives(p, x1, x2)
@@ -206,15 +210,15 @@ def step(p, F1, B0, st):
         ue = em_half(p, m, Dc, Bc, qm, u)
         ue = geodesic_momentum(p, m, ue)
         ue = em_half(p, m, Dc, Bc, qm, ue)
-        un = geodesic_momentum(p, m, u)
+        un = geodesic_momentum(p, m, u, m2)
         u = [torch.where(charged, a, b) for a, b in zip(ue, un)]
     else:
-        u = geodesic_momentum(p, m, u)
+        u = geodesic_momentum(p, m, u, m2)
     d1 = torch.zeros_like(dx1)
     d2 = torch.zeros_like(dx2)
     for _ in range(p.n_iter):
         mb = metric(p, x1 + 0.5 * d1, x2 + 0.5 * d2)
-        v1, v2 = velocity(mb, u)
+        v1, v2 = velocity(mb, u, m2)
         n1, n2 = p.dt * v1, p.dt * v2
         done = torch.equal(n1, d1) and torch.equal(n2, d2)
         d1, d2 = n1, n2
@@ -234,7 +238,7 @@ def step(p, F1, B0, st):
         "dx1": torch.where(live, ndx1, dx1), "dx2": torch.where(live, ndx2, dx2),
         "u1": torch.where(live, u[0], st["u1"]), "u2": torch.where(live, u2, st["u2"]),
         "u3": torch.where(live, u[2], st["u3"]),
-        "qm": qm, "live": live & ~leaving,
+        "qm": qm, "m2": m2, "live": live & ~leaving,
     }
     return out
 
@@ -247,6 +251,7 @@ def state_from(P, idx=None):
     sp = tag & 3
     qm = np.where(sp == 1, 1.0, np.where(sp == 2, -1.0, 0.0))
     live = (tag != 0) & ((tag & 0x80) == 0) & ((tag & 0x40) == 0)
+    m2 = np.where((tag & 7) == 7, 0.0, 1.0)   # massless neutral: species 3 + bit 0x04
     return {
         "i1": torch.from_numpy(np.asarray(P["i1"][sel], dtype=np.int64)),
         "i2": torch.from_numpy(np.asarray(P["i2"][sel], dtype=np.int64)),
@@ -255,7 +260,7 @@ def state_from(P, idx=None):
         "u1": torch.from_numpy(np.asarray(P["u1"][sel], dtype=np.float64)),
         "u2": torch.from_numpy(np.asarray(P["u2"][sel], dtype=np.float64)),
         "u3": torch.from_numpy(np.asarray(P["u3"][sel], dtype=np.float64)),
-        "qm": torch.from_numpy(qm), "live": torch.from_numpy(live),
+        "qm": torch.from_numpy(qm), "m2": torch.from_numpy(m2), "live": torch.from_numpy(live),
     }
 
 

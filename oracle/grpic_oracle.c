@@ -79,6 +79,7 @@ typedef struct {
 
 #define TAG_LEAVING 0x80
 #define TAG_SPECIES 0x03
+#define TAG_MASSLESS 0x04 /* with species 3: a massless neutral particle */
 
 static double g_dxi(const orc_params* p) { return log(p->r_max / p->r_min) / p->n_r; }
 static double g_dth(const orc_params* p) { return M_PI / p->n_th; }
@@ -219,11 +220,20 @@ void orc_metric_at(const orc_params* p, double x1, double x2, int clamp, orc_met
   m->d_hu33[1] = dth * dhpp_t;
 }
 
-/* gamma = sqrt(1 + h^ij u_i u_j) for massive particles (Sec. 2.3) */
-static double gamma_of(const orc_metric* m, const double u[3])
+/* gamma = sqrt(m^2 + h^ij u_i u_j) (Sec. 2.3): m2 = 1 for massive particles,
+ * 0 for massless ones */
+static double gamma_m(const orc_metric* m, const double u[3], double m2)
 {
-  return sqrt(1.0 + m->hu11 * u[0] * u[0] + m->hu22 * u[1] * u[1] + m->hu33 * u[2] * u[2] +
+  return sqrt(m2 + m->hu11 * u[0] * u[0] + m->hu22 * u[1] * u[1] + m->hu33 * u[2] * u[2] +
               2.0 * m->hu13 * u[0] * u[2]);
+}
+
+static double gamma_of(const orc_metric* m, const double u[3]) { return gamma_m(m, u, 1.0); }
+
+/* m^2 of a slot: 0 for a neutral particle with the massless bit, else 1 */
+static double tag_mass2(uint8_t t)
+{
+  return (t & (TAG_SPECIES | TAG_MASSLESS)) == (TAG_SPECIES | TAG_MASSLESS) ? 0.0 : 1.0;
 }
 
 /* --------------------------------------------------------------- tetrads */
@@ -341,14 +351,14 @@ static void em_half(const orc_metric* m, const double Dh[3], const double Bh[3],
 /* Implicit-midpoint geodesic momentum update at fixed x^n, eq.
  * discretized-geodesic-u: n_iter fixed-point iterations on u_1, u_2; u_3 is
  * left unchanged.  The derivatives are of the contravariant h^ij (reading R5). */
-static void geodesic_momentum(const orc_params* p, const orc_metric* m, double u[3])
+static void geodesic_momentum(const orc_params* p, const orc_metric* m, double u[3], double m2)
 {
   const double us1 = u[0], us2 = u[1], u3 = u[2];
   double ut1 = us1, ut2 = us2;
   for (int it = 0; it < p->n_iter; ++it) {
     double ub1 = 0.5 * (us1 + ut1), ub2 = 0.5 * (us2 + ut2);
     double ub[3] = {ub1, ub2, u3};
-    double gb = gamma_of(m, ub);
+    double gb = gamma_m(m, ub, m2);
     double f[2];
     for (int i = 0; i < 2; ++i) {
       double quad = m->d_hu11[i] * ub1 * ub1 + m->d_hu22[i] * ub2 * ub2 +
@@ -364,9 +374,9 @@ static void geodesic_momentum(const orc_params* p, const orc_metric* m, double u
 
 /* coordinate velocity dx^i/dt = alpha h^ij u_j / gamma - beta^i (eq.
  * equation-of-motion) and dphi/dt = alpha h^3j u_j / gamma */
-static void coord_velocity(const orc_metric* m, const double u[3], double v[3])
+static void coord_velocity(const orc_metric* m, const double u[3], double v[3], double m2)
 {
-  double g = gamma_of(m, u);
+  double g = gamma_m(m, u, m2);
   double iu0 = m->alpha / g;
   v[0] = (m->hu11 * u[0] + m->hu13 * u[2]) * iu0 - m->beta1;
   v[1] = m->hu22 * u[1] * iu0;
@@ -390,7 +400,7 @@ static void push_one(const orc_params* p, const double* F, orc_particles* P, int
   uint8_t t = P->tag[k];
   if (t == 0) return;
   if (t & TAG_LEAVING) { P->tag[k] = 0; return; } /* deposited last step (R27) */
-  const double qm = tag_qm(t), dt = p->dt;
+  const double qm = tag_qm(t), m2 = tag_mass2(t), dt = p->dt;
   const int64_t pl = g_plane(p);
   int32_t i1 = P->i1[k], i2 = P->i2[k];
   double dx1 = P->dx1[k], dx2 = P->dx2[k];
@@ -410,10 +420,10 @@ static void push_one(const orc_params* p, const double* F, orc_particles* P, int
     orc_con_to_hat(&m, Dc, Dh);
     orc_con_to_hat(&m, Bc, Bh);
     em_half(&m, Dh, Bh, qm, dt, u);
-    geodesic_momentum(p, &m, u);
+    geodesic_momentum(p, &m, u, 1.0);
     em_half(&m, Dh, Bh, qm, dt, u);
   } else {
-    geodesic_momentum(p, &m, u); /* EM stage skipped for q = 0 */
+    geodesic_momentum(p, &m, u, m2); /* EM stage skipped for q = 0 */
   }
 
   /* 10. implicit coordinate update, eq. discretized-geodesic-x (R6, R7) */
@@ -422,7 +432,7 @@ static void push_one(const orc_params* p, const double* F, orc_particles* P, int
     orc_metric mb;
     orc_metric_at(p, x1 + 0.5 * d1, x2 + 0.5 * d2, 1, &mb);
     double v[3];
-    coord_velocity(&mb, u, v);
+    coord_velocity(&mb, u, v, m2);
     d1 = dt * v[0];
     d2 = dt * v[1];
   }
@@ -431,7 +441,7 @@ static void push_one(const orc_params* p, const double* F, orc_particles* P, int
     orc_metric mm;
     orc_metric_at(p, x1 + 0.5 * d1, x2 + 0.5 * d2, 1, &mm);
     double v[3];
-    coord_velocity(&mm, u, v);
+    coord_velocity(&mm, u, v, m2);
     P->phi[k] += dt * v[2];
   }
   dx1 += d1; renorm(&i1, &dx1);
@@ -507,7 +517,7 @@ static void deposit_one(const orc_params* p, double* F, const orc_particles* P, 
   orc_metric_at(p, (double)ia + xm, (double)ja + ym, 1, &m);
   double u[3] = {P->u1[k], P->u2[k], P->u3[k]};
   double v[3];
-  coord_velocity(&m, u, v);
+  coord_velocity(&m, u, v, 1.0); /* only charged (massive) particles deposit */
   double fm = floor(xm), gm = floor(ym);
   int km = ia + (int)fm, lm = ja + (int)gm;
   double w1 = xm - fm, w2 = ym - gm;
@@ -1252,7 +1262,7 @@ void orc_energy_momentum(const orc_params* p, const orc_particles* P, double B0v
     double qm = tag_qm(P->tag[k]);
     double A[3];
     orc_wald_potential(p, x1, m.th / g_dth(p), B0v, A);
-    E[k] = m.alpha * gamma_of(&m, u) - m.beta1 * u[0] - qm * A[0];
+    E[k] = m.alpha * gamma_m(&m, u, tag_mass2(P->tag[k])) - m.beta1 * u[0] - qm * A[0];
     L[k] = u[2] + qm * A[2];
   }
 }

@@ -91,8 +91,8 @@ __device__ inline GradT<R> lift(const GradT<double>& d) {
 // - alpha / (2 gamma) d_i h^jk b_j b_k, i = 1, 2.
 template <class R>
 __device__ inline void geo_force(const CoeffsT<R>& m, const GradT<R>& d, const R& b1, const R& b2,
-                                 const R& u3, R fr[2]) {
-  const R Q = R(1.0) + m.hu11 * b1 * b1 + m.hu22 * b2 * b2 + m.hu33 * u3 * u3 +
+                                 const R& u3, R fr[2], double mass2) {
+  const R Q = R(mass2) + m.hu11 * b1 * b1 + m.hu22 * b2 * b2 + m.hu33 * u3 * u3 +
               R(2.0) * m.hu13 * b1 * u3;
   const R ig = rsqrt(Q);
   const R gb = Q * ig;
@@ -107,8 +107,9 @@ __device__ inline void geo_force(const CoeffsT<R>& m, const GradT<R>& d, const R
 
 // coordinate velocity (v1, v2) = alpha h^ij u_j / gamma - beta^i
 template <class R>
-__device__ inline void coord_vel(const CoeffsT<R>& m, const R& u1, const R& u2, const R& u3, R v[2]) {
-  const R Q = R(1.0) + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+__device__ inline void coord_vel(const CoeffsT<R>& m, const R& u1, const R& u2, const R& u3, R v[2],
+                                 double mass2) {
+  const R Q = R(mass2) + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
               R(2.0) * m.hu13 * u1 * u3;
   const R iu0 = m.alpha * rsqrt(Q);
   v[0] = (m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1;
@@ -174,6 +175,7 @@ __device__ inline void adjoint_one(const Grid& g, const GatherPlanesT<double>& f
   GradT<T6> d;
   frame_from(g, rsc_tan(g, x1, x2), &f, &d);
   const double qm = species_sign(t);
+  const double ms = mass2_of(t);  // m^2 in gamma: 0 for a massless neutral particle
   T6 E[3], B[3];
   if (qm != 0.0) {
     const T6 D1 = interp_tan<1, 0>(g, fp.D[0], i1, dx1, i2, dx2, inv_B0);
@@ -201,7 +203,7 @@ __device__ inline void adjoint_one(const Grid& g, const GatherPlanesT<double>& f
     bool converged = false;
     for (int it = 0; it < g.n_iter; ++it) {
       double fr[2];
-      geo_force(fv.c, dv, 0.5 * (s1 + z1), 0.5 * (s2 + z2), w3, fr);
+      geo_force(fv.c, dv, 0.5 * (s1 + z1), 0.5 * (s2 + z2), w3, fr, ms);
       const double n1 = s1 + g.dt * fr[0], n2 = s2 + g.dt * fr[1];
       converged = n1 == z1 && n2 == z2;
       z1 = n1;
@@ -213,7 +215,7 @@ __device__ inline void adjoint_one(const Grid& g, const GatherPlanesT<double>& f
       T6 t1 = u1, t2 = u2;
       for (int it = 0; it < g.n_iter; ++it) {
         T6 fr[2];
-        geo_force(f.c, d, T6(0.5) * (u1 + t1), T6(0.5) * (u2 + t2), u3, fr);
+        geo_force(f.c, d, T6(0.5) * (u1 + t1), T6(0.5) * (u2 + t2), u3, fr, ms);
         t1 = u1 + T6(g.dt) * fr[0];
         t2 = u2 + T6(g.dt) * fr[1];
       }
@@ -223,14 +225,14 @@ __device__ inline void adjoint_one(const Grid& g, const GatherPlanesT<double>& f
       // tangent of the map with Z held fixed
       T6 b1 = T6(0.5) * (u1 + T6(z1)), b2 = T6(0.5) * (u2 + T6(z2));
       T6 fr[2];
-      geo_force(f.c, d, b1, b2, u3, fr);
+      geo_force(f.c, d, b1, b2, u3, fr, ms);
       T6 n1 = u1 + T6(g.dt) * fr[0], n2 = u2 + T6(g.dt) * fr[1];
       // A = dt/2 df/dubar_{12} at the fixed point
       CoeffsT<T2> m2{T2(fv.c.alpha), T2(fv.c.beta1), T2(fv.c.hu11), T2(fv.c.hu22), T2(fv.c.hu33),
                      T2(fv.c.hu13)};
       const GradT<T2> d2 = lift<T2>(dv);
       T2 f2[2];
-      geo_force(m2, d2, seed<2>(0.5 * (s1 + z1), 0), seed<2>(0.5 * (s2 + z2), 1), T2(w3), f2);
+      geo_force(m2, d2, seed<2>(0.5 * (s1 + z1), 0), seed<2>(0.5 * (s2 + z2), 1), T2(w3), f2, ms);
       const double A[2][2] = {{0.5 * g.dt * f2[0].d[0], 0.5 * g.dt * f2[0].d[1]},
                               {0.5 * g.dt * f2[1].d[0], 0.5 * g.dt * f2[1].d[1]}};
       n1.v = z1;
@@ -251,7 +253,7 @@ __device__ inline void adjoint_one(const Grid& g, const GatherPlanesT<double>& f
     for (int it = 0; it < g.n_iter; ++it) {
       const CoeffsT<double> m = coeffs_from(g, rsc_direct(g, a1 + 0.5 * e1, a2 + 0.5 * e2));
       double v[2];
-      coord_vel(m, u1.v, u2.v, u3.v, v);
+      coord_vel(m, u1.v, u2.v, u3.v, v, ms);
       const double n1 = g.dt * v[0], n2 = g.dt * v[1];
       converged = n1 == e1 && n2 == e2;
       e1 = n1;
@@ -264,20 +266,20 @@ __device__ inline void adjoint_one(const Grid& g, const GatherPlanesT<double>& f
       d2 = T6(0.0);
       for (int it = 0; it < g.n_iter; ++it) {
         T6 v[2];
-        coord_vel(coeffs_from(g, rsc_tan(g, x1 + T6(0.5) * d1, x2 + T6(0.5) * d2)), u1, u2, u3, v);
+        coord_vel(coeffs_from(g, rsc_tan(g, x1 + T6(0.5) * d1, x2 + T6(0.5) * d2)), u1, u2, u3, v, ms);
         d1 = T6(g.dt) * v[0];
         d2 = T6(g.dt) * v[1];
       }
     } else {
       const T6 xm1 = x1 + T6(0.5 * e1), xm2 = x2 + T6(0.5 * e2);
       T6 v[2];
-      coord_vel(coeffs_from(g, rsc_tan(g, xm1, xm2)), u1, u2, u3, v);
+      coord_vel(coeffs_from(g, rsc_tan(g, xm1, xm2)), u1, u2, u3, v, ms);
       d1 = T6(g.dt) * v[0];
       d2 = T6(g.dt) * v[1];
       const CoeffsT<T2> m2 =
           coeffs_from(g, rsc_tan(g, seed<2>(a1 + 0.5 * e1, 0), seed<2>(a2 + 0.5 * e2, 1)));
       T2 v2[2];
-      coord_vel(m2, T2(u1.v), T2(u2.v), T2(u3.v), v2);
+      coord_vel(m2, T2(u1.v), T2(u2.v), T2(u3.v), v2, ms);
       const double A[2][2] = {{0.5 * g.dt * v2[0].d[0], 0.5 * g.dt * v2[0].d[1]},
                               {0.5 * g.dt * v2[1].d[0], 0.5 * g.dt * v2[1].d[1]}};
       d1.v = e1;

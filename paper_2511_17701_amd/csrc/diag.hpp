@@ -48,7 +48,7 @@ diag_particles_kernel(Grid g, ParticleArraysT<T> P, double B0, T* __restrict__ E
       sincos(th, &s, &c);
       const WaldPot w = wald_pot(g, exp(g.xi_min + x1 * g.dxi), s, c, B0);
       const double qm = species_sign(t);
-      E = m.alpha * gamma_of(m, u1, u2, u3) - m.beta1 * u1 - qm * w.A0;
+      E = m.alpha * gamma_of(m, u1, u2, u3, mass2_of(t)) - m.beta1 * u1 - qm * w.A0;
       L = u3 + qm * w.A3;
       if (!(t & kLeaving)) {
         sum[sp] = E;

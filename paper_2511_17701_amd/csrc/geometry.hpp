@@ -284,9 +284,10 @@ __host__ __device__ inline Cell cell_at(const Grid& g, double x1, double x2) {
   return e;
 }
 
-// gamma = sqrt(1 + h^ij u_i u_j) (Sec. 2.3, massive particles)
-__host__ __device__ inline double gamma_of(const Coeffs& m, double u1, double u2, double u3) {
-  return sqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+// gamma = sqrt(m^2 + h^ij u_i u_j) (Sec. 2.3; mass2 = 1 massive, 0 massless)
+__host__ __device__ inline double gamma_of(const Coeffs& m, double u1, double u2, double u3,
+                                           double mass2 = 1.0) {
+  return sqrt(mass2 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
               2.0 * m.hu13 * u1 * u3);
 }
 

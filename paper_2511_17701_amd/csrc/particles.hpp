@@ -20,8 +20,15 @@ namespace grpic {
 constexpr uint8_t kLeaving = 0x80;
 constexpr uint8_t kInvalid = 0x40;  // dropped by a bounds guard; never used again
 constexpr uint8_t kSpecies = 0x03;
+constexpr uint8_t kMassless = 0x04;  // with species 3: a massless neutral particle
 
 __host__ __device__ inline bool is_live(uint8_t t) { return t != 0 && !(t & kInvalid); }
+
+// m^2 in gamma = sqrt(m^2 + h^ij u_i u_j) (Sec. 2.3): 0 for a massless neutral
+// particle (species 3 with the massless bit), 1 otherwise
+__host__ __device__ inline double mass2_of(uint8_t t) {
+  return (t & (kSpecies | kMassless)) == (kSpecies | kMassless) ? 0.0 : 1.0;
+}
 
 // a position inside the grid (what the push may start from)
 template <class T>
@@ -126,7 +133,7 @@ __device__ inline void em_half(const FrameT<R>& f, const R E[3], const R B[3], R
 // discretized-geodesic-u); u_3 is untouched.
 template <class R>
 __device__ inline void geodesic_u(const Grid& g, const FrameT<R>& f, const GradT<R>& d, R& u1, R& u2,
-                                  R u3) {
+                                  R u3, R mass2) {
   const CoeffsT<R>& m = f.c;
   const R s1 = u1, s2 = u2;
   const R u33 = u3 * u3;
@@ -134,7 +141,7 @@ __device__ inline void geodesic_u(const Grid& g, const FrameT<R>& f, const GradT
   R t1 = s1, t2 = s2;
   for (int it = 0; it < g.n_iter; ++it) {
     const R b1 = (R)0.5 * (s1 + t1), b2 = (R)0.5 * (s2 + t2);
-    const R Q = (R)1 + m.hu11 * b1 * b1 + m.hu22 * b2 * b2 + m.hu33 * u33 + (R)2 * m.hu13 * b1 * u3;
+    const R Q = mass2 + m.hu11 * b1 * b1 + m.hu22 * b2 * b2 + m.hu33 * u33 + (R)2 * m.hu13 * b1 * u3;
     const R ig = rsqrt(Q);
     const R gb = Q * ig;
     const R h = (R)0.5 * m.alpha * ig;
@@ -391,10 +398,10 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
     const double B[3] = {al * B1 / f.s11, al * f.s22 * B2, al * f.s33 * (f.k13 * B1 + B3)};
     const double kb = 0.25 * qm * g.dt;
     em_half(f, E, B, kb, u1, u2, u3);
-    geodesic_u(g, f, d, u1, u2, u3);
+    geodesic_u(g, f, d, u1, u2, u3, 1.0);
     em_half(f, E, B, kb, u1, u2, u3);
   } else {
-    geodesic_u(g, f, d, u1, u2, u3);
+    geodesic_u(g, f, d, u1, u2, u3, mass2_of(t));  // EM stage skipped for q = 0
   }
 
   // implicit coordinate update (eq. discretized-geodesic-x); an iterate that
@@ -404,10 +411,16 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
   // The first iterate (d = 0) uses the coefficients at x^n already in hand.
   double d1 = 0.0, d2 = 0.0;
   Coeffs m = f.c;
+  // m^2 from the tag, taken here rather than at the top: the empty asm keeps
+  // the compiler from hoisting it, so that it is not live through the field
+  // gather and EM stages, where the FP64 update is at its register limit
+  uint32_t tl = t;
+  asm volatile("" : "+v"(tl));
+  const double ms = mass2_of((uint8_t)tl);
   double iu0;
   bool repeat = false;
   for (int it = 0;;) {
-    iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+    iu0 = m.alpha * rsqrt(ms + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
                           2.0 * m.hu13 * u1 * u3);
     const double n1 = g.dt * ((m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1);
     const double n2 = g.dt * (m.hu22 * u2 * iu0);
@@ -425,7 +438,7 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
     // deposit); after an exact repeat the last coefficients are already there
     if (!repeat) {
       m = coeffs_from(g, rsc_near<SER>(g, tab, i1, x1 + 0.5 * d1, i2, x2 + 0.5 * d2));
-      iu0 = m.alpha * rsqrt(1.0 + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+      iu0 = m.alpha * rsqrt(ms + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
                             2.0 * m.hu13 * u1 * u3);
     }
     P.phi[k] += g.dt * (m.hu13 * u1 + m.hu33 * u3) * iu0;
@@ -527,6 +540,7 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
     frame_from(g, rsc_near_f<SER>(g, tab, i1, dx1, i2, dx2), &f, &d);
   }
   const float qm = (float)species_sign(t);
+  const float ms = (float)mass2_of(t);
   if (qm != 0.0f) {
     const float D1 = interp<1, 0>(g, fp.D[0], i1, dx1, i2, dx2);
     const float D2 = interp<0, 1>(g, fp.D[1], i1, dx1, i2, dx2);
@@ -539,10 +553,10 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
     const float B[3] = {al * B1 / f.s11, al * f.s22 * B2, al * f.s33 * (f.k13 * B1 + B3)};
     const float kb = 0.25f * qm * (float)g.dt;
     em_half(f, E, B, kb, u1, u2, u3);
-    geodesic_u(g, f, d, u1, u2, u3);
+    geodesic_u(g, f, d, u1, u2, u3, 1.0f);
     em_half(f, E, B, kb, u1, u2, u3);
   } else {
-    geodesic_u(g, f, d, u1, u2, u3);
+    geodesic_u(g, f, d, u1, u2, u3, ms);  // EM stage skipped for q = 0
   }
 
   // implicit coordinate update with the displacement (d1, d2) in cells
@@ -552,7 +566,7 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
   float iu0;
   bool repeat = false;
   for (int it = 0;;) {
-    iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+    iu0 = m.alpha * rsqrt(ms + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
                           2.0f * m.hu13 * u1 * u3);
     const float n1 = dt * ((m.hu11 * u1 + m.hu13 * u3) * iu0 - m.beta1);
     const float n2 = dt * (m.hu22 * u2 * iu0);
@@ -569,7 +583,7 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
   {
     if (!repeat) {
       m = coeffs_from(g, rsc_near_f<SER>(g, tab, i1, dx1 + 0.5f * d1, i2, dx2 + 0.5f * d2));
-      iu0 = m.alpha * rsqrt(1.0f + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
+      iu0 = m.alpha * rsqrt(ms + m.hu11 * u1 * u1 + m.hu22 * u2 * u2 + m.hu33 * u3 * u3 +
                             2.0f * m.hu13 * u1 * u3);
     }
     mv.vphi = (m.hu13 * u1 + m.hu33 * u3) * iu0;

@@ -38,6 +38,7 @@ def setup(O, G, n, n_pairs, seed=7):
     P = ctx.new_particles(2 * n_pairs)
     ctx.particles_init(P, n_pairs, 0, w.T, 0, seed)
     P["tag"][::7] = 3                           # some neutral particles
+    P["tag"][3::11] = 7                         # and some massless ones
     torch.cuda.synchronize()
     return w, ctx, F1, P
 

@@ -394,6 +394,42 @@ def test_diagnostics_parity(O, G):
         assert d["sum_E"][s] == pytest.approx(E[sel].sum(), rel=1e-12)
 
 
+def test_massless_parity(O, G):
+    """Massless neutral particles (species 3 with bit 0x04, gamma from the null
+    norm, no EM push) among charged and massive neutral ones, three steps from
+    the oracle's state: the push; the fused pass (no current from neutral
+    slots); the time-centred E and L."""
+    import torch
+    w = wl("c1_64", 48)
+    prm, ctx = pair(O, G, w, charge_scale=0.3)
+    F, P = _state(O, prm, w, n_pairs=5000)
+    P["tag"][::5] = 7
+    P["tag"][1::13] = 3
+    g = np.random.default_rng(11)
+    for k in ("u1", "u2", "u3"):                  # photons of widely spread energy
+        P[k][::5] *= np.exp(g.uniform(-3.0, 3.0, P[k][::5].shape))
+    photons = P["tag"] == 7
+    for step in range(3):
+        Fg, Pg = up({"F": F})["F"], up(P)
+        Ff, Pf = up({"F": F})["F"], up(P)
+        O.push(prm, F, P)
+        O.deposit(prm, F, P)
+        ctx.push(Fg, Pg)
+        ctx.push_deposit(Ff, Pf)
+        assert_particles(prm, P, down(Pg), what=f"massless push {step}")
+        assert_particles(prm, P, down(Pf), what=f"massless fused {step}", prev=False)
+        assert_fields(F, Ff.cpu().numpy(), range(18, 21), what=f"massless J {step}")
+        F[18:21] = 0.0
+    assert (P["tag"][photons] != 0).sum() > 0.9 * photons.sum()
+    E, L = O.energy_momentum(prm, P, w.B0)
+    d = ctx.diagnostics(Fg, up(P), w.B0, per_particle=True)
+    live = P["tag"] != 0
+    np.testing.assert_allclose(d["E"].cpu().numpy()[live], E[live], rtol=1e-12)
+    np.testing.assert_allclose(d["L"].cpu().numpy()[live], L[live], rtol=1e-12, atol=1e-12)
+    assert d["n_alive"][3] == int(((P["tag"] & 0x83) == 3).sum())
+    torch.cuda.synchronize()
+
+
 # ---------------------------------------------------------------- edge cases
 
 def test_edge_cases(O, G):
@@ -429,6 +465,7 @@ def test_edge_cases(O, G):
     P["u1"][50:60] = abs(P["u1"][50:60]) + 1.0
     P["tag"][60:70] = 0
     P["tag"][70:80] = 3
+    P["tag"][80:90] = 7
     for k in ("i1", "i2", "dx1", "dx2"):
         P[k + "p"][:] = P[k]
     for step in range(3):

@@ -32,6 +32,7 @@ def params(O, n=24, n_iter=30, **kw):
 def particles(O, prm, n_pairs, seed, T=1.0):
     P = O.particles_init(prm, n_pairs, 0, T, 0, seed)
     P["tag"][::7] = 3            # some neutral particles
+    P["tag"][3::11] = 7          # and some massless ones
     return P
 
 

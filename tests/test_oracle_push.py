@@ -219,3 +219,125 @@ def test_dead_particles_untouched(O):
     O.push(prm, O.fields_init_wald(prm, 1.0), P)
     for k in P:
         np.testing.assert_array_equal(P[k], ref[k])
+
+
+# ---------------------------------------------------------- massless (Sec. 2.3)
+
+def _photon_orbit(a, M, prograde):
+    """Equatorial circular photon orbit of Kerr: radius and impact parameter
+    b = L/E (Bardeen, Press & Teukolsky 1972), the angular velocity
+    dphi/dt = u^phi / u^t from the Boyer-Lindquist inverse metric, and the
+    Kerr-Schild u_r of eq. BL-KS-transformation for E = 1."""
+    s = -1.0 if prograde else 1.0
+    c = math.cos(math.acos(s * a / M) / 3.0)
+    r = 2.0 * M * (1.0 + math.cos(2.0 / 3.0 * math.acos(s * a / M)))
+    b = -a - s * 6.0 * M * c
+    Sig, Del = r * r, r * r - 2 * M * r + a * a
+    gtt, gtp = -(1 - 2 * M * r / Sig), -2 * M * a * r / Sig
+    gpp = r * r + a * a + 2 * M * a * a * r / Sig
+    det = gtt * gpp - gtp * gtp
+    Gtt, Gtp, Gpp = gpp / det, -gtp / det, gtt / det
+    assert abs(Gtt - 2 * Gtp * b + Gpp * b * b) < 1e-12   # null at u_r(BL) = 0
+    om = (-Gtp + Gpp * b) / (-Gtt + Gtp * b)
+    return r, b, om, -(-2 * M * r + a * b) / Del
+
+
+@pytest.mark.parametrize("a,prograde", [(0.0, True), (0.9, True), (0.9, False)])
+def test_photon_circular_orbit(O, a, prograde):
+    """Massless particles (tag species 3 + bit 0x04, gamma = sqrt(h^ij u_i u_j)):
+    the equatorial circular photon orbit is a fixed point of both implicit
+    updates, so the radius holds to round-off and phi advances at the orbit's
+    angular velocity; the same momentum on a massive neutral particle (the
+    mass term kept) leaves the orbit at once."""
+    M = 1.0
+    r, b, om, u_r = _photon_orbit(a, M, prograde)
+    rh = 1 + math.sqrt(1 - a * a)
+    r_min = 0.9 * rh
+    dxi, dth = grid(r_min, 12.0, 512, 512)
+    prm = params(O, a, M, r_min, 12.0, 512, 0.01)
+    F = np.zeros((33,) + prm.shape())
+    P = single(O, prm, r, math.pi / 2, u_r, 0.0, b, 7)
+    Q = single(O, prm, r, math.pi / 2, u_r, 0.0, b, 3)
+    dr = dq = 0.0
+    n = 2000
+    for _ in range(n):
+        O.push(prm, F, P)
+        O.push(prm, F, Q)
+        dr = max(dr, abs(position(P, 0, r_min, dxi, dth)[0] / r - 1))
+        if Q["tag"][0]:
+            dq = max(dq, abs(position(Q, 0, r_min, dxi, dth)[0] / r - 1))
+    assert P["tag"][0] == 7
+    assert dr < 1e-13
+    assert abs(P["phi"][0] - om * n * prm.dt) < 1e-11 * n * prm.dt
+    assert dq > 1e-2
+
+
+def test_photon_energy_second_order_and_L_exact(O):
+    """A photon scattered by a Kerr hole (a = 0.9, closest approach r ~ 4):
+    u_3 = L stays bit-for-bit, and the conserved E at the time-centred
+    positions drifts at second order in dt."""
+    a = 0.9
+    rh = 1 + math.sqrt(1 - a * a)
+    errs = []
+    for dt in (0.04, 0.02):
+        prm = params(O, a, 1.0, 0.9 * rh, 40.0, 512, dt)
+        P = single(O, prm, 12.0, 1.2, -1.0, 0.6, 5.0, 7)
+        F = np.zeros((33,) + prm.shape())
+        O.push(prm, F, P)
+        E0, _ = O.energy_momentum(prm, P, 0.0)
+        e = 0.0
+        for _ in range(int(round(40.0 / dt))):
+            O.push(prm, F, P)
+            E, L = O.energy_momentum(prm, P, 0.0)
+            assert L[0] == 5.0
+            e = max(e, abs(E[0] / E0[0] - 1))
+        assert P["tag"][0] == 7
+        errs.append(e)
+    assert errs[1] < 1e-6
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_photon_scale_invariance_bit_exact(O):
+    """Null geodesics do not depend on the scale of the momentum: doubling u
+    (a power of two, so every rounding scales with it) gives the same path to
+    the last bit and exactly twice the momentum; a massive particle does not
+    share the property."""
+    a = 0.9
+    rh = 1 + math.sqrt(1 - a * a)
+    prm = params(O, a, 1.0, 0.9 * rh, 40.0, 256, 0.02)
+    F = np.zeros((33,) + prm.shape())
+    for tag, same in ((7, True), (3, False)):
+        Ps = [single(O, prm, 8.0, 1.0, -0.7 * s, 0.4 * s, 3.0 * s, tag) for s in (1, 2)]
+        for _ in range(300):
+            for P in Ps:
+                O.push(prm, F, P)
+        pos = [(P["i1"][0], P["dx1"][0], P["i2"][0], P["dx2"][0], P["phi"][0]) for P in Ps]
+        if same:
+            assert pos[0] == pos[1]
+            for c in ("u1", "u2", "u3"):
+                assert Ps[1][c][0] == 2.0 * Ps[0][c][0]
+        else:
+            assert pos[0] != pos[1]
+
+
+def test_ultrarelativistic_limit_is_massless(O):
+    """A massive neutral particle with large |u| moves on the photon's path up
+    to O(1/gamma^2) (Sec. 2.3: the mass term is the only difference): the gap
+    after 300 steps shrinks a hundredfold when |u| grows tenfold."""
+    a = 0.9
+    rh = 1 + math.sqrt(1 - a * a)
+    prm = params(O, a, 1.0, 0.9 * rh, 40.0, 256, 0.02)
+    F = np.zeros((33,) + prm.shape())
+    dxi, dth = grid(prm.r_min, prm.r_max, 256, 256)
+    gaps = []
+    for s in (1e3, 1e4):
+        P = single(O, prm, 8.0, 1.0, -0.7 * s, 0.4 * s, 3.0 * s, 7)
+        Q = single(O, prm, 8.0, 1.0, -0.7 * s, 0.4 * s, 3.0 * s, 3)
+        for _ in range(300):
+            O.push(prm, F, P)
+            O.push(prm, F, Q)
+        rp, tp = position(P, 0, prm.r_min, dxi, dth)
+        rq, tq = position(Q, 0, prm.r_min, dxi, dth)
+        gaps.append(abs(rp - rq) + rp * abs(tp - tq) + rp * abs(P["phi"][0] - Q["phi"][0]))
+    assert gaps[1] < 1e-7
+    assert 90.0 < gaps[0] / gaps[1] < 110.0
