@@ -49,14 +49,16 @@ class Params(ctypes.Structure):
     _fields_ = [("a", c_double), ("M", c_double), ("r_min", c_double), ("r_max", c_double),
                 ("dt", c_double), ("small_angle", c_double), ("charge_scale", c_double),
                 ("n_r", c_int32), ("n_th", c_int32), ("ng", c_int32), ("n_iter", c_int32),
-                ("n_filter", c_int32), ("n_absorb", c_int32)]
+                ("n_filter", c_int32), ("n_absorb", c_int32), ("r0", c_double), ("h0", c_double)]
 
     @classmethod
     def make(cls, a, M, r_min, r_max, n_r, n_th, dt, n_iter=10, ng=2, small_angle=1e-5,
-             charge_scale=0.0, n_filter=0, n_absorb=0):
+             charge_scale=0.0, n_filter=0, n_absorb=0, r0=0.0, h0=0.0):
+        """r0, h0: the quasi-spherical map (App. A), xi = log(r - r0) and the
+        equatorial concentration h0 of theta(eta); 0, 0 is log r, uniform theta."""
         return cls(a=a, M=M, r_min=r_min, r_max=r_max, dt=dt, small_angle=small_angle,
                    charge_scale=charge_scale, n_r=n_r, n_th=n_th, ng=ng, n_iter=n_iter,
-                   n_filter=n_filter, n_absorb=n_absorb)
+                   n_filter=n_filter, n_absorb=n_absorb, r0=r0, h0=h0)
 
     def shape(self):
         return (self.n_r + 2 * self.ng, self.n_th + 2 * self.ng)
@@ -72,7 +74,7 @@ class Particles(ctypes.Structure):
                 ("tag", POINTER(c_uint8))]
 
 
-_MET = ["r", "th", "s", "c", "R", "Sig", "Del", "A", "S2", "alpha", "beta1",
+_MET = ["r", "th", "s", "c", "R", "T", "dT", "Sig", "Del", "A", "S2", "alpha", "beta1",
         "hu11", "hu22", "hu33", "hu13", "hl11", "hl22", "hl33", "hl13", "sqrt_h", "sqrt_ht"]
 _DER = ["d_alpha", "d_beta1", "d_hu11", "d_hu22", "d_hu33", "d_hu13"]
 

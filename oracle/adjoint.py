@@ -40,21 +40,36 @@ DT = torch.float64
 
 
 def _grid(p):
-    dxi = math.log(p.r_max / p.r_min) / p.n_r
-    dth = math.pi / p.n_th
-    return dxi, dth
+    """log spacing of r - r0 and the uniform spacing of eta (App. A map)."""
+    r0 = getattr(p, "r0", 0.0)
+    dxi = math.log((p.r_max - r0) / (p.r_min - r0)) / p.n_r
+    deta = math.pi / p.n_th
+    return dxi, deta
 
 
 def metric(p, x1, x2):
     """Lapse, shift, inverse and lower spatial metric in code components at
-    code position (x1, x2) (App. A, quasi-spherical map with r0 = h0 = 0;
-    index 1 carries dr/dx1 = dxi r, index 2 carries dth)."""
-    dxi, dth = _grid(p)
+    code position (x1, x2) (App. A, quasi-spherical map: r = r0 + exp(xi),
+    theta(eta) with concentration h0; index 1 carries R = dr/dx1, index 2
+    carries T = dtheta/dx2).  Beyond either axis (a midpoint of the
+    coordinate iteration can fall there) the polar map is continued by
+    reflection, theta(-x2) = -theta(x2), theta(2 n_th - x2) = 2 pi - theta(x2),
+    as in the C oracle (reading R23)."""
+    dxi, deta = _grid(p)
     a, M = p.a, p.M
-    r = torch.exp(math.log(p.r_min) + x1 * dxi)
-    th = torch.clamp(x2 * dth, p.small_angle, math.pi - p.small_angle)
+    r0, h0 = getattr(p, "r0", 0.0), getattr(p, "h0", 0.0)
+    e = torch.exp(math.log(p.r_min - r0) + x1 * dxi)
+    r = r0 + e
+    R = dxi * e
+    lo, hi = x2 < 0.0, x2 > p.n_th
+    xr = torch.where(lo, -x2, torch.where(hi, 2.0 * p.n_th - x2, x2))
+    eta = xr * deta
+    y = eta / math.pi
+    th = eta + 2.0 * h0 * eta * (math.pi - 2.0 * eta) * (math.pi - eta) / (math.pi * math.pi)
+    th = torch.where(lo, -th, torch.where(hi, 2.0 * math.pi - th, th))
+    T = deta * (1.0 + 2.0 * h0 + 12.0 * h0 * y * (y - 1.0))
+    th = torch.clamp(th, p.small_angle, math.pi - p.small_angle)
     s, c = torch.sin(th), torch.cos(th)
-    R = dxi * r
     Sig = r * r + a * a * c * c
     Del = r * r - 2.0 * M * r + a * a
     A = (r * r + a * a) ** 2 - a * a * Del * s * s
@@ -64,10 +79,10 @@ def metric(p, x1, x2):
     m["beta1"] = z / (1.0 + z) / R
     m["hu11"] = A / (Sig * (Sig + 2.0 * M * r)) / (R * R)
     m["hu13"] = a / Sig / R
-    m["hu22"] = 1.0 / Sig / (dth * dth)
+    m["hu22"] = 1.0 / Sig / (T * T)
     m["hu33"] = 1.0 / (Sig * s * s)
     hl13 = -a * (1.0 + z) * s * s * R
-    hl22 = Sig * dth * dth
+    hl22 = Sig * T * T
     hl33 = A * s * s / Sig
     # tetrad factors of the App. A matrices (reading R22)
     m["s11"] = torch.sqrt(m["hu11"])
@@ -268,7 +283,7 @@ def u_r(p, st):
     """Physical radial covariant component u_r = u_1 / (dr/dx1)."""
     dxi, _ = _grid(p)
     x1 = st["i1"].to(DT) + st["dx1"]
-    return st["u1"] / (dxi * p.r_min * torch.exp(x1 * dxi))
+    return st["u1"] / (dxi * (p.r_min - getattr(p, "r0", 0.0)) * torch.exp(x1 * dxi))
 
 
 def run(p, F1, B0, st, steps):

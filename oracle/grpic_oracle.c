@@ -61,6 +61,8 @@ typedef struct {
   int32_t n_iter;        /* implicit iterations (Sec. 3.1)               */
   int32_t n_filter;      /* current filter passes n_f                    */
   int32_t n_absorb;      /* outer absorbing layer cells (R16)            */
+  double r0, h0;         /* quasi-spherical map (App. A): radial offset,  */
+                         /* equatorial concentration; 0, 0 = log r, theta */
 } orc_params;
 
 enum {
@@ -81,8 +83,60 @@ typedef struct {
 #define TAG_SPECIES 0x03
 #define TAG_MASSLESS 0x04 /* with species 3: a massless neutral particle */
 
-static double g_dxi(const orc_params* p) { return log(p->r_max / p->r_min) / p->n_r; }
-static double g_dth(const orc_params* p) { return M_PI / p->n_th; }
+/* Quasi-spherical map of App. A: xi = log(r - r0) uniform in x1 from the
+ * inner edge r_min to r_max; theta(eta) = eta + 2 h0 eta (pi - 2 eta)(pi - eta)
+ * / pi^2 with eta = x2 deta uniform on [0, pi] (reading R23: the coefficient
+ * of the printed d theta / d eta is 12 h0). */
+static double g_dxi(const orc_params* p)
+{
+  return log((p->r_max - p->r0) / (p->r_min - p->r0)) / p->n_r;
+}
+static double g_dth(const orc_params* p) { return M_PI / p->n_th; } /* d eta */
+
+/* r(x1) and R = dr/dx1 = dxi (r - r0) */
+static void map_r(const orc_params* p, double x1, double* r, double* R)
+{
+  const double dxi = g_dxi(p);
+  const double e = exp(log(p->r_min - p->r0) + x1 * dxi);
+  *r = p->r0 + e;
+  *R = dxi * e;
+}
+
+/* theta(x2), T = d theta / d x2 and dT = d T / d x2.  Beyond either axis
+ * (ghost cells) the map is continued by reflection, theta(-x2) = -theta(x2)
+ * and theta(2 n_th - x2) = 2 pi - theta(x2) (reading R23: the cubic is not
+ * odd about the axis for h0 != 0, and the ghost geometry must mirror the
+ * interior for the axis parities of the field ghosts to hold). */
+static void map_th(const orc_params* p, double x2, double* th, double* T, double* dT)
+{
+  double sg = 1.0, off = 0.0;
+  if (x2 < 0.0) { x2 = -x2; sg = -1.0; }
+  else if (x2 > p->n_th) { x2 = 2.0 * p->n_th - x2; sg = -1.0; off = 2.0 * M_PI; }
+  const double de = g_dth(p), eta = x2 * de, h0 = p->h0, y = eta / M_PI;
+  *th = off + sg * (eta + 2.0 * h0 * eta * (M_PI - 2.0 * eta) * (M_PI - eta) / (M_PI * M_PI));
+  *T = de * (1.0 + 2.0 * h0 + 12.0 * h0 * y * (y - 1.0));
+  *dT = sg * de * de * 12.0 * h0 * (2.0 * y - 1.0) / M_PI;
+}
+
+/* x2 of a polar angle: the map is linear for h0 = 0 and increasing for
+ * -1/2 < h0 < 1; bisection on [0, n_th] otherwise */
+static double x2_of_theta(const orc_params* p, double th)
+{
+  if (p->h0 == 0.0) return th / g_dth(p);
+  double lo = 0.0, hi = p->n_th;
+  for (int it = 0; it < 100; ++it) {
+    double mid = 0.5 * (lo + hi), t, T, dT;
+    map_th(p, mid, &t, &T, &dT);
+    if (t < th) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* x1 of a radius */
+static double x1_of_r(const orc_params* p, double r)
+{
+  return (log(r - p->r0) - log(p->r_min - p->r0)) / g_dxi(p);
+}
 static int64_t g_ld(const orc_params* p) { return (int64_t)p->n_th + 2 * p->ng; }
 static int64_t g_plane(const orc_params* p) { return ((int64_t)p->n_r + 2 * p->ng) * g_ld(p); }
 static int64_t IX(const orc_params* p, int i, int j)
@@ -112,7 +166,8 @@ static double tag_qm(uint8_t t)
 /* ------------------------------------------------------------------ metric */
 
 typedef struct {
-  double r, th, s, c, R;          /* R = dr/dx1 = dxi * r                     */
+  double r, th, s, c, R;          /* R = dr/dx1 = dxi (r - r0)                */
+  double T, dT;                   /* T = d theta/dx2, dT = dT/dx2              */
   double Sig, Del, A, S2;         /* Sigma, Delta, A, Sigma + 2 M r            */
   double alpha, beta1;            /* lapse; contravariant shift, code units    */
   double hu11, hu22, hu33, hu13;  /* h^ij, code units                          */
@@ -123,9 +178,10 @@ typedef struct {
 } orc_metric;
 
 /*
- * Metric at code position (x1, x2).  r = exp(log r_min + x1 dxi), theta =
- * x2 dth (App. A quasi-spherical map, r0 = h0 = 0).  With clamp != 0, theta is
- * clamped to [small_angle, pi - small_angle] (Sec. 3.3.2, reading R4).
+ * Metric at code position (x1, x2) of the quasi-spherical map (App. A):
+ * r = r0 + exp(xi), theta = theta(eta).  With clamp != 0, theta is clamped to
+ * [small_angle, pi - small_angle] (Sec. 3.3.2, reading R4); the map's
+ * derivatives are those at x2.
  *
  * Physical Kerr-Schild 3+1 quantities (App. A):
  *   Sigma = r^2 + a^2 cos^2, Delta = r^2 - 2Mr + a^2,
@@ -136,21 +192,22 @@ typedef struct {
  *   h_rr = 1+z, h_rphi = -a (1+z) sin^2, h_thth = Sigma, h_phiphi = A sin^2/Sigma,
  *   sqrt(h) = Sigma sin / alpha.
  * Code components: one lower index 1 carries a factor R = dr/dx1, index 2 a
- * factor dth, index 3 a factor dphi = 1.  M enters only through 2Mr (R1).
- * Derivatives: chain rule d/dx1 = R d/dr (dR/dx1 = dxi R), d/dx2 = dth d/dth;
- * at M = 1 these are the App. A quasi-spherical forms.
+ * factor T = dtheta/dx2, index 3 a factor dphi = 1.  M enters only through
+ * 2Mr (R1).  Derivatives: chain rule d/dx1 = R d/dr (dR/dx1 = dxi R),
+ * d/dx2 = T d/dtheta, plus the derivative of the factor T^-2 of h^22, which
+ * the printed App. A forms omit (reading R23; it vanishes for h0 = 0).
  */
 void orc_metric_at(const orc_params* p, double x1, double x2, int clamp, orc_metric* m)
 {
-  const double a = p->a, M = p->M, dxi = g_dxi(p), dth = g_dth(p);
-  double r = exp(log(p->r_min) + x1 * dxi);
-  double th = x2 * dth;
+  const double a = p->a, M = p->M, dxi = g_dxi(p);
+  double r, R, th, T, dT;
+  map_r(p, x1, &r, &R);
+  map_th(p, x2, &th, &T, &dT);
   if (clamp) {
     if (th < p->small_angle) th = p->small_angle;
     if (th > M_PI - p->small_angle) th = M_PI - p->small_angle;
   }
   double s = sin(th), c = cos(th);
-  double R = dxi * r;
   double Sig = r * r + a * a * c * c;
   double Del = r * r - 2.0 * M * r + a * a;
   double A = (r * r + a * a) * (r * r + a * a) - a * a * Del * s * s;
@@ -158,7 +215,7 @@ void orc_metric_at(const orc_params* p, double x1, double x2, int clamp, orc_met
   double z = 2.0 * M * r / Sig;
   double alpha = sqrt(Sig / S2);
 
-  m->r = r; m->th = th; m->s = s; m->c = c; m->R = R;
+  m->r = r; m->th = th; m->s = s; m->c = c; m->R = R; m->T = T; m->dT = dT;
   m->Sig = Sig; m->Del = Del; m->A = A; m->S2 = S2;
   m->alpha = alpha;
 
@@ -171,14 +228,14 @@ void orc_metric_at(const orc_params* p, double x1, double x2, int clamp, orc_met
   m->beta1 = beta_r / R;
   m->hu11 = hrr / (R * R);
   m->hu13 = hrp / R;
-  m->hu22 = htt / (dth * dth);
+  m->hu22 = htt / (T * T);
   m->hu33 = hpp;
 
   m->hl11 = (1.0 + z) * R * R;
   m->hl13 = -a * (1.0 + z) * s * s * R;
-  m->hl22 = Sig * dth * dth;
+  m->hl22 = Sig * T * T;
   m->hl33 = A * s * s / Sig;
-  m->sqrt_ht = R * dth * Sig / alpha;
+  m->sqrt_ht = R * T * Sig / alpha;
   m->sqrt_h = m->sqrt_ht * s;
 
   /* physical derivatives */
@@ -207,17 +264,17 @@ void orc_metric_at(const orc_params* p, double x1, double x2, int clamp, orc_met
 
   /* code-coordinate derivatives */
   m->d_alpha[0] = R * dal_r;
-  m->d_alpha[1] = dth * dal_t;
+  m->d_alpha[1] = T * dal_t;
   m->d_beta1[0] = (R * dbr_r - dxi * beta_r) / R;
-  m->d_beta1[1] = dth * dbr_t / R;
+  m->d_beta1[1] = T * dbr_t / R;
   m->d_hu11[0] = (R * dhrr_r - 2.0 * dxi * hrr) / (R * R);
-  m->d_hu11[1] = dth * dhrr_t / (R * R);
+  m->d_hu11[1] = T * dhrr_t / (R * R);
   m->d_hu13[0] = (R * dhrp_r - dxi * hrp) / R;
-  m->d_hu13[1] = dth * dhrp_t / R;
-  m->d_hu22[0] = R * dhtt_r / (dth * dth);
-  m->d_hu22[1] = dth * dhtt_t / (dth * dth);
+  m->d_hu13[1] = T * dhrp_t / R;
+  m->d_hu22[0] = R * dhtt_r / (T * T);
+  m->d_hu22[1] = T * dhtt_t / (T * T) - 2.0 * dT * htt / (T * T * T);
   m->d_hu33[0] = R * dhpp_r;
-  m->d_hu33[1] = dth * dhpp_t;
+  m->d_hu33[1] = T * dhpp_t;
 }
 
 /* gamma = sqrt(m^2 + h^ij u_i u_j) (Sec. 2.3): m2 = 1 for massive particles,
@@ -600,12 +657,13 @@ static void wald_at(const orc_params* p, double r, double th, double B0, orc_wal
 /* Wald potential in code components at a code position: A_0, A_1 = R A_r, A_3 */
 void orc_wald_potential(const orc_params* p, double x1, double x2, double B0, double out[3])
 {
-  double dxi = g_dxi(p), dth = g_dth(p);
-  double r = exp(log(p->r_min) + x1 * dxi), th = x2 * dth;
+  double r, R, th, T, dT;
+  map_r(p, x1, &r, &R);
+  map_th(p, x2, &th, &T, &dT);
   orc_wald w;
   wald_at(p, r, th, B0, &w);
   out[0] = w.A0;
-  out[1] = w.Ar * dxi * r;
+  out[1] = w.Ar * R;
   out[2] = w.A3;
 }
 
@@ -619,13 +677,13 @@ void orc_wald_fields(const orc_params* p, double x1, double x2, double B0, doubl
   orc_metric_at(p, x1, x2, 0, &m);
   orc_wald w;
   wald_at(p, m.r, m.th, B0, &w);
-  double dth = g_dth(p), R = m.R;
-  /* code derivatives: d1 = R d/dr, d2 = dth d/dth; A_1(code) = R A_r */
-  double d2A3 = dth * w.dA3_t, d1A3 = R * w.dA3_r, d2A1 = dth * R * w.dAr_t;
+  double T = m.T, R = m.R;
+  /* code derivatives: d1 = R d/dr, d2 = T d/dtheta; A_1(code) = R A_r */
+  double d2A3 = T * w.dA3_t, d1A3 = R * w.dA3_r, d2A1 = T * R * w.dAr_t;
   B[0] = d2A3 / m.sqrt_h;
   B[1] = -d1A3 / m.sqrt_h;
   B[2] = -d2A1 / m.sqrt_h;
-  double E1 = R * w.dA0_r, E2 = dth * w.dA0_t, E3 = 0.0;
+  double E1 = R * w.dA0_r, E2 = T * w.dA0_t, E3 = 0.0;
   /* sqrt(h) B^k taken from the curl directly, finite on the axis */
   double X1 = E1;
   double X2 = E2 - m.beta1 * d2A1;
@@ -749,14 +807,17 @@ static void grid_metric(const orc_params* p, int i, int j, int o1, int o2, gpt* 
   g->sqrt_h = m.sqrt_h; g->sqrt_ht = m.sqrt_ht;
 }
 
-/* polar area A_{i+1/2} = R (r^2+a^2) sqrt(1 + 2Mr/(r^2+a^2)) (1 - cos(dth/2))
- * at r(i+1/2) (Sec. 3.3.2, App. A "Spherical Kerr-Schild", dr -> R) */
+/* polar area A_{i+1/2} = R (r^2+a^2) sqrt(1 + 2Mr/(r^2+a^2)) (1 - cos theta_c)
+ * at r(i+1/2), over the cap from the axis to theta_c = theta(x2 = 1/2)
+ * (Sec. 3.3.2, App. A "Spherical Kerr-Schild", dr -> R, the cap edge through
+ * the quasi-spherical map) */
 static double polar_area(const orc_params* p, int i)
 {
-  double dxi = g_dxi(p), dth = g_dth(p);
-  double r = exp(log(p->r_min) + (i + 0.5) * dxi);
+  double r, R, thc, T, dT;
+  map_r(p, i + 0.5, &r, &R);
+  map_th(p, 0.5, &thc, &T, &dT);
   double ra = r * r + p->a * p->a;
-  return dxi * r * ra * sqrt(1.0 + 2.0 * p->M * r / ra) * (1.0 - cos(0.5 * dth));
+  return R * ra * sqrt(1.0 + 2.0 * p->M * r / ra) * (1.0 - cos(thc));
 }
 
 /* ------------------------------------------------------ aux E and H */
@@ -1086,12 +1147,12 @@ void orc_fields_init_wald(const orc_params* p, double* F, double B0v)
  * A_phi = -B0 cos(theta), so the discrete curl (eq. EB-set) gives
  * B^1 (i, j+1/2) = (A_3(j+1) - A_3(j)) / sqrt(h) and B^2 = B^3 = 0; D = 0.
  * The last ghost column has no j+1 node and takes the analytic value
- * B^1 = dth B0 sin(theta) / sqrt(h) (the axis pass then overwrites it). */
+ * B^1 = T B0 sin(theta) / sqrt(h), T = dtheta/dx2 (the axis pass then
+ * overwrites it). */
 void orc_fields_init_monopole(const orc_params* p, double* F, double B0v)
 {
   const int64_t pl = g_plane(p);
   const int ng = p->ng;
-  const double dth = g_dth(p);
   memset(F, 0, sizeof(double) * ORC_NPLANE * pl);
   double *D = F + P_D * pl, *B = F + P_B * pl;
   for (int i = -ng; i < p->n_r + ng; ++i)
@@ -1099,10 +1160,13 @@ void orc_fields_init_monopole(const orc_params* p, double* F, double B0v)
       orc_metric m;
       orc_metric_at(p, i, j + 0.5, 0, &m);
       if (j < p->n_th + ng - 1) {
-        const double a3 = -B0v * cos(j * dth), b3 = -B0v * cos((j + 1) * dth);
+        double ta, tb, T, dT;
+        map_th(p, j, &ta, &T, &dT);
+        map_th(p, j + 1, &tb, &T, &dT);
+        const double a3 = -B0v * cos(ta), b3 = -B0v * cos(tb);
         B[IX(p, i, j)] = (b3 - a3) / m.sqrt_h;
       } else {
-        B[IX(p, i, j)] = dth * B0v * sin((j + 0.5) * dth) / m.sqrt_h;
+        B[IX(p, i, j)] = m.T * B0v * sin(m.th) / m.sqrt_h;
       }
     }
   axis_bc(p, D, 0);
@@ -1187,7 +1251,6 @@ void orc_particles_init(const orc_params* p, orc_particles* P, int64_t n_pairs, 
                         double T, int64_t n_geo, uint64_t seed)
 {
   const int64_t ncell = (int64_t)p->n_r * p->n_th;
-  const double dxi = g_dxi(p), dth = g_dth(p);
   for (int64_t k = 0; k < n_pairs; ++k) {
     uint32_t w[4];
     draw(seed, (uint32_t)k, 0u, 0u, w);
@@ -1220,7 +1283,7 @@ void orc_particles_init(const orc_params* p, orc_particles* P, int64_t n_pairs, 
       draw(seed, (uint32_t)g, 4u, k, v);
       double r = 6.0 + 9.0 * U01_LOW(w[0]);
       double th = M_PI / 3.0 + (M_PI / 3.0) * U01_LOW(w[1]);
-      double x1 = (log(r) - log(p->r_min)) / dxi, x2 = th / dth;
+      double x1 = x1_of_r(p, r), x2 = x2_of_theta(p, th);
       double f1 = floor(x1), f2 = floor(x2);
       i1 = (int32_t)f1; dx1 = x1 - f1;
       i2 = (int32_t)f2; dx2 = x2 - f2;
@@ -1260,10 +1323,10 @@ void orc_energy_momentum(const orc_params* p, const orc_particles* P, double B0v
     orc_metric_at(p, x1, x2, 1, &m);
     double u[3] = {P->u1[k], P->u2[k], P->u3[k]};
     double qm = tag_qm(P->tag[k]);
-    double A[3];
-    orc_wald_potential(p, x1, m.th / g_dth(p), B0v, A);
-    E[k] = m.alpha * gamma_m(&m, u, tag_mass2(P->tag[k])) - m.beta1 * u[0] - qm * A[0];
-    L[k] = u[2] + qm * A[2];
+    orc_wald w;
+    wald_at(p, m.r, m.th, B0v, &w);
+    E[k] = m.alpha * gamma_m(&m, u, tag_mass2(P->tag[k])) - m.beta1 * u[0] - qm * w.A0;
+    L[k] = u[2] + qm * w.A3;
   }
 }
 

@@ -47,13 +47,18 @@ def c_run(O, prm, F, P, steps):
 
 
 def c_ur(prm, P):
-    dxi = math.log(prm.r_max / prm.r_min) / prm.n_r
-    return P["u1"] / (dxi * prm.r_min * np.exp((P["i1"] + P["dx1"]) * dxi))
+    dxi = math.log((prm.r_max - prm.r0) / (prm.r_min - prm.r0)) / prm.n_r
+    return P["u1"] / (dxi * (prm.r_min - prm.r0) * np.exp((P["i1"] + P["dx1"]) * dxi))
 
 
-def test_forward_is_the_c_oracle_push(O):
+# the standard grid and a general quasi-spherical one (App. A)
+MAPS = [{}, {"r0": 0.4, "h0": 0.3}]
+
+
+@pytest.mark.parametrize("mp", MAPS, ids=["std", "qks"])
+def test_forward_is_the_c_oracle_push(O, mp):
     import oracle.adjoint as A
-    prm, w = params(O, n_iter=10)
+    prm, w = params(O, n_iter=10, **mp)
     F = O.fields_init_wald(prm, w.B0)
     P = particles(O, prm, 3000, 5)
     # a few particles next to each axis and the radial edges
@@ -78,13 +83,16 @@ def test_forward_is_the_c_oracle_push(O):
         for k in ("dx1", "dx2", "u1", "u2", "u3"):
             a, b = st[k].detach().numpy()[moved], Pc[k][moved]
             err = np.abs(a - b) / np.maximum(np.abs(b), 1e-3)
-            assert err.max() <= 1e-12, (s, k, err.max())
+            # the closed-form and autograd derivatives round differently; the
+            # general map's extra factors (R, T and dT/dx2) add a few terms
+            assert err.max() <= (5e-12 if mp else 1e-12), (s, k, err.max())
     assert (P["i2"][:20] == 0).all()
 
 
-def test_gradients_match_central_differences_of_the_c_oracle(O):
+@pytest.mark.parametrize("mp", MAPS, ids=["std", "qks"])
+def test_gradients_match_central_differences_of_the_c_oracle(O, mp):
     import oracle.adjoint as A
-    prm, w = params(O)
+    prm, w = params(O, **mp)
     steps, h = 6, 1e-6
     F = O.fields_init_wald(prm, w.B0)
     P = particles(O, prm, 150, 11)

@@ -1,0 +1,317 @@
+"""Pins of the oracle on the general quasi-spherical grid of App. A
+(xi = log(r - r0), theta(eta) with the equatorial concentration h0; reading
+R23): the map itself, the metric as the spherical Kerr-Schild metric seen
+through the map, its derivatives, and the particle and field updates on such a
+grid (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+from _helpers import bl_energy
+
+QKS = dict(r0=0.4, h0=0.3)
+
+
+def qparams(O, a=0.9, M=1.0, r_min=None, r_max=20.0, n=48, dt=0.0, **kw):
+    rh = M + math.sqrt(max(M * M - a * a, 0.0))
+    r_min = 0.9 * rh if r_min is None else r_min
+    kw = {**QKS, **kw}
+    prm = O.Params.make(a, M, r_min, r_max, n, n, dt, **kw)
+    if dt == 0.0:
+        prm.dt = O.courant_dt(prm, 0.5)
+    return prm
+
+
+# ------------------------------------------------------------------ the map
+
+def test_map_endpoints_symmetry_and_derivatives(O):
+    """r(0) = r_min, r(n_r) = r_max, theta(0) = 0, theta(n_th) = pi, theta
+    symmetric about the equator (theta(n - x2) = pi - theta(x2)), dtheta/dx2 at
+    the equator reduced by 1 - h0 (points concentrated there for h0 > 0);
+    R = dr/dx1, T = dtheta/dx2 and dT/dx2 agree with central differences of
+    r, theta and T, and dR/dx1 = dxi R (dxi the log spacing of r - r0)."""
+    n = 40
+    prm = qparams(O, n=n)
+    m0, mn = O.metric_at(prm, 0.0, 0.0, clamp=False), O.metric_at(prm, n, n, clamp=False)
+    assert m0["r"] == pytest.approx(prm.r_min, rel=1e-15)
+    assert mn["r"] == pytest.approx(prm.r_max, rel=1e-14)
+    assert m0["th"] == 0.0 and mn["th"] == pytest.approx(math.pi, rel=1e-15)
+    deta = math.pi / n
+    assert O.metric_at(prm, 1.0, n / 2, clamp=False)["T"] == pytest.approx(deta * (1 - QKS["h0"]),
+                                                                           rel=1e-14)
+    dxi = math.log((prm.r_max - QKS["r0"]) / (prm.r_min - QKS["r0"])) / n
+    g = np.random.default_rng(3)
+    h = 1e-5
+    for _ in range(20):
+        x1, x2 = g.uniform(0, n), g.uniform(0, n)
+        m = O.metric_at(prm, x1, x2, clamp=False)
+        ms = O.metric_at(prm, x1, n - x2, clamp=False)
+        assert ms["th"] == pytest.approx(math.pi - m["th"], rel=1e-14, abs=1e-14)
+        a, b = O.metric_at(prm, x1 + h, x2, clamp=False), O.metric_at(prm, x1 - h, x2, clamp=False)
+        assert (a["r"] - b["r"]) / (2 * h) == pytest.approx(m["R"], rel=1e-8)
+        assert (a["R"] - b["R"]) / (2 * h) == pytest.approx(dxi * m["R"], rel=1e-8)
+        c, d = O.metric_at(prm, x1, x2 + h, clamp=False), O.metric_at(prm, x1, x2 - h, clamp=False)
+        assert (c["th"] - d["th"]) / (2 * h) == pytest.approx(m["T"], rel=1e-8)
+        assert (c["T"] - d["T"]) / (2 * h) == pytest.approx(m["dT"], rel=1e-6, abs=1e-12)
+        assert m["T"] > 0
+
+
+# --------------------------------------------------------------- the metric
+
+def test_metric_is_spherical_ks_under_the_map(O):
+    """At the same physical point, every code component of the general map is
+    the standard (r0 = h0 = 0) grid's component times the ratio of the map
+    factors its indices carry (R = dr/dx1 for index 1, T = dtheta/dx2 for
+    index 2): alpha and h^33 unchanged, h^11 R^2, h^13 R, beta^1 R, h^22 T^2
+    and sqrt(h) / (R T) agree."""
+    n = 48
+    prm = qparams(O, n=n)
+    std = O.Params.make(prm.a, prm.M, prm.r_min, prm.r_max, n, n, prm.dt)
+    dxi_s = math.log(prm.r_max / prm.r_min) / n
+    g = np.random.default_rng(4)
+    for _ in range(30):
+        x1, x2 = g.uniform(0, n), g.uniform(0.5, n - 0.5)
+        q = O.metric_at(prm, x1, x2, clamp=False)
+        s = O.metric_at(std, math.log(q["r"] / prm.r_min) / dxi_s, q["th"] / (math.pi / n),
+                        clamp=False)
+        assert s["r"] == pytest.approx(q["r"], rel=1e-13)
+        assert s["th"] == pytest.approx(q["th"], rel=1e-13)
+        Rq, Rs, Tq, Ts = q["R"], s["R"], q["T"], s["T"]
+        for kq, ks in ((q["alpha"], s["alpha"]), (q["hu33"], s["hu33"]),
+                       (q["hu11"] * Rq ** 2, s["hu11"] * Rs ** 2), (q["hu13"] * Rq, s["hu13"] * Rs),
+                       (q["beta1"] * Rq, s["beta1"] * Rs), (q["hu22"] * Tq ** 2, s["hu22"] * Ts ** 2),
+                       (q["sqrt_h"] / (Rq * Tq), s["sqrt_h"] / (Rs * Ts)),
+                       (q["hl22"] / Tq ** 2, s["hl22"] / Ts ** 2), (q["hl13"] / Rq, s["hl13"] / Rs)):
+            assert kq == pytest.approx(ks, rel=1e-12)
+
+
+def test_derivatives_vs_central_differences(O):
+    """The twelve code-coordinate derivatives the pusher uses agree with
+    Richardson-extrapolated central differences of the metric on the general
+    map, including the derivative of the map factor of h^22 that the printed
+    App. A forms omit (reading R23)."""
+    n = 48
+    prm = qparams(O, n=n, h0=0.45)
+    keys = ("alpha", "beta1", "hu11", "hu22", "hu33", "hu13")
+    g = np.random.default_rng(5)
+    for _ in range(25):
+        x1, x2 = g.uniform(1, n - 1), g.uniform(2, n - 2)
+        m = O.metric_at(prm, x1, x2, clamp=False)
+        for ax in (0, 1):
+            def f(h):
+                d = (h, 0.0) if ax == 0 else (0.0, h)
+                a = O.metric_at(prm, x1 + d[0], x2 + d[1], clamp=False)
+                b = O.metric_at(prm, x1 - d[0], x2 - d[1], clamp=False)
+                return np.array([(a[k] - b[k]) / (2 * h) for k in keys])
+            fd = (4 * f(1e-3) - f(2e-3)) / 3
+            an = np.array([m["d_" + k][ax] for k in keys])
+            scale = np.abs(np.array([m[k] for k in keys]))
+            np.testing.assert_allclose(an, fd, rtol=1e-7, atol=1e-9 * scale.max(),
+                                       err_msg=f"axis {ax} at {x1:.3f}, {x2:.3f}")
+
+
+# ------------------------------------------------------------------ pusher
+
+def test_geodesic_energy_second_order_on_general_map(O):
+    """The Table 1 GR orbit (a = 0.995, r = 10.6498, L = 2) pushed on a grid
+    with r0 = 0.4, h0 = 0.3 keeps u_3 bit-for-bit and its BL energy with an
+    error that is second order in dt: the physics does not depend on the map."""
+    a = 0.995
+    E0, u_r = bl_energy(a, 1.0, 10.6498, math.pi / 2, 2.0)
+    rh = 1 + math.sqrt(1 - a * a)
+    errs = []
+    for dt in (0.04, 0.02):
+        prm = qparams(O, a=a, r_min=0.9 * rh, r_max=15.0, n=256, dt=dt)
+        P = O.new_particles(1)
+        m = None
+        x1 = math.log((10.6498 - QKS["r0"]) / (prm.r_min - QKS["r0"])) / (
+            math.log((15.0 - QKS["r0"]) / (prm.r_min - QKS["r0"])) / 256)
+        x2 = 128.0   # the equator (the map is symmetric)
+        for c, v in (("i1", math.floor(x1)), ("i2", math.floor(x2))):
+            P[c][0] = v
+            P[c + "p"][0] = v
+        for c, v in (("dx1", x1 - math.floor(x1)), ("dx2", x2 - math.floor(x2))):
+            P[c][0] = v
+            P[c + "p"][0] = v
+        m = O.metric_at(prm, x1, x2, clamp=False)
+        assert m["r"] == pytest.approx(10.6498, rel=1e-13)
+        assert m["th"] == pytest.approx(math.pi / 2, rel=1e-15)
+        P["u1"][0] = u_r * m["R"]
+        P["u3"][0] = 2.0
+        P["w"][0] = 1.0
+        P["tag"][0] = 3
+        F = np.zeros((33,) + prm.shape())
+        e = 0.0
+        for _ in range(int(round(60.0 / dt))):
+            O.push(prm, F, P)
+            assert P["u3"][0] == 2.0
+            E, _ = O.energy_momentum(prm, P, 0.0)
+            e = max(e, abs(E[0] / E0 - 1))
+        errs.append(e)
+    assert errs[1] < 1e-6
+    assert 3.3 < errs[0] / errs[1] < 4.7
+
+
+def test_charged_wald_orbit_on_general_map(O):
+    """GR-EM-2D row of Table 1 (a = 0, Wald field calB = 0.1, r = 4, L = 4.5)
+    on a grid with r0 = 0.4, h0 = 0.3: the Wald data loaded through the map
+    and the push conserve E and L up to the interpolation drift."""
+    E0, u_r = bl_energy(0.0, 1.0, 4.0, math.pi / 2, 2.9)
+    prm = qparams(O, a=0.0, r_min=1.8, r_max=20.0, n=512, dt=0.01)
+    F = O.fields_init_wald(prm, 0.2)
+    n = 512
+    dxi = math.log((20.0 - QKS["r0"]) / (1.8 - QKS["r0"])) / n
+    x1, x2 = math.log((4.0 - QKS["r0"]) / (1.8 - QKS["r0"])) / dxi, n / 2
+    P = O.new_particles(1)
+    for c, v in (("i1", math.floor(x1)), ("i2", math.floor(x2)), ("dx1", x1 - math.floor(x1)),
+                 ("dx2", x2 - math.floor(x2))):
+        P[c][0] = v
+        P[c + "p"][0] = v
+    m = O.metric_at(prm, x1, x2, clamp=False)
+    P["u1"][0] = u_r * m["R"]
+    P["u3"][0] = 2.9
+    P["w"][0] = 1.0
+    P["tag"][0] = 1
+    Es, Ls = [], []
+    for _ in range(3000):
+        O.push(prm, F, P)
+        E, L = O.energy_momentum(prm, P, 0.2)
+        Es.append(E[0]); Ls.append(L[0])
+    assert max(abs(np.array(Es) / E0 - 1)) < 2e-4
+    assert max(abs(np.array(Ls) / 4.5 - 1)) < 2e-4
+
+
+# ------------------------------------------------------------------ fields
+
+def test_wald_divergence_free_on_general_map(O):
+    """The discrete Stokes curl of the Wald potential on the general map is
+    divergence free to round-off in every cell."""
+    n = 32
+    prm = qparams(O, n=n)
+    F = O.fields_init_wald(prm, 1.0)
+    g = prm.ng
+    div, scale = [], 0.0
+    for i in range(0, n - 1):
+        for j in range(1, n - 1):
+            s = lambda x1, x2: O.metric_at(prm, x1, x2, clamp=False)["sqrt_h"]
+            a = s(i + 1, j + 0.5) * F[3][i + 1 + g, j + g] - s(i, j + 0.5) * F[3][i + g, j + g]
+            b = s(i + 0.5, j + 1) * F[4][i + g, j + 1 + g] - s(i + 0.5, j) * F[4][i + g, j + g]
+            div.append(a + b)
+            scale = max(scale, abs(a), abs(b))
+    assert np.abs(div).max() <= 1e-13 * scale
+
+
+def test_wald_vacuum_stationary_second_order_on_general_map(O):
+    """Vacuum evolution of the Wald data on the general map: away from the
+    radial boundary layers and from the axes (theta in [pi/8, 7 pi/8] in eta)
+    every component stays at its initial value up to a truncation error that
+    falls about 4x per doubling of the resolution.  (On the rows next to the
+    axes the staggered half-nodes of a map with h0 != 0 are not the midpoints
+    in theta of their faces, while the fields vary like powers of theta there;
+    the paper's scheme, which takes sqrt(h) at the staggered code point, is
+    first order on those rows.)"""
+    devs = []
+    for n in (32, 64):
+        prm = qparams(O, n=n)
+        F = O.fields_init_wald(prm, 1.0)
+        F0 = F.copy()
+        for _ in range(int(round(4.0 / prm.dt))):
+            O.field_advance(prm, F, 0)
+            O.field_advance(prm, F, 1)
+        g = prm.ng
+        r = np.array([O.metric_at(prm, i - g, 0.5 * n, clamp=False)["r"]
+                      for i in range(n + 2 * g)])
+        sel = (r > 6.0) & (r < 12.0)
+        js = slice(g + n // 8, g + n - n // 8 + 1)
+        devs.append([np.abs(F[c] - F0[c])[sel][:, js].max() /
+                     np.abs(F0[c][sel][:, g:g + n]).max() for c in range(6)])
+    devs = np.array(devs)
+    assert devs[1].max() < 3e-2
+    assert np.all(devs[0] / devs[1] > 3.3), devs
+
+
+def test_gauss_law_preserved_on_general_map(O):
+    """With charge deposited and no filtering the full PIC step keeps
+    div D - 4 pi rho fixed to round-off at every interior node on the general
+    map, and the polar-cap balance at both axes (the cap bounded by
+    theta(x2 = 1/2), R29) to round-off."""
+    n = 24
+    prm = qparams(O, n=n, charge_scale=0.05)
+    F = O.fields_init_wald(prm, 1.0)
+    P = O.particles_init(prm, 800, 0, 1.0, 0, 4)
+    x2 = (P["i2"] + P["dx2"]) * 0.08
+    x2 = np.where(np.arange(len(x2)) % 4 < 2, x2, n - x2)
+    for s in ("", "p"):
+        P["i2" + s][:] = np.floor(x2).astype(np.int32)
+        P["dx2" + s][:] = x2 - np.floor(x2)
+    g = prm.ng
+
+    def caps():
+        rho = O.charge(prm, P)
+        out = []
+        for i in range(3, n - 2):
+            A = []
+            for ii in (i - 1, i):
+                m = O.metric_at(prm, ii + 0.5, 0.5, clamp=False)
+                r, ra = m["r"], m["r"] ** 2 + prm.a ** 2
+                A.append(m["R"] * ra * math.sqrt(1 + 2 * r / ra) * (1 - math.cos(m["th"])))
+            s_lo = O.metric_at(prm, i, 0.5, clamp=False)["sqrt_h"]
+            s_hi = O.metric_at(prm, i, n - 0.5, clamp=False)["sqrt_h"]
+            D1, D2 = F[0], F[1]
+            lo = (A[1] * D1[i + g, g] - A[0] * D1[i - 1 + g, g] + s_lo * D2[i + g, g] -
+                  4 * math.pi * rho[i + g, g])
+            hi = (A[1] * D1[i + g, n + g] - A[0] * D1[i - 1 + g, n + g] -
+                  s_hi * D2[i + g, n - 1 + g] - 4 * math.pi * rho[i + g, n + g])
+            out.append((lo, hi))
+        return np.array(out)
+
+    res0, _, _ = O.gauss_residual(prm, F, P)
+    c0 = caps()
+    for _ in range(15):
+        O.step(prm, F, P)
+    res1, _, scale = O.gauss_residual(prm, F, P)
+    c1 = caps()
+    assert np.abs(res1 - res0).max() <= 2e-14 * scale
+    cs = np.abs(F[0:2]).max() * 1e-3 + np.abs(c0).max()
+    assert np.abs(c1 - c0).max() <= 1e-12 * cs
+
+
+def test_monopole_flux_on_general_map(O):
+    """The monopole data on the general map: the sqrt(h) B^1 flux through
+    every sphere telescopes to A_3(pi) - A_3(0) = 2 B0, and each face's flux
+    is the cosine difference at the mapped node angles."""
+    n, B0 = 32, 1.3
+    prm = qparams(O, a=0.2, r_min=1.0, r_max=10.0, n=n, r0=0.5)
+    F = O.fields_init_monopole(prm, B0)
+    g = prm.ng
+    for i in (-2, 0, 9, n - 1, n + 1):
+        flux = sum(O.metric_at(prm, i, j + 0.5, clamp=False)["sqrt_h"] * F[3][i + g, j + g]
+                   for j in range(n))
+        assert abs(flux - 2.0 * B0) <= 1e-13 * B0, (i, flux)
+    # each face carries B0 (cos theta_j - cos theta_{j+1}) with the nodes'
+    # mapped angles: 2 B0 sin of the half-sum times sin of the half-difference
+    th = [O.metric_at(prm, 0, j, clamp=False)["th"] for j in range(n + 1)]
+    for i in (0, 9, n - 1):
+        for j in range(n):
+            sh = O.metric_at(prm, i, j + 0.5, clamp=False)["sqrt_h"]
+            exact = 2 * B0 * math.sin(0.5 * (th[j] + th[j + 1])) * math.sin(0.5 * (th[j + 1] - th[j]))
+            assert abs(sh * F[3][i + g, j + g] - exact) <= 4e-16 * B0, (i, j)
+
+
+def test_geodesic_loading_on_general_map(O):
+    """Test geodesics are placed at their drawn physical position: r in
+    [6, 15], theta in [pi/3, 2pi/3] through the inverse of the map, and bound."""
+    prm = qparams(O, n=64, r_max=20.0)
+    P = O.particles_init(prm, 0, 0, 1.0, 400, 11)
+    E, _ = O.energy_momentum(prm, P, 0.0)
+    th = []
+    for k in range(400):
+        m = O.metric_at(prm, P["i1"][k] + P["dx1"][k], P["i2"][k] + P["dx2"][k], clamp=False)
+        assert 6.0 <= m["r"] <= 15.0
+        assert math.pi / 3 - 1e-12 <= m["th"] <= 2 * math.pi / 3 + 1e-12
+        th.append(m["th"])
+    # uniform in theta: both ends of the range are reached (an x2 taken as
+    # theta / deta would start the set at theta(eta = pi/3) = pi/3 + 0.14)
+    assert min(th) < math.pi / 3 + 0.03 and max(th) > 2 * math.pi / 3 - 0.03
+    assert (E < 1.0).mean() > 0.95
