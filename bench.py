@@ -144,7 +144,7 @@ def cpu_baseline(w, dt):
     import oracle as O
     prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, dt, n_iter=w.n_iter,
                         small_angle=w.small_angle, charge_scale=w.charge_scale,
-                        n_filter=w.n_filter, n_absorb=w.n_absorb)
+                        n_filter=w.n_filter, n_absorb=w.n_absorb, r0=w.r0, h0=w.h0)
     F = O.fields_init_monopole(prm, w.B0) if w.init == "monopole" else O.fields_init_wald(prm, w.B0)
     big = w.n_particles > 2 ** 23
     if big:
@@ -189,7 +189,7 @@ class Run:
         self.ctx = grpic.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, cfl=w.cfl,
                                  n_iter=w.n_iter, small_angle=w.small_angle,
                                  charge_scale=w.charge_scale, n_filter=w.n_filter,
-                                 n_absorb=w.n_absorb, iter_tol=ARGS.iter_tol,
+                                 n_absorb=w.n_absorb, iter_tol=ARGS.iter_tol, r0=w.r0, h0=w.h0,
                                  precision=grpic.GRPIC_FP32 if precision == "fp32"
                                  else grpic.GRPIC_FP64)
         self.F = self.ctx.new_fields(dev)
@@ -317,7 +317,8 @@ def main():
         "dtype": "f64" if precision == "fp64" else "f32 (+f64 horizon metric)",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": f"{w.n_r}x{w.n_th}", "a": w.a,
-                   "r_range": [w.r_min, w.r_max], "particles": w.n_particles, "ppc": w.ppc,
+                   "r_range": [w.r_min, w.r_max], "map_r0_h0": [w.r0, w.h0],
+                   "particles": w.n_particles, "ppc": w.ppc,
                    "test_geodesics": w.n_geo, "T": w.T, "B0": w.B0, "n_iter": w.n_iter,
                    "dt": dt, "full_step": w.full_step, "n_filter": w.n_filter,
                    "n_absorb": w.n_absorb, "precision": precision,

@@ -5,9 +5,10 @@
  * Relativistic Module").
  *
  * Problem (Sec. 3): particles and fields on an axisymmetric (r, theta) grid,
- * uniform in the code coordinates x1 = ln(r / r_min) / dxi, x2 = theta / dth
- * (App. A, quasi-spherical Kerr-Schild map with r0 = h0 = 0), in the 3+1 split
- * of the Kerr metric of mass M and spin a (Sec. 2.1, App. A).
+ * uniform in the code coordinates of the quasi-spherical Kerr-Schild map of
+ * App. A, x1 = ln((r - r0) / (r_min - r0)) / dxi and x2 = eta / deta with
+ * theta(eta) of concentration h0 (r0 = h0 = 0: logarithmic r, uniform theta),
+ * in the 3+1 split of the Kerr metric of mass M and spin a (Sec. 2.1, App. A).
  *
  * Conventions shared by every call
  *  - Every pointer inside grpic_fields / grpic_particles is a device pointer,
@@ -97,6 +98,14 @@ typedef struct {
   int32_t n_absorb;     /* outer absorbing-layer width in cells, >= 0        */
   int32_t precision;    /* grpic_precision                                   */
   int32_t reserved;     /* must be 0                                         */
+  double r0;            /* quasi-spherical map (App. A): xi = log(r - r0) is
+                           uniform in x1; 0 <= r0 < r_min                    */
+  double h0;            /* equatorial concentration of the polar map
+                           theta = eta + 2 h0 eta (pi - 2 eta)(pi - eta)/pi^2,
+                           eta uniform in x2; -1/2 < h0 < 1.  r0 = h0 = 0 is
+                           the logarithmic-r, uniform-theta grid, the only
+                           one whose push takes in-cell series (others take
+                           the library exp and sincos)                       */
 } grpic_params;
 
 /* Device pointers to the field planes (Sec. 3.4 storage):

@@ -33,14 +33,35 @@ constexpr int kAdjDirs = 6;  // x1, x2, u1, u2, u3, B0
 using T6 = Tan<kAdjDirs>;
 using T2 = Tan<2>;
 
-// r, sin, cos of a tangent position (theta clamped: a clamped angle is constant)
+// r, sin, cos and the map factors of a tangent position (the quasi-spherical
+// map of App. A, reflected beyond either axis as in map_theta; theta clamped:
+// a clamped angle is constant, the map factors are not)
 template <int N>
 __device__ inline RSCT<Tan<N>> rsc_tan(const Grid& g, const Tan<N>& x1, const Tan<N>& x2) {
-  RSCT<Tan<N>> p;
-  p.r = exp(Tan<N>(g.xi_min) + x1 * Tan<N>(g.dxi));
-  Tan<N> th = x2 * Tan<N>(g.dth);
-  if (th.v < g.small_angle) th = Tan<N>(g.small_angle);
-  if (th.v > kPi - g.small_angle) th = Tan<N>(kPi - g.small_angle);
+  using TN = Tan<N>;
+  RSCT<TN> p;
+  const TN e = exp(TN(g.xi_min) + x1 * TN(g.dxi));
+  p.r = TN(g.r0) + e;
+  p.rd = TN(g.dxi) * e;
+  double sg = 1.0, off = 0.0;
+  TN xr = x2;
+  if (x2.v < 0.0) {
+    xr = -x2;
+    sg = -1.0;
+  } else if (x2.v > (double)g.n_th) {
+    xr = TN(2.0 * g.n_th) - x2;
+    sg = -1.0;
+    off = 2.0 * kPi;
+  }
+  const TN eta = xr * TN(g.dth), y = eta * TN(1.0 / kPi);
+  const double h0 = g.h0;
+  TN th = TN(off) + TN(sg) * (eta + TN(2.0 * h0 / (kPi * kPi)) * eta * (TN(kPi) - TN(2.0) * eta) *
+                                        (TN(kPi) - eta));
+  p.td = TN(g.dth) * (TN(1.0 + 2.0 * h0) + TN(12.0 * h0) * y * (y - TN(1.0)));
+  p.itd2 = rcp(p.td * p.td);
+  p.dtd = TN(sg * g.dth * g.dth * 12.0 * h0 / kPi) * (TN(2.0) * y - TN(1.0));
+  if (th.v < g.small_angle) th = TN(g.small_angle);
+  if (th.v > kPi - g.small_angle) th = TN(kPi - g.small_angle);
   sincos(th, &p.s, &p.c);
   return p;
 }

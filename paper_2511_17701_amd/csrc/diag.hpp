@@ -43,10 +43,12 @@ diag_particles_kernel(Grid g, ParticleArraysT<T> P, double B0, T* __restrict__ E
       const double x1 = 0.5 * (((double)P.i1p[k] + P.dx1p[k]) + ((double)P.i1[k] + d1));
       const double x2 = 0.5 * (((double)P.i2p[k] + P.dx2p[k]) + ((double)P.i2[k] + d2));
       const Coeffs m = coeffs_at(g, x1, x2);
-      const double th = clamp_theta(g, x2 * g.dth);
+      double r, rd, th, td, dtd;
+      map_r(g, x1, &r, &rd);
+      map_theta(g, x2, &th, &td, &dtd);
       double s, c;
-      sincos(th, &s, &c);
-      const WaldPot w = wald_pot(g, exp(g.xi_min + x1 * g.dxi), s, c, B0);
+      sincos(clamp_theta(g, th), &s, &c);
+      const WaldPot w = wald_pot(g, r, s, c, B0);
       const double qm = species_sign(t);
       E = m.alpha * gamma_of(m, u1, u2, u3, mass2_of(t)) - m.beta1 * u1 - qm * w.A0;
       L = u3 + qm * w.A3;

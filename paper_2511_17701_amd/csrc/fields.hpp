@@ -6,8 +6,9 @@
 //
 // Threads run along theta (the contiguous index of a plane), blocks along r.
 // Geometry at staggered grid points is assembled from 1-D tables of r and
-// 1/(dxi r dtheta) at integer / half-integer x1 and of sin, cos and 1/sin at
-// integer / half-integer x2, with one reciprocal square root per point.
+// 1/(R deta) at integer / half-integer x1 and of sin, cos, 1/sin (and, when
+// h0 != 0, T = dtheta/dx2 and deta/T) at integer / half-integer x2, with one
+// reciprocal square root per point; R = dr/dx1 = dxi (r - r0).
 #pragma once
 
 #include "geometry.hpp"
@@ -15,23 +16,23 @@
 namespace grpic {
 
 __device__ inline Cell cell_tab(const Grid& g, const Tables& t, int i, int o1, int j, int o2) {
-  const double r = t.r[o1][i + g.ng];
+  const double r = t.r[o1][i + g.ng], R = g.dxi * (r - g.r0);
   const double s = t.s[o2][j + g.ng], c = t.c[o2][j + g.ng];
+  const double T = g.h0 == 0.0 ? g.dth : t.td[o2][j + g.ng];
   const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r;
   const double Sig = r2 + a2 * c * c;
   const double S2 = Sig + tMr;
   const double ra = r2 + a2;
   const double A = ra * ra - a2 * (ra - tMr) * s * s;
-  const double R = g.dxi * r;
   const double opz = S2 / Sig;
   Cell e;
   e.alpha = sqrt(Sig / S2);
   e.beta1 = tMr / (S2 * R);
   e.hl11 = opz * R * R;
-  e.hl22 = Sig * g.dth * g.dth;
+  e.hl22 = Sig * T * T;
   e.hl33 = A * s * s / Sig;
   e.hl13 = -g.a * opz * s * s * R;
-  e.sqrt_ht = R * g.dth * Sig / e.alpha;
+  e.sqrt_ht = R * T * Sig / e.alpha;
   e.sqrt_h = e.sqrt_ht * s;
   return e;
 }
@@ -39,8 +40,8 @@ __device__ inline Cell cell_tab(const Grid& g, const Tables& t, int i, int o1, i
 // ---------------------------------------------------------------- weights
 // Solver weights at one staggered point (i + o1/2, j + o2/2).  With
 // S2 = Sigma + 2 M r and k = 1/sqrt(Sigma S2), the lapse is Sigma k,
-// 1/Sigma = S2 k^2, 1/S2 = Sigma k^2 and sqrt(h)/sin(theta) = R dtheta / k
-// (R = dxi r), so one reciprocal square root gives every factor of the
+// 1/Sigma = S2 k^2, 1/S2 = Sigma k^2 and sqrt(h)/sin(theta) = R T / k
+// (R = dr/dx1, T = dtheta/dx2), so one reciprocal square root gives every factor of the
 // closed forms of App. A (the same quantities as cell_tab).
 struct FW {
   double alpha;                   // lapse
@@ -51,25 +52,29 @@ struct FW {
   double ish;                     // 1 / sqrt(h)              (0 on the axis)
 };
 
+// kQ: the general quasi-spherical map (r0, h0 not both 0); otherwise the
+// logarithmic-r, uniform-theta grid, with R = dxi r and T = deta.
+template <bool kQ>
 __device__ inline FW fw_tab(const Grid& g, const Tables& t, int i, int o1, int j, int o2) {
-  const double r = t.r[o1][i + g.ng], ird = t.ird[o1][i + g.ng];
+  const double r = t.r[o1][i + g.ng], R = g.dxi * (kQ ? r - g.r0 : r);
   const double s = t.s[o2][j + g.ng], c = t.c[o2][j + g.ng], is = t.is[o2][j + g.ng];
+  const double T = kQ ? t.td[o2][j + g.ng] : g.dth;
+  const double ird = kQ ? t.ird[o1][i + g.ng] * t.eta_t[o2][j + g.ng] : t.ird[o1][i + g.ng];  // 1/(R T)
   const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r, s2 = s * s;
   const double Sig = r2 + a2 * c * c;
   const double S2 = Sig + tMr;
   const double ra = r2 + a2;
   const double A = ra * ra - a2 * (ra - tMr) * s2;
-  const double R = g.dxi * r;
   const double k = rsqrt(Sig * S2);
   const double k2 = k * k;
   const double S2k = S2 * k;
   FW e;
   e.alpha = Sig * k;
   e.hl11 = S2k * S2k * R * R;
-  e.hl22 = Sig * g.dth * g.dth;
+  e.hl22 = Sig * T * T;
   e.hl33 = A * s2 * S2 * k2;
-  e.w13 = -g.a * g.dth * R * R * s2 * S2 * S2k;
-  e.wb = R * g.dth * g.dth * s * tMr * Sig;
+  e.w13 = -g.a * T * R * R * s2 * S2 * S2k;
+  e.wb = R * T * T * s * tMr * Sig;
   e.h_sht = 0.5 * k * ird;
   e.ish = k * ird * is;
   return e;
@@ -119,7 +124,7 @@ __device__ inline PlaneIdx plane_idx(const Grid& g) {
 // eq. discretized-auxE/-auxH with the volume-weighted radial averages of
 // Sec. 3.3.1 (weights sqrt(h)/sin(theta)); for i in [-1, n_r], j in [0, n_th].
 // kE / kH select the outputs; both read the same B, D and share the weights.
-template <class T, bool kE, bool kH>
+template <class T, bool kE, bool kH, bool kQ>
 __global__ void aux_kernel(Grid g, Tables t, CTriT<T> Bs, CTriT<T> Ds, TriT<T> E, TriT<T> H) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y - 1;
@@ -127,14 +132,14 @@ __global__ void aux_kernel(Grid g, Tables t, CTriT<T> Bs, CTriT<T> Ds, TriT<T> E
   const int64_t o = ix(g, i, j), ld = g.ld;
   const bool half = j < g.n_th;  // theta-staggered components exist
   // weights at the points the stencils touch (unused ones are not computed)
-  const FW n00 = fw_tab(g, t, i, 0, j, 0);       // (i, j)
-  const FW n10 = fw_tab(g, t, i + 1, 0, j, 0);   // (i+1, j)
-  const FW h00 = fw_tab(g, t, i, 1, j, 0);       // (i+1/2, j)
-  const FW hm0 = fw_tab(g, t, i - 1, 1, j, 0);   // (i-1/2, j)
-  const FW n01 = fw_tab(g, t, i, 0, j, 1);       // (i, j+1/2)
-  const FW n11 = fw_tab(g, t, i + 1, 0, j, 1);   // (i+1, j+1/2)
-  const FW h01 = fw_tab(g, t, i, 1, j, 1);       // (i+1/2, j+1/2)
-  const FW hm1 = fw_tab(g, t, i - 1, 1, j, 1);   // (i-1/2, j+1/2)
+  const FW n00 = fw_tab<kQ>(g, t, i, 0, j, 0);       // (i, j)
+  const FW n10 = fw_tab<kQ>(g, t, i + 1, 0, j, 0);   // (i+1, j)
+  const FW h00 = fw_tab<kQ>(g, t, i, 1, j, 0);       // (i+1/2, j)
+  const FW hm0 = fw_tab<kQ>(g, t, i - 1, 1, j, 0);   // (i-1/2, j)
+  const FW n01 = fw_tab<kQ>(g, t, i, 0, j, 1);       // (i, j+1/2)
+  const FW n11 = fw_tab<kQ>(g, t, i + 1, 0, j, 1);   // (i+1, j+1/2)
+  const FW h01 = fw_tab<kQ>(g, t, i, 1, j, 1);       // (i+1/2, j+1/2)
+  const FW hm1 = fw_tab<kQ>(g, t, i - 1, 1, j, 1);   // (i-1/2, j+1/2)
   if (kE) {
     {  // E_1 (i+1/2, j)
       const double av = (n00.w13 * Ds.p[2][o] + n10.w13 * Ds.p[2][o + ld]) * h00.h_sht;
@@ -173,7 +178,7 @@ __global__ void aux_kernel(Grid g, Tables t, CTriT<T> Bs, CTriT<T> Ds, TriT<T> E
 // eq. discretized-faraday on the evolved ranges i in [0, n_r], j in [0, n_th].
 // With kSave the grid spans the whole plane and X0 <- X (the field before the
 // update, ghosts included) is taken in the same pass.
-template <class T, bool kSave>
+template <class T, bool kSave, bool kQ>
 __global__ void faraday_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> E, TriT<T> X0) {
   int i, j;
   if (kSave) {
@@ -192,15 +197,15 @@ __global__ void faraday_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> 
   }
   if (i < 0 || j < 0 || j > g.n_th || i > g.n_r) return;
   if (j < g.n_th) {
-    const double ish = fw_tab(g, t, i, 0, j, 1).ish;
+    const double ish = fw_tab<kQ>(g, t, i, 0, j, 1).ish;
     add_to(X.p[0], L.p[0], o, -(g.dt * (E.p[2][o + 1] - E.p[2][o]) * ish));
   }
   if (i < g.n_r && j >= 1 && j < g.n_th) {
-    const double ish = fw_tab(g, t, i, 1, j, 0).ish;
+    const double ish = fw_tab<kQ>(g, t, i, 1, j, 0).ish;
     add_to(X.p[1], L.p[1], o, g.dt * (E.p[2][o + g.ld] - E.p[2][o]) * ish);
   }
   if (i < g.n_r && j < g.n_th) {
-    const double ish = fw_tab(g, t, i, 1, j, 1).ish;
+    const double ish = fw_tab<kQ>(g, t, i, 1, j, 1).ish;
     const double curl = (E.p[1][o + g.ld] - E.p[1][o]) - (E.p[0][o + 1] - E.p[0][o]);
     add_to(X.p[2], L.p[2], o, -(g.dt * curl * ish));
   }
@@ -214,7 +219,7 @@ __global__ void faraday_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> 
 // kFinal (the last half of the step): the grid spans the whole plane, the
 // current is Ja alone, and the same pass takes X0 <- X before the update and
 // rotates the currents, Jb <- Ja and Ja <- 0, after it.
-template <class T, bool kFinal>
+template <class T, bool kFinal, bool kQ>
 __global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H, TriT<T> Ja, TriT<T> Jb, double wa,
                               double wb, double polar_k, TriT<T> X0) {
   int i, j;
@@ -240,23 +245,23 @@ __global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H
     if (i < g.n_r) {
       const double J1 = cur(0);
       if (j >= 1 && j < g.n_th) {
-        const double ish = fw_tab(g, t, i, 1, j, 0).ish;
+        const double ish = fw_tab<kQ>(g, t, i, 1, j, 0).ish;
         add_to(X.p[0], L.p[0], o, g.dt * ((H.p[2][o] - H.p[2][o - 1]) - fpi * J1) * ish);
       } else {
         const double r = t.r[1][i + g.ng];
         const double ra = r * r + g.a * g.a;
-        const double Ap = g.dxi * r * ra * sqrt(1.0 + 2.0 * g.M * r / ra) * polar_k;
+        const double Ap = g.dxi * (kQ ? r - g.r0 : r) * ra * sqrt(1.0 + 2.0 * g.M * r / ra) * polar_k;
         const double h3 = (j == 0) ? H.p[2][o] : -H.p[2][o - 1];
         add_to(X.p[0], L.p[0], o, g.dt * (h3 - fpi * J1) / Ap);
       }
     }
     if (j < g.n_th) {
-      const double ish = fw_tab(g, t, i, 0, j, 1).ish;
+      const double ish = fw_tab<kQ>(g, t, i, 0, j, 1).ish;
       const double J2 = cur(1);
       add_to(X.p[1], L.p[1], o, g.dt * (-(H.p[2][o] - H.p[2][o - g.ld]) - fpi * J2) * ish);
     }
     if (j >= 1 && j < g.n_th) {
-      const double ish = fw_tab(g, t, i, 0, j, 0).ish;
+      const double ish = fw_tab<kQ>(g, t, i, 0, j, 0).ish;
       const double J3 = cur(2);
       const double curl = (H.p[1][o] - H.p[1][o - g.ld]) - (H.p[0][o] - H.p[0][o - 1]);
       add_to(X.p[2], L.p[2], o, g.dt * (curl - fpi * J3) * ish);

@@ -1,8 +1,10 @@
 // geometry.hpp -- grid description and Kerr-Schild 3+1 geometry in code
 // coordinates, evaluated on the device (and on the host for dt and tables).
 //
-// Code coordinates (App. A, quasi-spherical Kerr-Schild with r0 = h0 = 0):
-//   r = exp(xi_min + x1 dxi), theta = x2 dth, phi with dphi = 1.
+// Code coordinates (App. A, quasi-spherical Kerr-Schild): r = r0 + exp(xi),
+//   xi = xi_min + x1 dxi; theta = eta + 2 h0 eta (pi - 2 eta)(pi - eta) / pi^2,
+//   eta = x2 dth (dth is the uniform eta spacing); phi with dphi = 1.
+//   r0 = h0 = 0 is the logarithmic-r, uniform-theta grid.
 // Kerr-Schild 3+1 split (Sec. 2.1, App. A), with S2 = Sigma + 2 M r:
 //   Sigma = r^2 + a^2 cos^2, Delta = r^2 - 2 M r + a^2,
 //   A = (r^2 + a^2)^2 - a^2 Delta sin^2, alpha^2 = Sigma / S2,
@@ -10,8 +12,8 @@
 //   h^thth = 1 / Sigma, h^phiphi = 1 / (Sigma sin^2),
 //   h_rr = S2 / Sigma, h_rphi = -a (S2 / Sigma) sin^2, h_thth = Sigma,
 //   h_phiphi = A sin^2 / Sigma, sqrt(h) = Sigma sin / alpha.
-// A covariant index 1 carries a factor R = dr/dx1 = dxi r, index 2 a factor
-// dth; contravariant indices the inverse factors.
+// A covariant index 1 carries a factor R = dr/dx1 = dxi (r - r0), index 2 a
+// factor T = dtheta/dx2; contravariant indices the inverse factors.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,7 +28,8 @@ constexpr double kPi = 3.14159265358979323846;
 // Everything a kernel needs to know about the grid and the run, by value.
 struct Grid {
   double a, M;
-  double xi_min, dxi, dth, inv_dth2;
+  double xi_min, dxi, dth, inv_dth2;  // xi_min = log(r_min - r0); dth: eta spacing
+  double r0, h0;                      // quasi-spherical map (0, 0: log r, uniform theta)
   double dt;
   double small_angle;
   double charge_scale;
@@ -45,14 +48,19 @@ __host__ __device__ inline int64_t ix(const Grid& g, int i, int j) {
   return (int64_t)(i + g.ng) * g.ld + (j + g.ng);
 }
 
-// 1-D coordinate tables, indexed by (index + ng); [0] integer, [1] half-integer;
-// rf, sf, cf: single-precision copies of the integer-point tables.
+// 1-D coordinate tables, indexed by (index + ng); [0] integer, [1] half-integer
+// points: r and 1/(R deta) along x1 (R = dr/dx1, deta the eta spacing); sin,
+// cos, 1/sin (0 on the axis), T = dtheta/dx2 and deta/T along x2 (T = deta and
+// deta/T = 1 when h0 = 0).  rf: r - r0 at integer x1, sf, cf: sin, cos at
+// integer x2, in single precision.
 struct Tables {
   const double* __restrict__ r[2];
+  const double* __restrict__ ird[2];
   const double* __restrict__ s[2];
   const double* __restrict__ c[2];
-  const double* __restrict__ ird[2];  // 1 / (dxi r dtheta) at integer / half-integer x1
-  const double* __restrict__ is[2];   // 1 / sin(theta) (0 on the axis) at integer / half-integer x2
+  const double* __restrict__ is[2];
+  const double* __restrict__ td[2];
+  const double* __restrict__ eta_t[2];
   const float* __restrict__ rf;
   const float* __restrict__ sf;
   const float* __restrict__ cf;
@@ -78,10 +86,12 @@ struct GradT {
   R alpha[2], beta1[2], hu11[2], hu22[2], hu33[2], hu13[2];
 };
 
-// r, sin(theta), cos(theta) of a point
+// r, sin(theta), cos(theta) of a point, and the map factors there:
+// rd = dr/dx1, td = dtheta/dx2, itd2 = 1/td^2, dtd = d td / dx2
 template <class R>
 struct RSCT {
   R r, s, c;
+  R rd, td, itd2, dtd;
 };
 
 using Coeffs = CoeffsT<double>;
@@ -148,15 +158,45 @@ __host__ __device__ inline float rsqrt(float x) {
 #endif
 }
 
-// r and clamped sin/cos by the library functions
+// The quasi-spherical map (App. A): r and R = dr/dx1 at x1; theta,
+// T = dtheta/dx2 and dT/dx2 at x2.  Beyond either axis the polar map is
+// continued by reflection (theta(-x2) = -theta(x2), theta(2 n_th - x2) =
+// 2 pi - theta(x2)), so that geometry there mirrors the interior.
+__host__ __device__ inline void map_r(const Grid& g, double x1, double* r, double* rd) {
+  const double e = exp(g.xi_min + x1 * g.dxi);
+  *r = g.r0 + e;
+  *rd = g.dxi * e;
+}
+
+__host__ __device__ inline void map_theta(const Grid& g, double x2, double* th, double* td,
+                                          double* dtd) {
+  double sg = 1.0, off = 0.0;
+  if (x2 < 0.0) {
+    x2 = -x2;
+    sg = -1.0;
+  } else if (x2 > (double)g.n_th) {
+    x2 = 2.0 * g.n_th - x2;
+    sg = -1.0;
+    off = 2.0 * kPi;
+  }
+  const double eta = x2 * g.dth, y = eta * (1.0 / kPi), h0 = g.h0;
+  *th = off + sg * (eta + 2.0 * h0 * eta * (kPi - 2.0 * eta) * (kPi - eta) * (1.0 / (kPi * kPi)));
+  *td = g.dth * (1.0 + 2.0 * h0 + 12.0 * h0 * y * (y - 1.0));
+  *dtd = sg * g.dth * g.dth * 12.0 * h0 * (2.0 * y - 1.0) * (1.0 / kPi);
+}
+
+// r, clamped sin/cos and the map factors by the library functions
 __host__ __device__ inline RSC rsc_direct(const Grid& g, double x1, double x2) {
   RSC p;
-  p.r = exp(g.xi_min + x1 * g.dxi);
-  sin_cos(clamp_theta(g, x2 * g.dth), &p.s, &p.c);
+  map_r(g, x1, &p.r, &p.rd);
+  double th;
+  map_theta(g, x2, &th, &p.td, &p.dtd);
+  p.itd2 = 1.0 / (p.td * p.td);
+  sin_cos(clamp_theta(g, th), &p.s, &p.c);
   return p;
 }
 
-// Inverse metric, lapse and shift at a point (R = dxi r).
+// Inverse metric, lapse and shift at a point (R = dr/dx1).
 template <class R>
 __host__ __device__ inline CoeffsT<R> coeffs_from(const Grid& g, RSCT<R> p) {
   const R r = p.r, s = p.s, c = p.c;
@@ -166,7 +206,7 @@ __host__ __device__ inline CoeffsT<R> coeffs_from(const Grid& g, RSCT<R> p) {
   const R ra = r2 + a2;
   const R s2 = s * s;
   const R A = ra * ra - a2 * (ra - tMr) * s2;
-  const R Rr = (R)g.dxi * r;
+  const R Rr = p.rd;
   // one reciprocal for 1/Sigma, 1/S2, 1/sin^2 and 1/R
   const R q = rcp(Sig * S2 * s2 * Rr);
   const R iSig = S2 * s2 * Rr * q, iS2 = Sig * s2 * Rr * q;
@@ -177,7 +217,7 @@ __host__ __device__ inline CoeffsT<R> coeffs_from(const Grid& g, RSCT<R> p) {
   m.beta1 = tMr * iS2 * iR;
   m.hu11 = A * iSig * iS2 * iR * iR;
   m.hu13 = a * iSig * iR;
-  m.hu22 = iSig * (R)g.inv_dth2;
+  m.hu22 = iSig * p.itd2;
   m.hu33 = iSig * is2;
   return m;
 }
@@ -190,7 +230,7 @@ __host__ __device__ inline Coeffs coeffs_at(const Grid& g, double x1, double x2)
 template <class R>
 __host__ __device__ inline void frame_from(const Grid& g, RSCT<R> p, FrameT<R>* f, GradT<R>* d) {
   const R r = p.r, s = p.s, c = p.c;
-  const R a = (R)g.a, M = (R)g.M, dxi = (R)g.dxi, dth = (R)g.dth;
+  const R a = (R)g.a, M = (R)g.M, dxi = (R)g.dxi, dth = p.td;
   const R a2 = a * a, r2 = r * r, tMr = (R)2 * M * r;
   const R Sig = r2 + a2 * c * c;
   const R S2 = Sig + tMr;
@@ -198,7 +238,7 @@ __host__ __device__ inline void frame_from(const Grid& g, RSCT<R> p, FrameT<R>* 
   const R Del = ra - tMr;
   const R s2 = s * s;
   const R A = ra * ra - a2 * Del * s2;
-  const R Rr = dxi * r;
+  const R Rr = p.rd;
   const R q = rcp(Sig * S2 * s2 * Rr * A);
   const R iSig = S2 * s2 * Rr * A * q, iS2 = Sig * s2 * Rr * A * q;
   const R is2 = Sig * S2 * Rr * A * q, iR = Sig * S2 * s2 * A * q;
@@ -212,7 +252,7 @@ __host__ __device__ inline void frame_from(const Grid& g, RSCT<R> p, FrameT<R>* 
   const R hrr = A * iSig * iS2;
   f->c.hu11 = hrr * iR * iR;
   f->c.hu13 = a * iSig * iR;
-  f->c.hu22 = iSig * (R)g.inv_dth2;
+  f->c.hu22 = iSig * p.itd2;
   f->c.hu33 = iSig * is2;
   f->s11 = hrr * rsqrt(hrr) * iR;
   f->s22 = Sig * rsqrt(Sig) * dth;
@@ -242,9 +282,9 @@ __host__ __device__ inline void frame_from(const Grid& g, RSCT<R> p, FrameT<R>* 
   // h^13 = a / (Sigma R)
   d->hu13[0] = -a * dSig_r * iSig2 - dxi * f->c.hu13;
   d->hu13[1] = -dth * a * dSig_t * iSig2 * iR;
-  // h^22 = 1 / (Sigma dth^2)
-  d->hu22[0] = -Rr * dSig_r * iSig2 * (R)g.inv_dth2;
-  d->hu22[1] = -dSig_t * iSig2 * (R)(g.dth * g.inv_dth2);
+  // h^22 = 1 / (Sigma T^2), T = dtheta/dx2 (its own x2 derivative included)
+  d->hu22[0] = -Rr * dSig_r * iSig2 * p.itd2;
+  d->hu22[1] = -(dth * dSig_t * iSig2 + (R)2 * p.dtd * iSig * dth * p.itd2) * p.itd2;
   // h^33 = 1 / (Sigma sin^2)
   d->hu33[0] = -Rr * dSig_r * iSig2 * is2;
   d->hu33[1] = -dth * (dSig_t + (R)2 * Sig * c * s * is2) * iSig2 * is2;
@@ -261,25 +301,26 @@ struct Cell {
 };
 
 __host__ __device__ inline Cell cell_at(const Grid& g, double x1, double x2) {
-  const double r = exp(g.xi_min + x1 * g.dxi);
+  double r, R, th, T, dT;
+  map_r(g, x1, &r, &R);
+  map_theta(g, x2, &th, &T, &dT);
   double s, c;
-  sin_cos(x2 * g.dth, &s, &c);
+  sin_cos(th, &s, &c);
   const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r;
   const double Sig = r2 + a2 * c * c;
   const double S2 = Sig + tMr;
   const double ra = r2 + a2;
   const double A = ra * ra - a2 * (ra - tMr) * s * s;
-  const double R = g.dxi * r;
   const double iSig = 1.0 / Sig;
   const double opz = S2 * iSig;  // 1 + z
   Cell e;
   e.alpha = sqrt(Sig / S2);
   e.beta1 = tMr / (S2 * R);
   e.hl11 = opz * R * R;
-  e.hl22 = Sig * g.dth * g.dth;
+  e.hl22 = Sig * T * T;
   e.hl33 = A * s * s * iSig;
   e.hl13 = -g.a * opz * s * s * R;
-  e.sqrt_ht = R * g.dth * Sig / e.alpha;
+  e.sqrt_ht = R * T * Sig / e.alpha;
   e.sqrt_h = e.sqrt_ht * s;
   return e;
 }

@@ -24,7 +24,7 @@ struct grpic_ctx {
   double* tables;  // r[2], s[2], c[2] (n + 2 ng each), then float r, sin, cos at nodes
   Tables tab;
   DiagAcc* acc;    // device accumulators for diagnostics
-  double polar_k;  // 1 - cos(dth / 2)
+  double polar_k;  // 1 - cos(theta(x2 = 1/2)): the polar cap of the axis update
   int* sort_off;   // n_cells + 1 counts / offsets, then block sums, then n_live
   int* sort_sums;
   int* sort_live;
@@ -339,7 +339,7 @@ grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_par
   return GRPIC_OK;
 }
 
-template <class T>
+template <class T, bool kQ>
 grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t stage, hipStream_t s) {
   grpic_status st;
   const Grid& g = c->g;
@@ -351,10 +351,10 @@ grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t sta
     hipLaunchKernelGGL(average_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, tri<T>(F->B0),
                        ctri<T>(F->B), tri<T>(F->D0), ctri<T>(F->D));
     LAUNCH_CHECK("average");
-    hipLaunchKernelGGL((aux_kernel<T, true, false>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B),
+    hipLaunchKernelGGL((aux_kernel<T, true, false, kQ>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B),
                        ctri<T>(F->D0), tri<T>(F->E), none<T>());
     LAUNCH_CHECK("aux_e");
-    hipLaunchKernelGGL((faraday_kernel<T, false>), gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->B0), none<T>(),
+    hipLaunchKernelGGL((faraday_kernel<T, false, kQ>), gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->B0), none<T>(),
                        ctri<T>(F->E), none<T>());
     LAUNCH_CHECK("faraday");
     return field_bc<T>(c, tri<T>(F->B0), none<T>(), ctri<T>(F->Binit), true, s);
@@ -363,23 +363,23 @@ grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t sta
   // second plane set
   if ((st = filter_passes<T>(c, tri<T>(F->J), tri<T>(F->T), 3, kStagD2, int3{1, -1, -1}, s))) return st;
   // E, H from (B0, D); B0 <- B and B += Faraday(E)
-  hipLaunchKernelGGL((aux_kernel<T, true, true>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B0),
+  hipLaunchKernelGGL((aux_kernel<T, true, true, kQ>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B0),
                      ctri<T>(F->D), tri<T>(F->E), tri<T>(F->H));
   LAUNCH_CHECK("aux_eh");
-  hipLaunchKernelGGL((faraday_kernel<T, true>), gpl2, kBlock2, 0, s, g, c->tab, tri<T>(F->B), comp<T>(c, F->Bc),
+  hipLaunchKernelGGL((faraday_kernel<T, true, kQ>), gpl2, kBlock2, 0, s, g, c->tab, tri<T>(F->B), comp<T>(c, F->Bc),
                      ctri<T>(F->E), tri<T>(F->B0));
   LAUNCH_CHECK("faraday");
   if ((st = field_bc<T>(c, tri<T>(F->B), comp<T>(c, F->Bc), ctri<T>(F->Binit), true, s))) return st;
   // D0 += Ampere(H, (J0 + J)/2)
-  hipLaunchKernelGGL((ampere_kernel<T, false>), gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->D0), none<T>(),
+  hipLaunchKernelGGL((ampere_kernel<T, false, kQ>), gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->D0), none<T>(),
                      ctri<T>(F->H), tri<T>(F->J0), tri<T>(F->J), 0.5, 0.5, c->polar_k, none<T>());
   LAUNCH_CHECK("ampere");
   if ((st = field_bc<T>(c, tri<T>(F->D0), none<T>(), ctri<T>(F->Dinit), false, s))) return st;
   // H from (B, D0); D0 <- D, D += Ampere(H, J), J0 <- J, J <- 0
-  hipLaunchKernelGGL((aux_kernel<T, false, true>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B),
+  hipLaunchKernelGGL((aux_kernel<T, false, true, kQ>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B),
                      ctri<T>(F->D0), none<T>(), tri<T>(F->H));
   LAUNCH_CHECK("aux_h");
-  hipLaunchKernelGGL((ampere_kernel<T, true>), gpl2, kBlock2, 0, s, g, c->tab, tri<T>(F->D), comp<T>(c, F->Dc),
+  hipLaunchKernelGGL((ampere_kernel<T, true, kQ>), gpl2, kBlock2, 0, s, g, c->tab, tri<T>(F->D), comp<T>(c, F->Dc),
                      ctri<T>(F->H), tri<T>(F->J), tri<T>(F->J0), 1.0, 0.0, c->polar_k, tri<T>(F->D0));
   LAUNCH_CHECK("ampere");
   return field_bc<T>(c, tri<T>(F->D), comp<T>(c, F->Dc), ctri<T>(F->Dinit), false, s);
@@ -440,6 +440,8 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     return fail(GRPIC_EINVAL, "boundary layers overlap (n_filter %d, n_absorb %d, n_r %d)", p->n_filter,
                 p->n_absorb, p->n_r);
   if (!(p->r_min > 0.0) || !(p->r_max > p->r_min)) return fail(GRPIC_EINVAL, "need 0 < r_min < r_max");
+  if (!(p->r0 >= 0.0 && p->r0 < p->r_min)) return fail(GRPIC_EINVAL, "need 0 <= r0 < r_min");
+  if (!(p->h0 > -0.5 && p->h0 < 1.0)) return fail(GRPIC_EINVAL, "need -1/2 < h0 < 1");
   if (!((p->M > 0.0 && std::fabs(p->a) < p->M) || (p->M == 0.0 && p->a == 0.0)))
     return fail(GRPIC_EINVAL, "need |a| < M (or M = a = 0)");
   if (!(p->small_angle > 0.0 && p->small_angle < 0.1)) return fail(GRPIC_EINVAL, "small_angle out of range");
@@ -454,8 +456,10 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   Grid& g = c->g;
   g.a = p->a;
   g.M = p->M;
-  g.xi_min = std::log(p->r_min);
-  g.dxi = std::log(p->r_max / p->r_min) / p->n_r;
+  g.r0 = p->r0;
+  g.h0 = p->h0;
+  g.xi_min = std::log(p->r_min - p->r0);
+  g.dxi = std::log((p->r_max - p->r0) / (p->r_min - p->r0)) / p->n_r;
   g.dth = kPi / p->n_th;
   g.inv_dth2 = 1.0 / (g.dth * g.dth);
   g.small_angle = p->small_angle;
@@ -488,7 +492,12 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     g.dt = p->cfl / vmax;
   }
   c->prm.dt = g.dt;
-  c->polar_k = 1.0 - std::cos(0.5 * g.dth);
+  {
+    // the polar cap of the axis update ends at theta(x2 = 1/2)
+    double thc, td, dtd;
+    map_theta(g, 0.5, &thc, &td, &dtd);
+    c->polar_k = 1.0 - std::cos(thc);
+  }
   g.sin_lo = std::sin(p->small_angle);
   g.cos_lo = std::cos(p->small_angle);
   g.sin_hi = std::sin(kPi - p->small_angle);
@@ -496,23 +505,27 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   // the push evaluates exp and sincos of in-cell offsets (at most 1.5 cells)
   // by series that are exact to rounding for arguments up to 0.03 (short) or
   // 0.11 (long)
+  // (the series are written for the logarithmic-r, uniform-theta grid; a
+  // general quasi-spherical map takes the library functions)
   {
     const double off = 1.5 * std::fmax(g.dxi, g.dth);
     g.ser = (off <= 0.03 && 4.0 * g.dth <= 0.03) ? 2 : (off <= 0.11 ? 1 : 0);
+    if (g.r0 != 0.0 || g.h0 != 0.0) g.ser = 0;
   }
   // single-precision push: cells whose inner edge lies below r = 3 M keep the
   // metric and its derivatives in FP64 (the horizon region, where lapse and
   // shift vary fastest)
   g.i_fp64 = 0;
-  if (g.M > 0.0) {
-    const double x = std::ceil((std::log(3.0 * g.M) - g.xi_min) / g.dxi);
+  if (g.M > 0.0 && 3.0 * g.M > g.r0) {
+    const double x = std::ceil((std::log(3.0 * g.M - g.r0) - g.xi_min) / g.dxi);
     g.i_fp64 = (int)std::fmin(std::fmax(x, 0.0), (double)p->n_r);
   }
 
   hipError_t e = hipGetDevice(&c->device);
   const int nr = p->n_r + 2 * p->n_ghost, nt = p->n_th + 2 * p->n_ghost;
-  const size_t nt_all = 4 * (size_t)nr + 6 * (size_t)nt;  // r, 1/(dxi r dtheta); sin, cos, 1/sin
-  const size_t nf_all = (size_t)nr + 2 * (size_t)nt;  // float r, sin, cos at integer nodes
+  // r, 1/(R deta); sin, cos, 1/sin, T = dtheta/dx2, deta/T (integer, half-integer)
+  const size_t nt_all = 4 * (size_t)nr + 10 * (size_t)nt;
+  const size_t nf_all = (size_t)nr + 2 * (size_t)nt;  // float r - r0, sin, cos at integer nodes
   const size_t bytes = nt_all * sizeof(double) + nf_all * sizeof(float);
   if (e == hipSuccess) e = hipMalloc(&c->tables, bytes);
   if (e != hipSuccess) {
@@ -539,36 +552,44 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     c->sort_live = c->sort_sums + nb;
   }
   double* h = new double[(bytes + sizeof(double) - 1) / sizeof(double)];
-  double* pr0 = h;
-  double* pr1 = h + nr;
-  double* ps0 = h + 2 * nr;
-  double* ps1 = ps0 + nt;
-  double* pc0 = ps1 + nt;
-  double* pc1 = pc0 + nt;
-  double* pq0 = pc1 + nt;  // 1 / (dxi r dtheta)
-  double* pq1 = pq0 + nr;
-  double* pi0 = pq1 + nr;  // 1 / sin
-  double* pi1 = pi0 + nt;
-  for (int i = 0; i < nr; ++i) {
-    pr0[i] = std::exp(g.xi_min + (double)(i - g.ng) * g.dxi);
-    pr1[i] = std::exp(g.xi_min + ((double)(i - g.ng) + 0.5) * g.dxi);
-    pq0[i] = 1.0 / (g.dxi * pr0[i] * g.dth);
-    pq1[i] = 1.0 / (g.dxi * pr1[i] * g.dth);
-  }
-  for (int j = 0; j < nt; ++j) {
-    const double t0 = (double)(j - g.ng) * g.dth, t1 = ((double)(j - g.ng) + 0.5) * g.dth;
-    ps0[j] = std::sin(t0);
-    pc0[j] = std::cos(t0);
-    ps1[j] = std::sin(t1);
-    pc1[j] = std::cos(t1);
-    pi0[j] = (j == g.ng || j == g.ng + p->n_th) ? 0.0 : 1.0 / ps0[j];  // no inverse on the axis
-    pi1[j] = 1.0 / ps1[j];
+  // layout: r[2], ird[2] (nr each); s[2], c[2], is[2], td[2], eta_t[2] (nt each)
+  double* tr[2] = {h, h + nr};
+  double* tird[2] = {h + 2 * nr, h + 3 * nr};
+  double* ts[2] = {h + 4 * nr, h + 4 * nr + nt};
+  double* tc[2] = {ts[1] + nt, ts[1] + 2 * nt};
+  double* tis[2] = {tc[1] + nt, tc[1] + 2 * nt};
+  double* ttd[2] = {tis[1] + nt, tis[1] + 2 * nt};
+  double* tet[2] = {ttd[1] + nt, ttd[1] + 2 * nt};
+  for (int o = 0; o < 2; ++o) {
+    for (int i = 0; i < nr; ++i) {
+      double rd;
+      map_r(g, (double)(i - g.ng) + 0.5 * o, &tr[o][i], &rd);
+      tird[o][i] = 1.0 / (rd * g.dth);
+    }
+    for (int j = 0; j < nt; ++j) {
+      double th, dtd;
+      map_theta(g, (double)(j - g.ng) + 0.5 * o, &th, &ttd[o][j], &dtd);
+      ts[o][j] = std::sin(th);
+      tc[o][j] = std::cos(th);
+      const bool axis = o == 0 && (j == g.ng || j == g.ng + p->n_th);
+      tis[o][j] = axis ? 0.0 : 1.0 / ts[o][j];  // no inverse on the axis
+      tet[o][j] = g.dth / ttd[o][j];
+    }
   }
   float* hf = reinterpret_cast<float*>(h + nt_all);
-  for (int i = 0; i < nr; ++i) hf[i] = (float)pr0[i];
+  for (int i = 0; i < nr; ++i) hf[i] = (float)(tr[0][i] - g.r0);
   for (int j = 0; j < nt; ++j) {
-    hf[nr + j] = (float)ps0[j];
-    hf[nr + nt + j] = (float)pc0[j];
+    hf[nr + j] = (float)ts[0][j];
+    hf[nr + nt + j] = (float)tc[0][j];
+  }
+  for (int o = 0; o < 2; ++o) {
+    c->tab.r[o] = c->tables + (tr[o] - h);
+    c->tab.ird[o] = c->tables + (tird[o] - h);
+    c->tab.s[o] = c->tables + (ts[o] - h);
+    c->tab.c[o] = c->tables + (tc[o] - h);
+    c->tab.is[o] = c->tables + (tis[o] - h);
+    c->tab.td[o] = c->tables + (ttd[o] - h);
+    c->tab.eta_t[o] = c->tables + (tet[o] - h);
   }
   e = hipMemcpy(c->tables, h, bytes, hipMemcpyHostToDevice);
   delete[] h;
@@ -579,16 +600,6 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     delete c;
     return fail(GRPIC_EHIP, "table upload: %s", hipGetErrorString(e));
   }
-  c->tab.r[0] = c->tables;
-  c->tab.r[1] = c->tables + nr;
-  c->tab.s[0] = c->tables + 2 * nr;
-  c->tab.s[1] = c->tab.s[0] + nt;
-  c->tab.c[0] = c->tab.s[1] + nt;
-  c->tab.c[1] = c->tab.c[0] + nt;
-  c->tab.ird[0] = c->tab.c[1] + nt;
-  c->tab.ird[1] = c->tab.ird[0] + nr;
-  c->tab.is[0] = c->tab.ird[1] + nr;
-  c->tab.is[1] = c->tab.is[0] + nt;
   const float* tf = reinterpret_cast<const float*>(c->tables + nt_all);
   c->tab.rf = tf;
   c->tab.sf = tf + nr;
@@ -625,7 +636,7 @@ grpic_status grpic_particles_init(grpic_ctx* c, const grpic_particles* P, int64_
     return fail(GRPIC_ECAPACITY, "particle set has %lld slots, request needs %lld", (long long)P->n,
                 (long long)(2 * n_pairs + n_geo));
   if (2 * n_pairs + n_geo > 0xFFFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^32 particles");
-  if (n_geo > 0 && !(std::log(6.0) > g.xi_min && std::log(15.0) < g.xi_min + g.n_r * g.dxi && g.M > 0.0))
+  if (n_geo > 0 && !(6.0 > c->prm.r_min && 15.0 < c->prm.r_max && g.M > 0.0))
     return fail(GRPIC_EINVAL, "test geodesics need r in [6, 15] inside the grid and M > 0");
   return c->f32 ? particles_init_impl<float>(c, P, n_pairs, ppc, T, n_geo, seed, S(stream))
                 : particles_init_impl<double>(c, P, n_pairs, ppc, T, n_geo, seed, S(stream));
@@ -718,8 +729,12 @@ grpic_status grpic_field_advance(grpic_ctx* c, const grpic_fields* F, int32_t st
   if ((st = check_ctx(c)) || (st = check_fields(c, F))) return st;
   if (stage != GRPIC_FIELDS_PRE_PUSH && stage != GRPIC_FIELDS_POST_DEPOSIT)
     return fail(GRPIC_EINVAL, "unknown field stage %d", stage);
-  return c->f32 ? field_advance_impl<float>(c, F, stage, S(stream))
-                : field_advance_impl<double>(c, F, stage, S(stream));
+  const bool q = c->g.r0 != 0.0 || c->g.h0 != 0.0;
+  if (c->f32)
+    return q ? field_advance_impl<float, true>(c, F, stage, S(stream))
+             : field_advance_impl<float, false>(c, F, stage, S(stream));
+  return q ? field_advance_impl<double, true>(c, F, stage, S(stream))
+           : field_advance_impl<double, false>(c, F, stage, S(stream));
 }
 
 grpic_status grpic_diagnostics(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, double B0,

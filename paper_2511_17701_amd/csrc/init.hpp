@@ -71,16 +71,17 @@ struct Tetrad {
 
 // tetrad factors at (x1, x2), theta clamped (App. A)
 __device__ inline Tetrad tetrad_at(const Grid& g, double x1, double x2) {
-  const double r = exp(g.xi_min + x1 * g.dxi);
+  double r, R, th, T, dT;
+  map_r(g, x1, &r, &R);
+  map_theta(g, x2, &th, &T, &dT);
   double s, c;
-  sincos(clamp_theta(g, x2 * g.dth), &s, &c);
+  sincos(clamp_theta(g, th), &s, &c);
   const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r;
   const double Sig = r2 + a2 * c * c, S2 = Sig + tMr, ra = r2 + a2;
   const double A = ra * ra - a2 * (ra - tMr) * s * s;
-  const double R = g.dxi * r;
   Tetrad e;
   e.s11 = sqrt(A / (Sig * S2)) / R;
-  e.s22 = sqrt(Sig) * g.dth;
+  e.s22 = sqrt(Sig) * T;
   e.s33 = sqrt(A / Sig) * s;
   e.k13 = -g.a * R * S2 / A;
   return e;
@@ -91,6 +92,20 @@ __device__ inline void hat_to_cov(const Tetrad& e, const double uh[3], double& u
   u1 = uh[0] / e.s11 + e.k13 * e.s33 * uh[2];
   u2 = e.s22 * uh[1];
   u3 = e.s33 * uh[2];
+}
+
+// x2 of a polar angle: theta / dth on the uniform-theta grid; bisection of
+// the increasing map of App. A otherwise
+__device__ inline double x2_of_theta(const Grid& g, double th) {
+  if (g.h0 == 0.0) return th / g.dth;
+  double lo = 0.0, hi = (double)g.n_th;
+  for (int it = 0; it < 100; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    double t, td, dtd;
+    map_theta(g, mid, &t, &td, &dtd);
+    if (t < th) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
 }
 
 template <class T>
@@ -151,7 +166,7 @@ __global__ void load_geodesics_kernel(Grid g, ParticleArraysT<T> P, int64_t firs
     draw4(seed, (uint32_t)k, 4u, a, v);
     const double r = 6.0 + 9.0 * u_low(w[0]);
     const double th = kPi / 3.0 + (kPi / 3.0) * u_low(w[1]);
-    const double x1 = (log(r) - g.xi_min) / g.dxi, x2 = th / g.dth;
+    const double x1 = (log(r - g.r0) - g.xi_min) / g.dxi, x2 = x2_of_theta(g, th);
     const double f1 = floor(x1), f2 = floor(x2);
     i1 = (int)f1;
     dx1 = x1 - f1;
@@ -159,7 +174,7 @@ __global__ void load_geodesics_kernel(Grid g, ParticleArraysT<T> P, int64_t firs
     dx2 = x2 - f2;
     const double y1 = (double)i1 + dx1, y2 = (double)i2 + dx2;
     const Tetrad e = tetrad_at(g, y1, y2);
-    const double rr = exp(g.xi_min + y1 * g.dxi);
+    const double rr = g.r0 + exp(g.xi_min + y1 * g.dxi);
     const double uk = sqrt(g.M / (rr - 3.0 * g.M));
     const double uh[3] = {0.05 * (2.0 * u_low(w[3]) - 1.0), 0.05 * (2.0 * u_low(v[0]) - 1.0),
                           (0.9 + 0.2 * u_low(w[2])) * uk};
@@ -213,50 +228,54 @@ struct PotCode {
 };
 
 __device__ inline PotCode wald_code(const Grid& g, double x1, double x2, double B0) {
-  const double r = exp(g.xi_min + x1 * g.dxi);
+  double r, R, th, T, dT;
+  map_r(g, x1, &r, &R);
+  map_theta(g, x2, &th, &T, &dT);
   double s, c;
-  sincos(x2 * g.dth, &s, &c);
+  sincos(th, &s, &c);
   const WaldPot p = wald_pot(g, r, s, c, B0);
-  return PotCode{p.Ar * g.dxi * r, p.A3};
+  return PotCode{p.Ar * R, p.A3};
 }
 
 // analytic D^i (component comp) at (x1, x2): E_i = d_i A_0 and
 // sqrt(h) B^k from the curl of A, D^j = h^ji (E_i - e_ikl beta^k B^l) / alpha
 __device__ inline double wald_D(const Grid& g, double x1, double x2, double B0, int comp) {
-  const double r = exp(g.xi_min + x1 * g.dxi);
+  double r, R, th, T, dT;
+  map_r(g, x1, &r, &R);
+  map_theta(g, x2, &th, &T, &dT);
   double s, c;
-  sincos(x2 * g.dth, &s, &c);
+  sincos(th, &s, &c);
   const WaldPot p = wald_pot(g, r, s, c, B0);
   const double a2 = g.a * g.a, r2 = r * r, tMr = 2.0 * g.M * r;
   const double Sig = r2 + a2 * c * c, S2 = Sig + tMr, ra = r2 + a2;
   const double A = ra * ra - a2 * (ra - tMr) * s * s;
-  const double R = g.dxi * r;
   const double alpha = sqrt(Sig / S2);
   const double beta1 = tMr / (S2 * R);
-  // code derivatives: d/dx1 = R d/dr, d/dx2 = dth d/dth
-  const double E1 = R * p.A0_r, E2 = g.dth * p.A0_t;
-  const double shB2 = -R * p.A3_r;              // sqrt(h) B^2
-  const double shB3 = -g.dth * R * p.Ar_t;      // sqrt(h) B^3
+  // code derivatives: d/dx1 = R d/dr, d/dx2 = T d/dtheta
+  const double E1 = R * p.A0_r, E2 = T * p.A0_t;
+  const double shB2 = -R * p.A3_r;          // sqrt(h) B^2
+  const double shB3 = -T * R * p.Ar_t;      // sqrt(h) B^3
   const double X1 = E1;
   const double X2 = E2 + beta1 * shB3;
   const double X3 = -beta1 * shB2;
   if (comp == 0) return (A / (Sig * S2) / (R * R) * X1 + g.a / (Sig * R) * X3) / alpha;
-  if (comp == 1) return g.inv_dth2 / Sig * X2 / alpha;
+  if (comp == 1) return 1.0 / (T * T) / Sig * X2 / alpha;
   return (g.a / (Sig * R) * X1 + X3 / (Sig * s * s)) / alpha;
 }
 
 __device__ inline double wald_B(const Grid& g, double x1, double x2, double B0, int comp) {
-  const double r = exp(g.xi_min + x1 * g.dxi);
+  double r, R, th, T, dT;
+  map_r(g, x1, &r, &R);
+  map_theta(g, x2, &th, &T, &dT);
   double s, c;
-  sincos(x2 * g.dth, &s, &c);
+  sincos(th, &s, &c);
   const WaldPot p = wald_pot(g, r, s, c, B0);
   const double a2 = g.a * g.a, r2 = r * r;
   const double Sig = r2 + a2 * c * c, S2 = Sig + 2.0 * g.M * r;
-  const double R = g.dxi * r;
-  const double sqrt_h = R * g.dth * Sig * s / sqrt(Sig / S2);
-  if (comp == 0) return g.dth * p.A3_t / sqrt_h;
+  const double sqrt_h = R * T * Sig * s / sqrt(Sig / S2);
+  if (comp == 0) return T * p.A3_t / sqrt_h;
   if (comp == 1) return -R * p.A3_r / sqrt_h;
-  return -g.dth * R * p.Ar_t / sqrt_h;
+  return -T * R * p.Ar_t / sqrt_h;
 }
 
 // Whole planes incl. ghosts: D pointwise, B by the discrete Stokes curl of
@@ -296,7 +315,7 @@ __global__ void wald_kernel(Grid g, Tables t, TriT<T> D, TriT<T> B, double B0) {
 // (i, j+1/2) is the difference of A_3 between the nodes j and j+1 over sqrt(h)
 // (eq. EB-set) and every other component is zero (the caller zeroes the
 // planes).  The last column (no node j+1) takes the analytic
-// B^1 = dth B0 sin(theta) / sqrt(h); the axis pass overwrites it.
+// B^1 = T B0 sin(theta) / sqrt(h), T = dtheta/dx2; the axis pass overwrites it.
 template <class T>
 __global__ void monopole_kernel(Grid g, Tables t, T* __restrict__ B1, double B0) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x - g.ng;
@@ -308,7 +327,7 @@ __global__ void monopole_kernel(Grid g, Tables t, T* __restrict__ B1, double B0)
     const double a3 = -B0 * t.c[0][j + g.ng], b3 = -B0 * t.c[0][j + 1 + g.ng];
     v = (b3 - a3) / sqrt_h;
   } else {
-    v = g.dth * B0 * t.s[1][j + g.ng] / sqrt_h;
+    v = t.td[1][j + g.ng] * B0 * t.s[1][j + g.ng] / sqrt_h;
   }
   B1[ix(g, i, j)] = (T)v;
 }

@@ -251,9 +251,14 @@ constexpr double kPiLo = 1.2246467991473531772e-16;
 template <int SER>
 __device__ inline RSC rsc_near(const Grid& g, const Tables& t, int i1, double x1, int i2, double x2) {
   if (SER == 0) return rsc_direct(g, x1, x2);
+  // the series serve the logarithmic-r, uniform-theta grid (r0 = h0 = 0)
   RSC p;
   const double tr = (x1 - (double)i1) * g.dxi;
   p.r = t.r[0][i1 + g.ng] * (SER == 2 ? exp_short(tr) : exp_small(tr));
+  p.rd = g.dxi * p.r;
+  p.td = g.dth;
+  p.itd2 = g.inv_dth2;
+  p.dtd = 0.0;
   const double th = x2 * g.dth;
   const double band = SER == 2 ? 4.0 * g.dth : 0.11;
   if (th <= g.small_angle) {
@@ -301,19 +306,42 @@ __device__ inline void sincos_small_f(float x, float* s, float* c) {
   *c = fmaf(z, pc, 1.0f);
 }
 
-// Single precision: r, sin, cos at offsets (f1, f2) from the corner of cell
-// (i1, i2), |f| <= 1.5.  The polar angle is measured from the nearer axis,
-// theta = (i2 + f2) dth or pi - theta = (n_th - i2 - f2) dth, so that sin keeps
-// its relative precision next to either axis; clamped at small_angle.
+// Single precision: r, sin, cos and the map factors at offsets (f1, f2) from
+// the corner of cell (i1, i2), |f| <= 1.5.  The polar angle is measured from
+// the nearer axis, theta(x2) or pi - theta(x2) = theta(n_th - x2) (the map is
+// symmetric about the equator), so that sin keeps its relative precision next
+// to either axis; clamped at small_angle.  SER > 0: the logarithmic-r,
+// uniform-theta grid with series; SER = 0: the general map of App. A with the
+// library functions.
 template <int SER>
 __device__ inline RSCT<float> rsc_near_f(const Grid& g, const Tables& t, int i1, float f1, int i2,
                                         float f2) {
   RSCT<float> p;
   const float dth = (float)g.dth, eps = (float)g.small_angle;
-  p.r = SER > 0 ? t.rf[i1 + g.ng] * exp_small_f(f1 * (float)g.dxi)
-             : t.rf[i1 + g.ng] * expf(f1 * (float)g.dxi);
+  const float e = SER > 0 ? t.rf[i1 + g.ng] * exp_small_f(f1 * (float)g.dxi)
+                          : t.rf[i1 + g.ng] * expf(f1 * (float)g.dxi);
+  p.r = SER > 0 ? e : (float)g.r0 + e;
+  p.rd = (float)g.dxi * e;
   const bool upper = 2 * i2 >= g.n_th;
-  const float ang = upper ? ((float)(g.n_th - i2) - f2) * dth : ((float)i2 + f2) * dth;
+  const float eta = upper ? ((float)(g.n_th - i2) - f2) * dth : ((float)i2 + f2) * dth;
+  float ang = eta;
+  if (SER > 0) {
+    p.td = dth;
+    p.itd2 = (float)g.inv_dth2;
+    p.dtd = 0.0f;
+  } else {
+    // past the axis (a midpoint of the coordinate iteration) the map is
+    // continued by reflection, as in map_theta: theta odd, T even, dT odd
+    const bool past = eta < 0.0f;
+    const float ea = past ? -eta : eta;
+    const float h0 = (float)g.h0, pi = (float)kPi, y = ea * (float)(1.0 / kPi);
+    const float th = ea + 2.0f * h0 * ea * (pi - 2.0f * ea) * (pi - ea) * (float)(1.0 / (kPi * kPi));
+    ang = past ? -th : th;
+    p.td = dth * (1.0f + 2.0f * h0 + 12.0f * h0 * y * (y - 1.0f));
+    p.itd2 = rcp(p.td * p.td);
+    const float dd = dth * dth * 12.0f * h0 * (2.0f * y - 1.0f) * (float)(1.0 / kPi);
+    p.dtd = (upper != past) ? -dd : dd;
+  }
   float s, c;
   if (ang <= eps) {
     s = (float)g.sin_lo;

@@ -45,7 +45,8 @@ class Params(ctypes.Structure):
                 ("charge_scale", c_double), ("iter_tol", c_double), ("n_r", c_int32),
                 ("n_th", c_int32),
                 ("n_ghost", c_int32), ("n_iter", c_int32), ("n_filter", c_int32),
-                ("n_absorb", c_int32), ("precision", c_int32), ("reserved", c_int32)]
+                ("n_absorb", c_int32), ("precision", c_int32), ("reserved", c_int32),
+                ("r0", c_double), ("h0", c_double)]
 
 
 class Fields(ctypes.Structure):
@@ -117,12 +118,12 @@ class Context:
 
     def __init__(self, a, M, r_min, r_max, n_r, n_th, dt=0.0, cfl=0.5, n_iter=10,
                  small_angle=1e-5, charge_scale=0.0, n_filter=0, n_absorb=0,
-                 precision=GRPIC_FP64, n_ghost=2, iter_tol=0.0):
+                 precision=GRPIC_FP64, n_ghost=2, iter_tol=0.0, r0=0.0, h0=0.0):
         p = Params(a=a, M=M, r_min=r_min, r_max=r_max, dt=dt, cfl=cfl, small_angle=small_angle,
                    charge_scale=charge_scale, iter_tol=iter_tol, n_r=n_r, n_th=n_th,
                    n_ghost=n_ghost,
                    n_iter=n_iter, n_filter=n_filter, n_absorb=n_absorb, precision=precision,
-                   reserved=0)
+                   reserved=0, r0=r0, h0=h0)
         h = c_void_p()
         _check(_lib.grpic_create(ctypes.byref(p), ctypes.byref(h)), "grpic_create")
         self._h = h

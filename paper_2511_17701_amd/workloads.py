@@ -21,12 +21,15 @@ c3_2048   0.99   2048^2  100        32 ppc, T = 1, B0 = 10                100   
 c4_256    0.9    256^2   20         1e6, T = 1, frozen Wald, B0 learnable 50     adjoint (*)
 c5_4096   0.95   4096^2  200        16 ppc (pairs), T = 1, B0 = 10        200    FP32 full step
 c6_mono   0.2    2048^2  10         90 ppc (pairs), T = 0.5, B0 = 1       100    FP64 full step
+c7_qks    0.2    2048^2  10         as c6, quasi-spherical r0 = 0.5, h0=0.3 100   FP64 full step
 ========  =====  ======  =========  ====================================  =====  =========
 
 c6_monopole is the paper's own benchmark shape: the BZ monopole test
 (A_phi = -B0 cos theta, D = 0) on a 2048^2 log-r x theta mesh with 90 particles
 per cell, r from r_g to 10 r_g with an absorbing layer 1 r_g thick (94 cells),
-pairs at the test's injection temperature T = 0.5.
+pairs at the test's injection temperature T = 0.5.  c7_qks_monopole is the same
+shape on the general quasi-spherical map of App. A (xi = log(r - 0.5), points
+concentrated toward the equator with h0 = 0.3).
 
 (*) the differentiation form runs the implicit iterations to their fixed
 points (up to 200 iterations, stopping at an exact repeat), as its
@@ -67,6 +70,8 @@ class Workload:
     full_step: bool = False    # field_advance inside the step
     init: str = "wald"         # initial field: "wald" | "monopole"
     r_inner: float = 0.0       # inner radius (0: 0.9 r_h)
+    r0: float = 0.0            # quasi-spherical map (App. A): xi = log(r - r0)
+    h0: float = 0.0            # and equatorial concentration of theta(eta)
 
     @property
     def r_h(self) -> float:
@@ -111,6 +116,10 @@ WORKLOADS = {
     "c6_monopole": Workload("c6_monopole", a=0.2, n_r=2048, n_th=2048, r_max=10.0, B0=1.0, T=0.5,
                             n_pairs=0, ppc=90, n_geo=0, steps=100, precision="fp64",
                             n_absorb=94, full_step=True, init="monopole", r_inner=1.0),
+    "c7_qks_monopole": Workload("c7_qks_monopole", a=0.2, n_r=2048, n_th=2048, r_max=10.0,
+                                B0=1.0, T=0.5, n_pairs=0, ppc=90, n_geo=0, steps=100,
+                                precision="fp64", n_absorb=94, full_step=True, init="monopole",
+                                r_inner=1.0, r0=0.5, h0=0.3),
 }
 
 

@@ -36,16 +36,19 @@ def wl(name, n=None, **kw):
     return w.scaled(n, n, **kw) if n else w
 
 
-def pair(O, G, w, charge_scale=0.0, n_filter=None, n_absorb=None):
-    """Oracle params and a HIP context with identical dt."""
+def pair(O, G, w, charge_scale=0.0, n_filter=None, n_absorb=None, r0=0.0, h0=0.0,
+         precision=None):
+    """Oracle params and a HIP context with identical dt (r0, h0: the
+    quasi-spherical map of App. A)."""
     nf = w.n_filter if n_filter is None else n_filter
     na = w.n_absorb if n_absorb is None else n_absorb
+    extra = {} if precision is None else {"precision": precision}
     ctx = G.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, cfl=w.cfl, n_iter=w.n_iter,
                     small_angle=w.small_angle, charge_scale=charge_scale, n_filter=nf,
-                    n_absorb=na)
+                    n_absorb=na, r0=r0, h0=h0, **extra)
     prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, ctx.dt, n_iter=w.n_iter,
                         small_angle=w.small_angle, charge_scale=charge_scale, n_filter=nf,
-                        n_absorb=na)
+                        n_absorb=na, r0=r0, h0=h0)
     assert ctx.dt == pytest.approx(O.courant_dt(prm, w.cfl), rel=1e-14)
     return prm, ctx
 
