@@ -55,8 +55,8 @@ __device__ inline RSCT<Tan<N>> rsc_tan(const Grid& g, const Tan<N>& x1, const Ta
   }
   const TN eta = xr * TN(g.dth), y = eta * TN(1.0 / kPi);
   const double h0 = g.h0;
-  TN th = TN(off) + TN(sg) * (eta + TN(2.0 * h0 / (kPi * kPi)) * eta * (TN(kPi) - TN(2.0) * eta) *
-                                        (TN(kPi) - eta));
+  TN th = TN(off) + TN(sg) * (eta + TN(2.0 * h0) * eta * (TN(kPi) - TN(2.0) * eta) *
+                                        (TN(kPi) - eta) / TN(kPi * kPi));
   p.td = TN(g.dth) * (TN(1.0 + 2.0 * h0) + TN(12.0 * h0) * y * (y - TN(1.0)));
   p.itd2 = rcp(p.td * p.td);
   p.dtd = TN(sg * g.dth * g.dth * 12.0 * h0 / kPi) * (TN(2.0) * y - TN(1.0));

@@ -510,6 +510,7 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   {
     const double off = 1.5 * std::fmax(g.dxi, g.dth);
     g.ser = (off <= 0.03 && 4.0 * g.dth <= 0.03) ? 2 : (off <= 0.11 ? 1 : 0);
+    g.axis_band = 4.0 * g.dth;
     if (g.r0 != 0.0 || g.h0 != 0.0) g.ser = 0;
   }
   // single-precision push: cells whose inner edge lies below r = 3 M keep the

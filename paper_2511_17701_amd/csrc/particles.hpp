@@ -238,7 +238,8 @@ __device__ inline void sincos_short(double x, double* s, double* c) {
 // pi - (pi rounded to double)
 constexpr double kPiLo = 1.2246467991473531772e-16;
 
-// r, sin, cos at code position (x1, x2) near cell (i1, i2) (|x - i| <= 1.5):
+// r, sin, cos and the map factors at code position (x1, x2) near cell
+// (i1, i2) (|x - i| <= 1.5) on the logarithmic-r, uniform-theta grid:
 // r = r_i exp((x1 - i1) dxi); the polar angle is first rounded and clamped as
 // theta = clamp(x2 dth), and the result is the sine and cosine of that double:
 // by a series on theta itself next to theta = 0, on psi = pi - theta (exact
@@ -247,11 +248,11 @@ constexpr double kPiLo = 1.2246467991473531772e-16;
 // would cancel), and by angle addition from the tables elsewhere.
 // SER = 2: offsets |x - i| dxi, dth <= 0.03 and an axis band of 4 cells (its
 // angles <= 0.03): short series throughout.  SER = 1: offsets <= 0.11 and an
-// axis band of 0.11 rad: long series.  SER = 0: library functions.
+// axis band of 0.11 rad: long series.  SER = 0: library functions (also every
+// general quasi-spherical map).
 template <int SER>
 __device__ inline RSC rsc_near(const Grid& g, const Tables& t, int i1, double x1, int i2, double x2) {
   if (SER == 0) return rsc_direct(g, x1, x2);
-  // the series serve the logarithmic-r, uniform-theta grid (r0 = h0 = 0)
   RSC p;
   const double tr = (x1 - (double)i1) * g.dxi;
   p.r = t.r[0][i1 + g.ng] * (SER == 2 ? exp_short(tr) : exp_small(tr));
@@ -260,7 +261,7 @@ __device__ inline RSC rsc_near(const Grid& g, const Tables& t, int i1, double x1
   p.itd2 = g.inv_dth2;
   p.dtd = 0.0;
   const double th = x2 * g.dth;
-  const double band = SER == 2 ? 4.0 * g.dth : 0.11;
+  const double band = SER == 2 ? g.axis_band : 0.11;
   if (th <= g.small_angle) {
     p.s = g.sin_lo;
     p.c = g.cos_lo;

@@ -63,11 +63,18 @@ def down(P):
 
 
 def u_scale(prm, P):
-    dxi = math.log(prm.r_max / prm.r_min) / prm.n_r
-    dth = math.pi / prm.n_th
-    r = prm.r_min * np.exp((P["i1"] + P["dx1"]) * dxi)
-    th = (P["i2"] + P["dx2"]) * dth
-    c = [dxi * r, r * dth, r * np.maximum(np.abs(np.sin(th)), 1e-5)]
+    """Code-unit scales of u_1, u_2, u_3: R = dr/dx1, r T (T = dtheta/dx2) and
+    r sin(theta), from the quasi-spherical map of App. A (a tolerance scale)."""
+    r0, h0 = prm.r0, prm.h0
+    dxi = math.log((prm.r_max - r0) / (prm.r_min - r0)) / prm.n_r
+    deta = math.pi / prm.n_th
+    e = (prm.r_min - r0) * np.exp((P["i1"] + P["dx1"]) * dxi)
+    r = r0 + e
+    eta = np.clip((P["i2"] + P["dx2"]) * deta, 0.0, math.pi)
+    y = eta / math.pi
+    th = eta + 2 * h0 * eta * (math.pi - 2 * eta) * (math.pi - eta) / math.pi ** 2
+    T = deta * (1 + 2 * h0 + 12 * h0 * y * (y - 1))
+    c = [dxi * e, r * T, r * np.maximum(np.abs(np.sin(th)), 1e-5)]
     gam = np.sqrt(1 + sum((P[k] / ci) ** 2 for k, ci in zip(("u1", "u2", "u3"), c)))
     return [gam * ci for ci in c]
 

@@ -208,3 +208,48 @@ def test_qks_adjoint_matches_reference_gradient(O, G):
           f"p99 {np.quantile(err, 0.99):.3g}; dL/dB0 {B0.grad.item():.12g} vs {gB0_o:.12g}")
     assert np.quantile(err, 0.99) <= 1e-9
     assert abs(B0.grad.item() - gB0_o) <= 1e-9 * abs(gB0_o)
+
+
+@pytest.mark.parametrize("n", [96, 768])
+def test_qks_push_fine_grids(O, G, n):
+    """The push and the fused pass on the general map at finer grids (96^2
+    and 768^2: in-cell angle steps up to 0.05 and 0.007 rad); three push
+    steps and a fused step from the oracle's state, with particles next to
+    both axes."""
+    w = wl("c1_64", n)
+    prm, ctx = pair(O, G, w, charge_scale=0.3, **QKS)
+    F = O.fields_init_wald(prm, w.B0)
+    P = O.particles_init(prm, 15000, 0, w.T, 0, w.seed)
+    P["i2"][:60] = np.arange(60) % 3
+    P["dx2"][:60] = np.linspace(1e-6, 0.99, 60)
+    P["i2"][60:120] = n - 1 - np.arange(60) % 3
+    P["dx2"][60:120] = np.linspace(0.01, 1 - 1e-6, 60)
+    P["tag"][120::13] = 7
+    for k in ("i2", "dx2"):
+        P[k + "p"][:] = P[k]
+    Fg = up({"F": F})["F"]
+    for step in range(3):
+        Pg = up(P)
+        O.push(prm, F, P)
+        ctx.push(Fg, Pg)
+        assert_particles(prm, P, down(Pg), what=f"qks fine push n={n} step {step}")
+    Fg, Pg = up({"F": F})["F"], up(P)
+    O.push(prm, F, P)
+    O.deposit(prm, F, P)
+    ctx.push_deposit(Fg, Pg)
+    assert_particles(prm, P, down(Pg), what=f"qks fine fused n={n}", prev=False)
+    Jg = Fg.cpu().numpy()
+    if n > 96:
+        # at 768^2 the particles placed in the first cells sit a few 1e-4 rad
+        # from an axis, where J^3 ~ 1/sin^2(theta) at the path midpoint turns
+        # the last bit of the midpoint into ~1e-12 of the plane's maximum:
+        # compare the nodes more than 3 cells from either axis to the plane
+        # bar, the rest to 1e-11
+        g = prm.ng
+        inner = (slice(None), slice(g + 3, g + n - 2))
+        for c in range(18, 21):
+            sc = np.abs(F[c]).max()
+            assert np.abs(F[c][inner] - Jg[c][inner]).max() <= 1e-12 * sc, c
+            assert np.abs(F[c] - Jg[c]).max() <= 1e-11 * sc, c
+    else:
+        assert_fields(F, Jg, range(18, 21), what=f"qks fine J n={n}")
