@@ -40,6 +40,9 @@ struct Grid {
   int n_iter, n_filter, n_absorb;
   int ser;                // series used by the push for in-cell offsets (0 = library)
   double axis_band;       // short series: polar band next to each axis (4 cells)
+  // uniform values the push would otherwise form per wavefront in vector
+  // registers: a^2, 2 M, pi - small_angle, pi - axis_band
+  double a2, two_M, th_hi, band_hi;
   int i_fp64;             // single-precision push: cells i1 < i_fp64 (r < 3 M, the
                           // horizon region) take the metric and its derivatives in FP64
   int64_t plane;          // reals per plane
@@ -207,7 +210,10 @@ __host__ __device__ inline RSC rsc_direct(const Grid& g, double x1, double x2) {
 template <class R>
 __host__ __device__ inline CoeffsT<R> coeffs_from(const Grid& g, RSCT<R> p) {
   const R r = p.r, s = p.s, c = p.c;
-  const R a = (R)g.a, a2 = a * a, r2 = r * r, tMr = (R)(2.0 * g.M) * r;
+  // (FP64: a^2 and 2 M from the grid, held in scalar registers; the
+  // single-precision form keeps forming them, which suits its allocation)
+  const R a = (R)g.a, a2 = sizeof(R) == 8 ? (R)g.a2 : a * a, r2 = r * r;
+  const R tMr = (sizeof(R) == 8 ? (R)g.two_M : (R)(2.0 * g.M)) * r;
   const R Sig = r2 + a2 * c * c;
   const R S2 = Sig + tMr;
   const R ra = r2 + a2;
@@ -238,7 +244,8 @@ template <class R>
 __host__ __device__ inline void frame_from(const Grid& g, RSCT<R> p, FrameT<R>* f, GradT<R>* d) {
   const R r = p.r, s = p.s, c = p.c;
   const R a = (R)g.a, M = (R)g.M, dxi = (R)g.dxi, dth = p.td;
-  const R a2 = a * a, r2 = r * r, tMr = (R)2 * M * r;
+  const R a2 = sizeof(R) == 8 ? (R)g.a2 : a * a, r2 = r * r;
+  const R tMr = sizeof(R) == 8 ? (R)g.two_M * r : (R)2 * M * r;
   const R Sig = r2 + a2 * c * c;
   const R S2 = Sig + tMr;
   const R ra = r2 + a2;

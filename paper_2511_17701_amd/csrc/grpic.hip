@@ -456,6 +456,9 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   Grid& g = c->g;
   g.a = p->a;
   g.M = p->M;
+  g.a2 = g.a * g.a;
+  g.two_M = 2.0 * g.M;
+  g.th_hi = kPi - p->small_angle;
   g.r0 = p->r0;
   g.h0 = p->h0;
   g.xi_min = std::log(p->r_min - p->r0);
@@ -511,6 +514,7 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
     const double off = 1.5 * std::fmax(g.dxi, g.dth);
     g.ser = (off <= 0.03 && 4.0 * g.dth <= 0.03) ? 2 : (off <= 0.11 ? 1 : 0);
     g.axis_band = 4.0 * g.dth;
+    g.band_hi = kPi - g.axis_band;
     if (g.r0 != 0.0 || g.h0 != 0.0) g.ser = 0;
   }
   // single-precision push: cells whose inner edge lies below r = 3 M keep the

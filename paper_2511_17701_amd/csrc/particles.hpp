@@ -265,12 +265,12 @@ __device__ inline RSC rsc_near(const Grid& g, const Tables& t, int i1, double x1
   if (th <= g.small_angle) {
     p.s = g.sin_lo;
     p.c = g.cos_lo;
-  } else if (th >= kPi - g.small_angle) {
+  } else if (th >= g.th_hi) {
     p.s = g.sin_hi;
     p.c = g.cos_hi;
   } else if (th <= band) {
     if (SER == 2) sincos_short(th, &p.s, &p.c); else sincos_small(th, &p.s, &p.c);
-  } else if (th >= kPi - band) {
+  } else if (th >= (SER == 2 ? g.band_hi : kPi - 0.11)) {
     double cq;
     if (SER == 2) sincos_short((kPi - th) + kPiLo, &p.s, &cq);
     else sincos_small((kPi - th) + kPiLo, &p.s, &cq);
