@@ -1017,10 +1017,11 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
 }
 
 // ------------------------------------------------------------------ kernels
-// The FP64 push kernels are held to 128 VGPRs (4 wavefronts per SIMD; a few
-// spilled registers): on gfx950 the push is latency- and issue-bound, and the
-// fourth wavefront hides more than the spills cost (the compiler's own choice,
-// ~160 VGPRs, gives 3 wavefronts and a 10-15 % slower pass).
+// The FP64 push kernels are held to 128 VGPRs (4 wavefronts per SIMD; no
+// spills on the series paths): on gfx950 the push is latency- and issue-bound,
+// and the fourth wavefront hides more than the compiler's own choice (~160
+// VGPRs, 3 wavefronts, a 10-15 % slower pass); a fifth (96 VGPRs) spills
+// 148 B per lane and runs about 30 % slower.
 #define GRPIC_FP64_PUSH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4)))
 
 template <int SER>
