@@ -285,7 +285,7 @@ grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_
     switch (c->g.ser) {
       case 2: hipLaunchKernelGGL((push_deposit_kernel_f32<2>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
       case 1: hipLaunchKernelGGL((push_deposit_kernel_f32<1>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
-      default: hipLaunchKernelGGL((push_deposit_kernel_f32<0>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
+      default: hipLaunchKernelGGL(push_deposit_kernel_f32_lib, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
     }
   } else {
     GatherPlanesT<double> gp;

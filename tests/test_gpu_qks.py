@@ -63,11 +63,13 @@ def test_qks_initial_data(O, G):
     assert_fields(Fo, Fg.cpu().numpy(), range(0, 33), what="qks monopole")
 
 
-def test_qks_push_per_step(O, G):
+@pytest.mark.parametrize("h0", [0.3, -0.3])
+def test_qks_push_per_step(O, G, h0):
     """Five push steps (frozen Wald field), each from the oracle's state, with
-    particles next to both axes and photons among them."""
+    particles next to both axes and photons among them (points concentrated
+    toward the equator, h0 = 0.3, and toward the axes, h0 = -0.3)."""
     w = wl("c1_64", 48)
-    prm, ctx = pair(O, G, w, **QKS)
+    prm, ctx = pair(O, G, w, r0=QKS["r0"], h0=h0)
     F = O.fields_init_wald(prm, w.B0)
     P = O.particles_init(prm, 8000, 0, w.T, 0, w.seed)
     P["i2"][:40] = 0

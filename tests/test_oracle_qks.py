@@ -25,21 +25,22 @@ def qparams(O, a=0.9, M=1.0, r_min=None, r_max=20.0, n=48, dt=0.0, **kw):
 
 # ------------------------------------------------------------------ the map
 
-def test_map_endpoints_symmetry_and_derivatives(O):
+@pytest.mark.parametrize("h0", [0.3, -0.3])
+def test_map_endpoints_symmetry_and_derivatives(O, h0):
     """r(0) = r_min, r(n_r) = r_max, theta(0) = 0, theta(n_th) = pi, theta
     symmetric about the equator (theta(n - x2) = pi - theta(x2)), dtheta/dx2 at
     the equator reduced by 1 - h0 (points concentrated there for h0 > 0);
     R = dr/dx1, T = dtheta/dx2 and dT/dx2 agree with central differences of
     r, theta and T, and dR/dx1 = dxi R (dxi the log spacing of r - r0)."""
     n = 40
-    prm = qparams(O, n=n)
+    prm = qparams(O, n=n, h0=h0)
     m0, mn = O.metric_at(prm, 0.0, 0.0, clamp=False), O.metric_at(prm, n, n, clamp=False)
     assert m0["r"] == pytest.approx(prm.r_min, rel=1e-15)
     assert mn["r"] == pytest.approx(prm.r_max, rel=1e-14)
     assert m0["th"] == 0.0 and mn["th"] == pytest.approx(math.pi, rel=1e-15)
     deta = math.pi / n
-    assert O.metric_at(prm, 1.0, n / 2, clamp=False)["T"] == pytest.approx(deta * (1 - QKS["h0"]),
-                                                                           rel=1e-14)
+    assert O.metric_at(prm, 1.0, n / 2, clamp=False)["T"] == pytest.approx(deta * (1 - h0), rel=1e-14)
+    assert O.metric_at(prm, 1.0, 0.0, clamp=False)["T"] == pytest.approx(deta * (1 + 2 * h0), rel=1e-14)
     dxi = math.log((prm.r_max - QKS["r0"]) / (prm.r_min - QKS["r0"])) / n
     g = np.random.default_rng(3)
     h = 1e-5
@@ -86,13 +87,14 @@ def test_metric_is_spherical_ks_under_the_map(O):
             assert kq == pytest.approx(ks, rel=1e-12)
 
 
-def test_derivatives_vs_central_differences(O):
+@pytest.mark.parametrize("h0", [0.45, -0.4])
+def test_derivatives_vs_central_differences(O, h0):
     """The twelve code-coordinate derivatives the pusher uses agree with
     Richardson-extrapolated central differences of the metric on the general
     map, including the derivative of the map factor of h^22 that the printed
     App. A forms omit (reading R23)."""
     n = 48
-    prm = qparams(O, n=n, h0=0.45)
+    prm = qparams(O, n=n, h0=h0)
     keys = ("alpha", "beta1", "hu11", "hu22", "hu33", "hu13")
     g = np.random.default_rng(5)
     for _ in range(25):
