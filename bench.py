@@ -264,7 +264,7 @@ def main():
     global ARGS
     ARGS = parse()
     if ARGS.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; run with --gpus 1"}))
         sys.exit(2)
     if ARGS.copy_calibration:
         copy_calibration()

@@ -24,8 +24,8 @@
  *   - the Wald vacuum potential (Sec. 4.1.2, eq. Wald), particle loading, and
  *     the conserved energy / angular momentum of Sec. 2.3.
  *
- * Choices the paper leaves open are the readings listed in the design doc (R-numbers
- * in comments below name them).  Every function is pinned by the tests in
+ * Choices the paper leaves open are numbered readings (R1, R2, ...), named in
+ * the comments where they apply and stated there.  Every function is pinned by the tests in
  * tests/test_oracle_*.py (closed forms, Table 1, conservation laws, symmetry)
  * except the outer absorbing layer (R16, match_lambda and its use in
  * field_bc): parity unpinned -- the paper gives its form only by reference.
