@@ -42,3 +42,7 @@ def test_argument_errors_reported_without_gpu():
         grpic.Context(1.2, 1.0, 1.3, 20.0, 32, 32)
     with pytest.raises(grpic.GrpicError, match="too small"):
         grpic.Context(0.9, 1.0, 1.3, 20.0, 4, 32)
+    with pytest.raises(grpic.GrpicError, match="r0"):
+        grpic.Context(0.9, 1.0, 1.3, 20.0, 32, 32, r0=1.3)
+    with pytest.raises(grpic.GrpicError, match="h0"):
+        grpic.Context(0.9, 1.0, 1.3, 20.0, 32, 32, h0=-0.5)
