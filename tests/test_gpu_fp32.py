@@ -305,3 +305,28 @@ def test_fp32_sort(G):
     rows_b = np.sort(np.stack([b["u1"][:n_live], b["u2"][:n_live], b["u3"][:n_live]]).view(np.uint32), axis=1)
     np.testing.assert_array_equal(rows_a, rows_b)
     torch.cuda.synchronize()
+
+
+def test_fp32_push_with_photons(G):
+    """Massless particles (tag 7) in the single-precision push: one step of a
+    loaded plasma with every fifth slot retagged, against the FP64 push of the
+    same rounded state (the photons' momenta spread over e^+-3)."""
+    import torch
+    w = wl("c3_2048", 256)
+    c32, c64 = contexts(G, w)
+    P32, F32, _, F64 = loaded(G, w, c32, c64)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    sel = torch.zeros(P32["tag"].numel(), dtype=torch.bool)
+    sel[::5] = True
+    P32["tag"][sel.to(P32["tag"].device)] = 7
+    scale = torch.exp(torch.empty(int(sel.sum())).uniform_(-3.0, 3.0, generator=g)).to(torch.float32)
+    for k in ("u1", "u2", "u3"):
+        P32[k][sel.to(P32[k].device)] *= scale.to(P32[k].device)
+    P64 = widen(P32)
+    c32.push(F32, P32)
+    c64.push(F64, P64)
+    st, _ = compare(w, P32, P64, "one push with photons")
+    assert st["tag_mismatch"] == 0
+    assert st["x_max"] <= 2e-6 * w.n_r / 256 + 1e-6
+    assert st["u_med"] <= 1e-6
+    assert st["u_max"] <= 1e-4
