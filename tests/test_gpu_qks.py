@@ -255,3 +255,51 @@ def test_qks_push_fine_grids(O, G, n):
             assert np.abs(F[c] - Jg[c]).max() <= 1e-11 * sc, c
     else:
         assert_fields(F, Jg, range(18, 21), what=f"qks fine J n={n}")
+
+
+def test_qks_fp32_full_steps(G):
+    """The single-precision form on the general map over 100 full PIC steps
+    of the C3 recipe (a = 0.99, B0 = 10, 32 ppc) at 256^2, against the FP64
+    form from the same rounded state: the bars of the standard grid's test."""
+    import torch
+    from test_gpu_fp32 import compare
+    w = wl("c3_2048", 256)
+    kw = dict(cfl=w.cfl, n_iter=w.n_iter, small_angle=w.small_angle, charge_scale=w.charge_scale,
+              n_filter=w.n_filter, n_absorb=w.n_absorb, **QKS)
+    c32 = G.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, precision=G.GRPIC_FP32, **kw)
+    c64 = G.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, dt=c32.dt, **kw)
+    P32 = c32.new_particles(w.n_particles)
+    c32.particles_init(P32, 0, w.ppc, w.T, 0, w.seed)
+    F32 = c32.new_fields()
+    c32.fields_init_wald(F32, w.B0)
+    P64 = {k: (v.to(torch.float64) if v.dtype == torch.float32 else v.clone())
+           for k, v in P32.items()}
+    F64 = F32[:33].double()
+    for _ in range(w.steps):
+        c32.step(F32, P32, fused=True)
+        c64.step(F64, P64, fused=True)
+    torch.cuda.synchronize()
+    st, live = compare(w, P32, P64, f"qks {w.steps} full steps")
+    d32 = c32.diagnostics(F32, P32, w.B0, per_particle=True)
+    d64 = c64.diagnostics(F64, P64, w.B0, per_particle=True)
+    E32 = d32["E"].double().cpu().numpy()[live]
+    E64 = d64["E"].cpu().numpy()[live]
+    e_err = np.abs(E32 - E64) / np.maximum(np.abs(E64), 1.0)
+    g = 2
+    inner = (slice(None), slice(g + 2, g + w.n_th - 1))
+    err_in, err_all = [], []
+    for c in range(6):
+        a = F32[c].double().cpu().numpy()
+        b = F64[c].cpu().numpy()
+        s = np.abs(b).max()
+        err_all.append(np.abs(a - b).max() / s)
+        err_in.append(np.abs(a - b)[inner].max() / s)
+    print(f"[qks fp32 vs fp64] energy p99 {np.quantile(e_err, 0.99):.3g}; D, B inner "
+          f"{max(err_in):.3g}, all {max(err_all):.3g}")
+    assert d32["n_nonfinite"] == 0 and d64["n_nonfinite"] == 0
+    assert st["tag_mismatch"] <= max(2, 1e-5 * st["n"])
+    assert st["u_p99"] <= 1e-5
+    assert st["u_med"] <= 2e-6
+    assert np.quantile(e_err, 0.99) <= 1e-5
+    assert max(err_in) <= 1e-5
+    assert max(err_all) <= 1e-4
