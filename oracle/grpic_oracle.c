@@ -9,9 +9,10 @@
  * What it computes (Galishnikova, Hakobyan, Philippov, Crinquand, "Entity II:
  * General Relativistic Module"):
  *   - the Kerr-Schild 3+1 metric in quasi-spherical code coordinates (App. A,
- *     "Quasi-spherical Kerr-Schild", with r0 = 0, h0 = 0) with the mass M as a
- *     parameter; M = 0, a = 0 is the flat "kerr_schild_0" metric (App. A,
- *     "Spherical Minkowski");
+ *     "Quasi-spherical Kerr-Schild": xi = log(r - r0), theta(eta) with the
+ *     equatorial concentration h0; r0 = h0 = 0 is log r, uniform theta) with
+ *     the mass M as a parameter; M = 0, a = 0 is the flat "kerr_schild_0"
+ *     metric (App. A, "Spherical Minkowski");
  *   - the orthonormal tetrad (App. A, matrix forms of e^i_hat and e_i^hat);
  *   - the particle update of Sec. 3.1 (steps 1-11): field interpolation,
  *     tetrad-frame Boris half pushes, implicit geodesic momentum iteration
@@ -21,12 +22,15 @@
  *   - the conformal charge-conserving deposit (Sec. 3.2) and J^3 = q alpha u^3/gamma;
  *   - the field solver of Sec. 3.3 (discrete Faraday, Ampere, auxiliary E/H,
  *     volume-weighted averages, polar-axis D^1) and the PIC loop of Sec. 3.4;
- *   - the Wald vacuum potential (Sec. 4.1.2, eq. Wald), particle loading, and
- *     the conserved energy / angular momentum of Sec. 2.3.
+ *   - massive and massless particles (Sec. 2.3: gamma from the normalisation
+ *     with m^2 = 1 or 0; massless ones are neutral);
+ *   - the Wald vacuum potential (Sec. 4.1.2, eq. Wald), the BZ monopole test's
+ *     initial field, particle loading, and the conserved energy / angular
+ *     momentum of Sec. 2.3.
  *
  * Choices the paper leaves open are numbered readings (R1, R2, ...), named in
- * the comments where they apply and stated there.  Every function is pinned by the tests in
- * tests/test_oracle_*.py (closed forms, Table 1, conservation laws, symmetry)
+ * the comments where they apply and stated there.  Every function is pinned
+ * by the tests in tests/test_oracle_*.py (closed forms, Table 1, conservation laws, symmetry)
  * except the outer absorbing layer (R16, match_lambda and its use in
  * field_bc): parity unpinned -- the paper gives its form only by reference.
  *
