@@ -93,37 +93,80 @@ class Metric(ctypes.Structure):
 _lib = None
 
 
+def _load(path):
+    L = ctypes.CDLL(path)
+    P, PP, D = POINTER(Params), POINTER(Particles), POINTER(c_double)
+    L.orc_plane_size.argtypes = [P]; L.orc_plane_size.restype = c_int64
+    L.orc_metric_at.argtypes = [P, c_double, c_double, c_int, POINTER(Metric)]
+    for nm in ("orc_cov_to_hat", "orc_hat_to_cov", "orc_con_to_hat", "orc_hat_to_con"):
+        getattr(L, nm).argtypes = [POINTER(Metric), D, D]
+    L.orc_boris.argtypes = [D, D, D, c_double, c_double]
+    L.orc_push.argtypes = [P, D, PP]
+    L.orc_deposit.argtypes = [P, D, PP]
+    L.orc_charge.argtypes = [P, PP, D]
+    L.orc_wald_potential.argtypes = [P, c_double, c_double, c_double, D]
+    L.orc_wald_fields.argtypes = [P, c_double, c_double, c_double, D, D]
+    L.orc_field_advance.argtypes = [P, D, c_int]
+    L.orc_fields_init_wald.argtypes = [P, D, c_double]
+    L.orc_fields_init_monopole.argtypes = [P, D, c_double]
+    L.orc_philox4x32_10.argtypes = [POINTER(c_uint32), POINTER(c_uint32), POINTER(c_uint32)]
+    L.orc_particles_init.argtypes = [P, PP, c_int64, c_int32, c_double, c_int64, c_uint64]
+    L.orc_energy_momentum.argtypes = [P, PP, c_double, D, D]
+    L.orc_gauss_residual.argtypes = [P, D, PP, D, D, D]
+    L.orc_gauss_residual.restype = c_double
+    L.orc_courant_dt.argtypes = [P, c_double]
+    L.orc_courant_dt.restype = c_double
+    L.orc_num_threads.restype = c_int
+    L.orc_wald_potential_planes.argtypes = [P, c_double, D, D]
+    L.orc_sqrt_h_plane.argtypes = [P, c_int, c_int, D]
+    L.orc_gather.argtypes = [P, D, c_int32, c_double, c_int32, c_double, D, D]
+    L.orc_axis_bc.argtypes = [P, D, c_int]
+    L.orc_field_bc.argtypes = [P, D, D, c_int]
+    L.orc_filter_currents.argtypes = [P, D]
+    L.orc_match_lambda.argtypes = [P, c_double]
+    L.orc_match_lambda.restype = c_double
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(LIB)
-        P, PP, D = POINTER(Params), POINTER(Particles), POINTER(c_double)
-        L.orc_plane_size.argtypes = [P]; L.orc_plane_size.restype = c_int64
-        L.orc_metric_at.argtypes = [P, c_double, c_double, c_int, POINTER(Metric)]
-        for nm in ("orc_cov_to_hat", "orc_hat_to_cov", "orc_con_to_hat", "orc_hat_to_con"):
-            getattr(L, nm).argtypes = [POINTER(Metric), D, D]
-        L.orc_boris.argtypes = [D, D, D, c_double, c_double]
-        L.orc_push.argtypes = [P, D, PP]
-        L.orc_deposit.argtypes = [P, D, PP]
-        L.orc_charge.argtypes = [P, PP, D]
-        L.orc_wald_potential.argtypes = [P, c_double, c_double, c_double, D]
-        L.orc_wald_fields.argtypes = [P, c_double, c_double, c_double, D, D]
-        L.orc_field_advance.argtypes = [P, D, c_int]
-        L.orc_fields_init_wald.argtypes = [P, D, c_double]
-        L.orc_fields_init_monopole.argtypes = [P, D, c_double]
-        L.orc_philox4x32_10.argtypes = [POINTER(c_uint32), POINTER(c_uint32), POINTER(c_uint32)]
-        L.orc_particles_init.argtypes = [P, PP, c_int64, c_int32, c_double, c_int64, c_uint64]
-        L.orc_energy_momentum.argtypes = [P, PP, c_double, D, D]
-        L.orc_gauss_residual.argtypes = [P, D, PP, D, D, D]
-        L.orc_gauss_residual.restype = c_double
-        L.orc_courant_dt.argtypes = [P, c_double]
-        L.orc_courant_dt.restype = c_double
-        L.orc_num_threads.restype = c_int
-        L.orc_wald_potential_planes.argtypes = [P, c_double, D, D]
-        L.orc_sqrt_h_plane.argtypes = [P, c_int, c_int, D]
-        _lib = L
+        _lib = _load(LIB)
     return _lib
+
+
+class planted:
+    """Context manager for planted-mistake checks of the pins: compiles a copy
+    of grpic_oracle.c with each (old, new) text replacement applied (each `old`
+    must occur exactly once) into a temporary library and routes every oracle
+    call through it until the context ends."""
+
+    def __init__(self, *patches):
+        self.patches = patches
+
+    def __enter__(self):
+        import tempfile
+        src = open(SRC).read()
+        for old, new in self.patches:
+            assert src.count(old) == 1, "planted mistake: text to replace not found once: %r" % old
+            src = src.replace(old, new)
+        self._dir = tempfile.TemporaryDirectory()
+        c = os.path.join(self._dir.name, "planted.c")
+        so = os.path.join(self._dir.name, "libplanted.so")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-w", "-o", so, c,
+                        "-lm"], check=True)
+        global _lib
+        self._saved = lib()
+        _lib = _load(so)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+        self._dir.cleanup()
+        return False
 
 
 def _dp(a):
@@ -231,6 +274,33 @@ def charge(prm: Params, P: dict) -> np.ndarray:
 
 def field_advance(prm: Params, F: np.ndarray, stage: int) -> None:
     lib().orc_field_advance(ctypes.byref(prm), _dp(F), int(stage))
+
+
+# parts of the step, called on their own by the pins
+
+def gather(prm: Params, F: np.ndarray, x1: float, x2: float):
+    """(D, B) interpolated at code position (x1, x2) from planes D and B0."""
+    i1, i2 = int(np.floor(x1)), int(np.floor(x2))
+    D, B = np.zeros(3), np.zeros(3)
+    lib().orc_gather(ctypes.byref(prm), _dp(F), i1, x1 - i1, i2, x2 - i2, _dp(D), _dp(B))
+    return D, B
+
+
+def axis_bc(prm: Params, X: np.ndarray, kind: int) -> None:
+    """Axis ghosts of a triple X (3 planes): kind 0 D-like, 1 B-like, 2 current."""
+    lib().orc_axis_bc(ctypes.byref(prm), _dp(X), int(kind))
+
+
+def field_bc(prm: Params, X: np.ndarray, Xinit: np.ndarray, kind: int) -> None:
+    lib().orc_field_bc(ctypes.byref(prm), _dp(X), _dp(Xinit), int(kind))
+
+
+def filter_currents(prm: Params, F: np.ndarray) -> None:
+    lib().orc_filter_currents(ctypes.byref(prm), _dp(F))
+
+
+def match_lambda(prm: Params, x: float) -> float:
+    return lib().orc_match_lambda(ctypes.byref(prm), float(x))
 
 
 def wald_potential(prm: Params, x1: float, x2: float, B0: float):

@@ -30,9 +30,11 @@
  *
  * Choices the paper leaves open are numbered readings (R1, R2, ...), named in
  * the comments where they apply and stated there.  Every function is pinned
- * by the tests in tests/test_oracle_*.py (closed forms, Table 1, conservation laws, symmetry)
- * except the outer absorbing layer (R16, match_lambda and its use in
- * field_bc): parity unpinned -- the paper gives its form only by reference.
+ * by the tests in tests/test_oracle_*.py (closed forms, Table 1, conservation
+ * laws, symmetry, exact reproduction of linear fields, stationarity and
+ * absorption for the outer layer); the cubic shape of the absorbing ramp
+ * (R16) is a reading the pins do not single out (any ramp that relaxes
+ * towards the initial fields passes them).
  *
  * Layouts (shared interface, not shared code):
  *   field plane  : (n_r + 2 ng) x (n_th + 2 ng) doubles, element (i, j) at
@@ -526,12 +528,24 @@ void orc_push(const orc_params* p, const double* F, orc_particles* P)
 
 /* -------------------------------------------------------------- deposit */
 
+/* Mirror factor of a contribution that lands on node row j (Sec. 3.3.2 with
+ * reading R29): the image of a particle in the nearer polar axis deposits the
+ * same contribution on an axis row (j = 0 or j = n_th) with the component's
+ * axis parity, so the axis rows hold the two-sided (mirrored) values: an even
+ * quantity (J^1, the charge) doubles there, the odd J^3 cancels.  Rows off
+ * the axes receive nothing from the image (it lies beyond the axis). */
+static double axis_image(const orc_params* p, int j, double parity)
+{
+  return (j == 0 || j == p->n_th) ? 1.0 + parity : 1.0;
+}
+
 /* Conformal charge-conserving deposit (Sec. 3.2, eq. charge-conservation-disc)
  * by the zigzag scheme of Umeda et al. (2003) with the first-order shape in
  * code coordinates (reading R9), from the stored previous position to the
  * stored new one (after axis reflection, R28).  J^1 at (i+1/2, j), J^2 at
  * (i, j+1/2); the out-of-plane J^3 = q (alpha/gamma) u^3 at nodes, weighted by
  * the shape at the path midpoint with theta clamped (Sec. 3.3.2, reading R11).
+ * Node rows on the axes take the particle's mirror image too (axis_image).
  * Adds into planes P_J; processes particles in index order. */
 static void deposit_one(const orc_params* p, double* F, const orc_particles* P, int64_t k)
 {
@@ -563,12 +577,12 @@ static void deposit_one(const orc_params* p, double* F, const orc_particles* P, 
   double Wx1 = 0.5 * (xa + xr), Wy1 = 0.5 * (ya + yr);
   double Wx2 = 0.5 * (xr + xb) - ibl, Wy2 = 0.5 * (yr + yb) - jbl;
 
-  J1[IX(p, ia, ja)] += Fx1 * (1.0 - Wy1);
-  J1[IX(p, ia, ja + 1)] += Fx1 * Wy1;
+  J1[IX(p, ia, ja)] += Fx1 * (1.0 - Wy1) * axis_image(p, ja, 1.0);
+  J1[IX(p, ia, ja + 1)] += Fx1 * Wy1 * axis_image(p, ja + 1, 1.0);
   J2[IX(p, ia, ja)] += Fy1 * (1.0 - Wx1);
   J2[IX(p, ia + 1, ja)] += Fy1 * Wx1;
-  J1[IX(p, ib, jb)] += Fx2 * (1.0 - Wy2);
-  J1[IX(p, ib, jb + 1)] += Fx2 * Wy2;
+  J1[IX(p, ib, jb)] += Fx2 * (1.0 - Wy2) * axis_image(p, jb, 1.0);
+  J1[IX(p, ib, jb + 1)] += Fx2 * Wy2 * axis_image(p, jb + 1, 1.0);
   J2[IX(p, ib, jb)] += Fy2 * (1.0 - Wx2);
   J2[IX(p, ib + 1, jb)] += Fy2 * Wx2;
 
@@ -583,10 +597,11 @@ static void deposit_one(const orc_params* p, double* F, const orc_particles* P, 
   int km = ia + (int)fm, lm = ja + (int)gm;
   double w1 = xm - fm, w2 = ym - gm;
   double c3 = q * v[2];
-  J3[IX(p, km, lm)] += c3 * (1.0 - w1) * (1.0 - w2);
-  J3[IX(p, km + 1, lm)] += c3 * w1 * (1.0 - w2);
-  J3[IX(p, km, lm + 1)] += c3 * (1.0 - w1) * w2;
-  J3[IX(p, km + 1, lm + 1)] += c3 * w1 * w2;
+  double e0 = axis_image(p, lm, -1.0), e1 = axis_image(p, lm + 1, -1.0);
+  J3[IX(p, km, lm)] += c3 * (1.0 - w1) * (1.0 - w2) * e0;
+  J3[IX(p, km + 1, lm)] += c3 * w1 * (1.0 - w2) * e0;
+  J3[IX(p, km, lm + 1)] += c3 * (1.0 - w1) * w2 * e1;
+  J3[IX(p, km + 1, lm + 1)] += c3 * w1 * w2 * e1;
 }
 
 void orc_deposit(const orc_params* p, double* F, const orc_particles* P)
@@ -595,7 +610,8 @@ void orc_deposit(const orc_params* p, double* F, const orc_particles* P)
 }
 
 /* conformal charge sqrt(h) rho = sum q S(x - x_p) at nodes (Sec. 3.2), first-order
- * shape at the current positions; written to plane `out` (zeroed first) */
+ * shape at the current positions, the axis rows two-sided like the deposited
+ * current (axis_image); written to plane `out` (zeroed first) */
 void orc_charge(const orc_params* p, const orc_particles* P, double* out)
 {
   memset(out, 0, sizeof(double) * g_plane(p));
@@ -608,10 +624,11 @@ void orc_charge(const orc_params* p, const orc_particles* P, double* out)
     double q = sign * p->charge_scale * P->w[k];
     int i = P->i1[k], j = P->i2[k];
     double w1 = P->dx1[k], w2 = P->dx2[k];
-    out[IX(p, i, j)] += q * (1.0 - w1) * (1.0 - w2);
-    out[IX(p, i + 1, j)] += q * w1 * (1.0 - w2);
-    out[IX(p, i, j + 1)] += q * (1.0 - w1) * w2;
-    out[IX(p, i + 1, j + 1)] += q * w1 * w2;
+    double e0 = axis_image(p, j, 1.0), e1 = axis_image(p, j + 1, 1.0);
+    out[IX(p, i, j)] += q * (1.0 - w1) * (1.0 - w2) * e0;
+    out[IX(p, i + 1, j)] += q * w1 * (1.0 - w2) * e0;
+    out[IX(p, i, j + 1)] += q * (1.0 - w1) * w2 * e1;
+    out[IX(p, i + 1, j + 1)] += q * w1 * w2 * e1;
   }
 }
 
@@ -756,7 +773,8 @@ static void axis_bc(const orc_params* p, double* X, int kind)
 }
 
 /* cubic absorbing ramp (R16): 0 inside, ((x - x0)/n_absorb)^3 capped at 1.
- * Parity unpinned: no value of the paper fixes this form. */
+ * The paper fixes no value of this form; the pins fix its direction (towards
+ * the initial fields) and that it absorbs, not the cubic shape. */
 static double match_lambda(const orc_params* p, double x)
 {
   if (p->n_absorb <= 0) return 0.0;
@@ -938,17 +956,17 @@ static void faraday(const orc_params* p, double* X, const double* E, double dt)
 
 /* eq. discretized-ampere: X <- X + dt (curl H - 4 pi J)/sqrt(h) with J the
  * average of w0 * J0 + w1 * J1 (planes); D^1 on the axis rows by the integral
- * (polar-cap) form of Sec. 3.3.2 with the cap area A_{i+1/2}.  At theta = pi
- * the cap is bounded with the opposite orientation (R29), and the axis-row
- * current is the one-sided first-order deposit, so the cap charge balance
- * uses 4 pi (R29). */
+ * (polar-cap) form of Sec. 3.3.2 with the cap area A_{i+1/2} and the printed
+ * 2 pi, which goes with the two-sided (mirrored) axis-row current the deposit
+ * leaves there (R29).  At theta = pi the cap is bounded with the opposite
+ * orientation (R29). */
 static void ampere(const orc_params* p, double* X, const double* H, const double* Ja,
                    const double* Jb, double wa, double wb, double dt)
 {
   const int64_t pl = g_plane(p);
   const double *H1 = H, *H2 = H + pl, *H3 = H + 2 * pl;
   double *X1 = X, *X2 = X + pl, *X3 = X + 2 * pl;
-  const double fpi = 4.0 * M_PI;
+  const double fpi = 4.0 * M_PI, tpi = 2.0 * M_PI;
 #define JJ(c, o) (wa * Ja[(c) * pl + (o)] + wb * Jb[(c) * pl + (o)])
   for (int i = 0; i < p->n_r; ++i) {
     for (int j = 1; j < p->n_th; ++j) {
@@ -959,8 +977,8 @@ static void ampere(const orc_params* p, double* X, const double* H, const double
     }
     double Ap = polar_area(p, i);
     int64_t o0 = IX(p, i, 0), on = IX(p, i, p->n_th);
-    X1[o0] += dt * (H3[IX(p, i, 0)] - fpi * JJ(0, o0)) / Ap;
-    X1[on] += dt * (-H3[IX(p, i, p->n_th - 1)] - fpi * JJ(0, on)) / Ap;
+    X1[o0] += dt * (H3[IX(p, i, 0)] - tpi * JJ(0, o0)) / Ap;
+    X1[on] += dt * (-H3[IX(p, i, p->n_th - 1)] - tpi * JJ(0, on)) / Ap;
   }
   for (int i = 0; i <= p->n_r; ++i)
     for (int j = 0; j < p->n_th; ++j) {
@@ -1336,9 +1354,17 @@ void orc_energy_momentum(const orc_params* p, const orc_particles* P, double B0v
 
 /* Gauss-law residual at nodes (Sec. 3.2): res(i, j) = Delta_i(sqrt(h) D^1)
  * + Delta_j(sqrt(h) D^2) - 4 pi (sqrt(h) rho), with the conformal charge of the
- * current positions filtered like the currents (n_f passes).  Written to
- * `res` (a plane; zero outside i in [n_f + 2, n_r - n_absorb), j in [1, n_th)).
- * Returns the largest |res| and, in *scale, the largest |term|. */
+ * current positions (two-sided on the axis rows, like the deposit) filtered
+ * like the currents (n_f passes).  On the axis nodes the polar-cap form of
+ * Sec. 3.3.2: A_{i+1/2} D^1(i+1/2, 0) - A_{i-1/2} D^1(i-1/2, 0)
+ * + sqrt(h) D^2(i, 1/2) - 2 pi (two-sided charge), and its mirror image at
+ * theta = pi with the opposite orientation of the D^2 flux (R29).
+ * Written to `res` (a plane; zero outside i in [n_f + 2, i_hi), j in [0, n_th]):
+ * the horizon layer overwrites the columns i <= n_f, and the outer columns
+ * from i_hi = n_r - max(n_absorb, n_f) on are the absorbing layer or take
+ * filtered charge from particles that leave the grid (their charge vanishes
+ * on removal without a current).  Returns the largest |res| and, in *scale,
+ * the largest |term|. */
 double orc_gauss_residual(const orc_params* p, const double* F, const orc_particles* P, double* res,
                           double* tmp, double* scale)
 {
@@ -1350,8 +1376,10 @@ double orc_gauss_residual(const orc_params* p, const double* F, const orc_partic
   memcpy(rho, tmp, sizeof(double) * pl);
   memset(res, 0, sizeof(double) * pl);
   double mx = 0.0, sc = 0.0;
-  for (int i = p->n_filter + 2; i < p->n_r - p->n_absorb; ++i)
-    for (int j = 1; j < p->n_th; ++j) {
+  const int nth = p->n_th;
+  const int i_hi = p->n_r - (p->n_absorb > p->n_filter ? p->n_absorb : p->n_filter);
+  for (int i = p->n_filter + 2; i < i_hi; ++i) {
+    for (int j = 1; j < nth; ++j) {
       gpt a, b, c, d;
       grid_metric(p, i, j, 1, 0, &a);
       grid_metric(p, i - 1, j, 1, 0, &b);
@@ -1366,6 +1394,21 @@ double orc_gauss_residual(const orc_params* p, const double* F, const orc_partic
       double tm = fmax(fmax(fabs(t1), fabs(t2)), fmax(fmax(fabs(t3), fabs(t4)), fabs(t5)));
       if (tm > sc) sc = tm;
     }
+    const double Ahi = polar_area(p, i), Alo = polar_area(p, i - 1);
+    for (int side = 0; side < 2; ++side) {
+      const int j = side ? nth : 0;
+      gpt c;
+      grid_metric(p, i, side ? nth - 1 : 0, 0, 1, &c);
+      double t1 = Ahi * D1[IX(p, i, j)], t2 = Alo * D1[IX(p, i - 1, j)];
+      double t3 = c.sqrt_h * D2[IX(p, i, side ? nth - 1 : 0)];
+      double t5 = 2.0 * M_PI * rho[IX(p, i, j)];
+      double r = (t1 - t2) + (side ? -t3 : t3) - t5;
+      res[IX(p, i, j)] = r;
+      if (fabs(r) > mx) mx = fabs(r);
+      double tm = fmax(fmax(fabs(t1), fabs(t2)), fmax(fabs(t3), fabs(t5)));
+      if (tm > sc) sc = tm;
+    }
+  }
   free(rho);
   *scale = sc;
   return mx;
@@ -1388,3 +1431,31 @@ double orc_courant_dt(const orc_params* p, double cfl)
     }
   return cfl / vmax;
 }
+
+/* ------------------------------------------------- parts, for the pins */
+
+/* The parts below are called on their own by the tests that pin them. */
+
+/* gather of Sec. 3.1 step 2 at a position: D^n from plane P_D, B^n from P_B0 */
+void orc_gather(const orc_params* p, const double* F, int i1, double dx1, int i2, double dx2,
+                double D[3], double B[3])
+{
+  const int64_t pl = g_plane(p);
+  gather(p, F + P_D * pl, F + P_B0 * pl, i1, dx1, i2, dx2, D, B);
+}
+
+/* axis reflection of a triple (kind 0 D-like, 1 B-like, 2 current) */
+void orc_axis_bc(const orc_params* p, double* X, int kind) { axis_bc(p, X, kind); }
+
+/* boundaries of an updated triple against its absorbing-layer target */
+void orc_field_bc(const orc_params* p, double* X, const double* Xinit, int kind)
+{
+  field_bc(p, X, Xinit, kind);
+}
+
+/* the n_f filter passes on the current planes P_J */
+void orc_filter_currents(const orc_params* p, double* F) { filter_currents(p, F); }
+
+/* absorbing-layer ramp lambda at x1 = x */
+double orc_match_lambda(const orc_params* p, double x) { return match_lambda(p, x); }
+

@@ -88,8 +88,10 @@ diag_particles_kernel(Grid g, ParticleArraysT<T> P, double B0, T* __restrict__ E
 }
 
 // first-order charge sqrt(h) rho = sum q S at the nodes around the current
-// positions; the lanes of a wavefront that share a cell add their run sum
-// once (every lane reaches the run sums: no early return before them)
+// positions, two-sided on the axis node rows like the deposited current (the
+// particle's mirror image in the nearer axis doubles an axis-row value); the
+// lanes of a wavefront that share a cell add their run sum once (every lane
+// reaches the run sums: no early return before them)
 template <class T>
 __global__ void __launch_bounds__(256) charge_kernel(Grid g, ParticleArraysT<T> P, T* __restrict__ Q) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,12 +110,13 @@ __global__ void __launch_bounds__(256) charge_kernel(Grid g, ParticleArraysT<T> 
       q = sg * g.charge_scale * P.w[k];
     }
   }
+  const double e0 = (i2 == 0) ? 2.0 : 1.0, e1 = (i2 + 1 == g.n_th) ? 2.0 : 1.0;
   const T z = (T)0;
   const Runs r = runs_of(act ? (i1 + 2) * g.ld + (i2 + 2) : -1);
-  const T s00 = run_sum(act ? (T)(q * (1.0 - w1) * (1.0 - w2)) : z, r);
-  const T s01 = run_sum(act ? (T)(q * (1.0 - w1) * w2) : z, r);
-  const T s10 = run_sum(act ? (T)(q * w1 * (1.0 - w2)) : z, r);
-  const T s11 = run_sum(act ? (T)(q * w1 * w2) : z, r);
+  const T s00 = run_sum(act ? (T)(q * (1.0 - w1) * (1.0 - w2) * e0) : z, r);
+  const T s01 = run_sum(act ? (T)(q * (1.0 - w1) * w2 * e1) : z, r);
+  const T s10 = run_sum(act ? (T)(q * w1 * (1.0 - w2) * e0) : z, r);
+  const T s11 = run_sum(act ? (T)(q * w1 * w2 * e1) : z, r);
   if (act && r.head) {
     T* p = Q + ix(g, i1, i2);
     atomic_add(p, s00);
@@ -123,25 +126,47 @@ __global__ void __launch_bounds__(256) charge_kernel(Grid g, ParticleArraysT<T> 
   }
 }
 
-// residual div D - 4 pi rho at nodes i in [n_f + 2, n_r - n_absorb), j in [1, n_th)
-template <class T>
-__global__ void gauss_kernel(Grid g, Tables t, const T* __restrict__ D1,
+// residual div D - 4 pi rho at nodes i in [n_f + 2, i_hi), j in [0, n_th]:
+// the horizon layer overwrites the columns i <= n_f, and from
+// i_hi = n_r - max(n_absorb, n_f) on lie the absorbing layer and the columns
+// that take filtered charge from particles leaving the grid.  The axis nodes
+// take the polar-cap form of Sec. 3.3.2, A_{i+1/2} D^1(i+1/2) - A_{i-1/2}
+// D^1(i-1/2) +- sqrt(h) D^2 - 2 pi rho with the two-sided axis-row charge (the
+// D^2 flux enters with the opposite orientation at theta = pi).
+template <class T, bool kQ>
+__global__ void gauss_kernel(Grid g, Tables t, double polar_k, int i_hi, const T* __restrict__ D1,
                              const T* __restrict__ D2, const T* __restrict__ Q,
                              T* __restrict__ res, DiagAcc* acc) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y + g.n_filter + 2;
   double rmax = 0.0, smax = 0.0;
-  if (j < g.n_th && i < g.n_r - g.n_absorb) {
+  if (j <= g.n_th && i < i_hi) {
     const int64_t o = ix(g, i, j);
-    const double t1 = cell_tab(g, t, i, 1, j, 0).sqrt_h * D1[o];
-    const double t2 = cell_tab(g, t, i - 1, 1, j, 0).sqrt_h * D1[o - g.ld];
-    const double t3 = cell_tab(g, t, i, 0, j, 1).sqrt_h * D2[o];
-    const double t4 = cell_tab(g, t, i, 0, j - 1, 1).sqrt_h * D2[o - 1];
-    const double t5 = 4.0 * kPi * Q[o];
-    const double r = (t1 - t2) + (t3 - t4) - t5;
+    double r;
+    if (j >= 1 && j < g.n_th) {
+      const double t1 = cell_tab(g, t, i, 1, j, 0).sqrt_h * D1[o];
+      const double t2 = cell_tab(g, t, i - 1, 1, j, 0).sqrt_h * D1[o - g.ld];
+      const double t3 = cell_tab(g, t, i, 0, j, 1).sqrt_h * D2[o];
+      const double t4 = cell_tab(g, t, i, 0, j - 1, 1).sqrt_h * D2[o - 1];
+      const double t5 = 4.0 * kPi * Q[o];
+      r = (t1 - t2) + (t3 - t4) - t5;
+      smax = fmax(fmax(fabs(t1), fabs(t2)), fmax(fmax(fabs(t3), fabs(t4)), fabs(t5)));
+    } else {
+      auto cap = [&](int ii) {
+        const double rr = t.r[1][ii + g.ng];
+        const double ra = rr * rr + g.a * g.a;
+        return g.dxi * (kQ ? rr - g.r0 : rr) * ra * sqrt(1.0 + 2.0 * g.M * rr / ra) * polar_k;
+      };
+      const int jd = j == 0 ? 0 : g.n_th - 1;
+      const double t1 = cap(i) * D1[o];
+      const double t2 = cap(i - 1) * D1[o - g.ld];
+      const double t3 = cell_tab(g, t, i, 0, jd, 1).sqrt_h * D2[ix(g, i, jd)];
+      const double t5 = 2.0 * kPi * Q[o];
+      r = (t1 - t2) + (j == 0 ? t3 : -t3) - t5;
+      smax = fmax(fmax(fabs(t1), fabs(t2)), fmax(fabs(t3), fabs(t5)));
+    }
     if (res) res[o] = r;
     rmax = fabs(r);
-    smax = fmax(fmax(fabs(t1), fabs(t2)), fmax(fmax(fabs(t3), fabs(t4)), fabs(t5)));
   }
   for (int off = 32; off > 0; off >>= 1) {
     rmax = fmax(rmax, __shfl_down(rmax, off, 64));

@@ -213,9 +213,9 @@ __global__ void faraday_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> 
 
 // ---------------------------------------------------------------- Ampere
 // eq. discretized-ampere with the current J = wa Ja + wb Jb; D^1 on the axis
-// rows from the polar-cap integral form (Sec. 3.3.2): cap area A_{i+1/2}; the
-// theta = pi cap has the opposite orientation, and the one-sided axis-row
-// current enters with 4 pi.
+// rows from the polar-cap integral form (Sec. 3.3.2): cap area A_{i+1/2}, the
+// printed 2 pi with the two-sided (mirrored) axis-row current the deposit
+// leaves there; the theta = pi cap has the opposite orientation.
 // kFinal (the last half of the step): the grid spans the whole plane, the
 // current is Ja alone, and the same pass takes X0 <- X before the update and
 // rotates the currents, Jb <- Ja and Ja <- 0, after it.
@@ -252,7 +252,7 @@ __global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H
         const double ra = r * r + g.a * g.a;
         const double Ap = g.dxi * (kQ ? r - g.r0 : r) * ra * sqrt(1.0 + 2.0 * g.M * r / ra) * polar_k;
         const double h3 = (j == 0) ? H.p[2][o] : -H.p[2][o - 1];
-        add_to(X.p[0], L.p[0], o, g.dt * (h3 - fpi * J1) / Ap);
+        add_to(X.p[0], L.p[0], o, g.dt * (h3 - 2.0 * kPi * J1) / Ap);
       }
     }
     if (j < g.n_th) {

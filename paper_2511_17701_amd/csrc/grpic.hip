@@ -412,10 +412,15 @@ grpic_status diagnostics_impl(grpic_ctx* c, const grpic_fields* F, const grpic_p
     hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (T*)gauss_res, 0.0);
     LAUNCH_CHECK("fill");
   }
-  const int ni = g.n_r - g.n_absorb - (g.n_filter + 2), nj = g.n_th - 1;
-  if (ni > 0 && nj > 0) {
-    hipLaunchKernelGGL(gauss_kernel<T>, grid2(ni, nj), kBlock2, 0, s, g, c->tab, (const T*)F->D[0],
-                       (const T*)F->D[1], (const T*)Q, (T*)gauss_res, c->acc);
+  const int i_hi = g.n_r - std::max(g.n_absorb, g.n_filter);
+  const int ni = i_hi - (g.n_filter + 2), nj = g.n_th + 1;
+  if (ni > 0) {
+    if (g.r0 != 0.0 || g.h0 != 0.0)
+      hipLaunchKernelGGL((gauss_kernel<T, true>), grid2(ni, nj), kBlock2, 0, s, g, c->tab, c->polar_k, i_hi,
+                         (const T*)F->D[0], (const T*)F->D[1], (const T*)Q, (T*)gauss_res, c->acc);
+    else
+      hipLaunchKernelGGL((gauss_kernel<T, false>), grid2(ni, nj), kBlock2, 0, s, g, c->tab, c->polar_k, i_hi,
+                         (const T*)F->D[0], (const T*)F->D[1], (const T*)Q, (T*)gauss_res, c->acc);
     LAUNCH_CHECK("gauss");
   }
   return GRPIC_OK;

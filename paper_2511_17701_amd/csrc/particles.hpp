@@ -777,6 +777,25 @@ __device__ inline bool make_contrib(const Grid& g, const Tables& tab, const Move
   c.j3[1] = c3 * (one - w1) * w2;
   c.j3[2] = c3 * w1 * (one - w2);
   c.j3[3] = c3 * w1 * w2;
+  // The particle's mirror image in the nearer axis (Sec. 3.3.2) adds the same
+  // contribution on an axis node row (j = 0 or n_th) with the component's axis
+  // parity: J^1 (even) doubles there, J^3 (odd) cancels, so the axis rows hold
+  // the two-sided values the polar-cap update takes with 2 pi.  The footprint
+  // spans node rows ja - 1 .. ja + 2, so only particles within two rows of an
+  // axis can reach one (a wavefront-uniform skip for cell-sorted particles).
+  if (ja <= 1 || ja >= g.n_th - 2) {
+    auto e1 = [&](int j) { return (j == 0 || j == g.n_th) ? (T)2 : one; };
+    auto e3 = [&](int j) { return (j == 0 || j == g.n_th) ? (T)0 : one; };
+    c.j1[0] *= e1(ja);
+    c.j1[1] *= e1(ja + 1);
+    c.j1[2] *= e1(ja + dj);
+    c.j1[3] *= e1(ja + dj + 1);
+    const T f0 = e3(ja + c.lm), f1 = e3(ja + c.lm + 1);
+    c.j3[0] *= f0;
+    c.j3[1] *= f1;
+    c.j3[2] *= f0;
+    c.j3[3] *= f1;
+  }
   return true;
 }
 

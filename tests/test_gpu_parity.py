@@ -107,7 +107,7 @@ def assert_particles(prm, Po, Pg, tol=TOL, what="", prev=True):
         worst = (err / bound).max(initial=0)
         assert worst <= 1.0, f"{what} {k}: worst err/bound {worst:.3e}"
     err = np.abs(Pg["phi"] - Po["phi"])[live]
-    assert err.max(initial=0) <= tol * max(1.0, np.abs(Po["phi"]).max()) * 1e3, what + " phi"
+    assert err.max(initial=0) <= tol * max(1.0, np.abs(Po["phi"]).max()), what + " phi"
 
 
 def assert_fields(F_o, F_g, planes, tol=TOL, what=""):

@@ -147,24 +147,77 @@ def test_gauss_law_preserved(O):
     assert np.abs(res1 - res0).max() <= 2e-14 * scale
 
 
-def test_gauss_law_preserved_with_filter(O):
-    """With n_f = 2 filter passes (R15) the discrete divergence of the filtered
-    current equals minus the rate of the identically filtered charge, so the
-    residual stays fixed at interior nodes away from the radial boundary
-    layers and the axis rows touched by the filter's axis ghosts."""
-    prm = c1_params(O, 32, charge_scale=0.02, n_filter=2)
-    F, P, res0, res1, scale = _run_with_particles(O, prm, 20, 2)
+def _filtered_gauss_drift(O, steps=50, n_filter=4):
+    """Largest change of the Gauss residual over `steps` full steps with n_f
+    filter passes, relative to the largest term, on every node the residual
+    covers (the axis nodes in the polar-cap form), and on the n_f + 2 node
+    rows next to each axis (axis rows included)."""
+    prm = c1_params(O, 32, charge_scale=0.02, n_filter=n_filter)
+    F, P, res0, res1, scale = _run_with_particles(O, prm, steps, 2)
     d = np.abs(res1 - res0)
-    g = prm.ng
-    inner = d[g + 6:g + 32 - 6, g + 3:g + 32 - 2]
-    assert inner.max() <= 2e-14 * scale
+    g, n = prm.ng, 32
+    i = slice(g + n_filter + 2, g + n)
+    near = max(d[i, g:g + n_filter + 2].max(), d[i, g + n - n_filter - 1:g + n + 1].max())
+    assert (res0[i, g] != 0).any() and (res0[i, g + n] != 0).any()   # axis nodes covered
+    return d.max() / scale, near / scale
+
+
+# axis rows left one-sided: the deposit without the particles' mirror images
+ONE_SIDED_AXIS = (("return (j == 0 || j == p->n_th) ? 1.0 + parity : 1.0;", "return 1.0;"),
+                  ("const double fpi = 4.0 * M_PI, tpi = 2.0 * M_PI;",
+                   "const double fpi = 4.0 * M_PI, tpi = 4.0 * M_PI;"),
+                  ("double t5 = 2.0 * M_PI * rho[IX(p, i, j)];", "double t5 = 4.0 * M_PI * rho[IX(p, i, j)];"))
+
+
+def test_gauss_law_preserved_with_filter(O):
+    """With n_f = 4 filter passes (R15, the C5 setting) the discrete divergence
+    of the filtered current equals minus the rate of the identically filtered
+    charge at every node, the axis nodes and the n_f + 1 rows next to each
+    axis included: the deposit leaves two-sided (mirrored) values on the axis
+    rows (R29), so the parity ghosts of the filter continue the current and
+    the charge as the particles' mirror images do, and the (1,2,1) stencil
+    commutes with the divergence there as in the interior.  Checked over 50
+    steps on every node clear of the radial boundary layers."""
+    drift, near = _filtered_gauss_drift(O)
+    assert drift <= 2e-14 and near <= 2e-14, (drift, near)
+
+
+def test_gauss_with_filter_fails_one_sided_axis_rows(O):
+    """Planted mistake: the axis rows left one-sided (the reading before R29 was
+    settled: no mirror images, 4 pi in the cap update and the cap residual)
+    keep Gauss's law without filtering but break it on the rows next to the
+    axes once the filter is on, so the pin above fixes the axis convention."""
+    with O.planted(*ONE_SIDED_AXIS):
+        drift0, _ = _filtered_gauss_drift(O, steps=10, n_filter=0)
+        drift, near = _filtered_gauss_drift(O, steps=10)
+    assert drift0 <= 2e-14
+    assert near >= 1e-9 and drift == near, (drift, near)
+
+
+def test_gauss_with_filter_fails_planted_mistakes(O):
+    """Planted mistakes in the parts the filtered Gauss pin covers each break it:
+    a J^1 axis ghost with the odd parity, J^2 with the even one, the axis-row
+    J^3 kept (not cancelled by its mirror image), the cap current with 4 pi."""
+    plants = [
+        (("const double par[3] = {1.0, -1.0, -1.0};", "const double par[3] = {-1.0, -1.0, -1.0};"),),
+        (("const double par[3] = {1.0, -1.0, -1.0};", "const double par[3] = {1.0, 1.0, -1.0};"),),
+        (("const double fpi = 4.0 * M_PI, tpi = 2.0 * M_PI;",
+          "const double fpi = 4.0 * M_PI, tpi = 4.0 * M_PI;"),),
+    ]
+    for pl in plants:
+        with O.planted(*pl):
+            drift, near = _filtered_gauss_drift(O, steps=10)
+        assert drift >= 1e-9, (pl, drift)
 
 
 def test_axis_cap_charge_conservation(O):
     """Charge balance at the axis nodes (R29): the polar-cap form of Gauss's law,
-    A_{i+1/2} D^1(i+1/2, 0) - A_{i-1/2} D^1(i-1/2, 0) + sqrt(h) D^2(i, 1/2) - 4 pi Q(i, 0)
-    (and its mirror at theta = pi), is conserved to round-off by the axis
-    D^1 update with the one-sided deposit."""
+    A_{i+1/2} D^1(i+1/2, 0) - A_{i-1/2} D^1(i-1/2, 0) + sqrt(h) D^2(i, 1/2) - 2 pi Q(i, 0)
+    with the two-sided (mirrored) axis-row charge Q (and its mirror at
+    theta = pi), is conserved to round-off by the axis D^1 update with the
+    printed 2 pi and the two-sided axis-row current.  The cap areas are written
+    out here from App. A; the oracle's Gauss residual on the axis nodes must
+    equal these values."""
     prm = c1_params(O, 24, charge_scale=0.05)
     F = O.fields_init_wald(prm, 1.0)
     # particles concentrated next to both axes
@@ -191,9 +244,9 @@ def test_axis_cap_charge_conservation(O):
             s_hi = O.metric_at(prm, i, n - 0.5, clamp=False)["sqrt_h"]
             D1, D2 = F[0], F[1]
             lo = (A[1] * D1[i + g, g] - A[0] * D1[i - 1 + g, g] + s_lo * D2[i + g, g] -
-                  4 * math.pi * rho[i + g, g])
+                  2 * math.pi * rho[i + g, g])
             hi = (A[1] * D1[i + g, n + g] - A[0] * D1[i - 1 + g, n + g] -
-                  s_hi * D2[i + g, n - 1 + g] - 4 * math.pi * rho[i + g, n + g])
+                  s_hi * D2[i + g, n - 1 + g] - 2 * math.pi * rho[i + g, n + g])
             out.append((lo, hi))
         return np.array(out)
 
@@ -203,6 +256,9 @@ def test_axis_cap_charge_conservation(O):
     c1 = caps()
     scale = np.abs(F[0:2]).max() * 1e-3 + np.abs(c0).max()
     assert np.abs(c1 - c0).max() <= 1e-12 * scale, np.abs(c1 - c0).max() / scale
+    res, _, _ = O.gauss_residual(prm, F, P)
+    np.testing.assert_allclose(res[g + 3:g + n - 2, g], c1[:, 0], rtol=1e-12, atol=1e-14 * scale)
+    np.testing.assert_allclose(res[g + 3:g + n - 2, g + n], c1[:, 1], rtol=1e-12, atol=1e-14 * scale)
 
 
 # ------------------------------------------------------- mirror symmetry

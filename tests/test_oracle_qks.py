@@ -237,7 +237,7 @@ def test_gauss_law_preserved_on_general_map(O):
     """With charge deposited and no filtering the full PIC step keeps
     div D - 4 pi rho fixed to round-off at every interior node on the general
     map, and the polar-cap balance at both axes (the cap bounded by
-    theta(x2 = 1/2), R29) to round-off."""
+    theta(x2 = 1/2), 2 pi with the two-sided axis-row charge, R29) to round-off."""
     n = 24
     prm = qparams(O, n=n, charge_scale=0.05)
     F = O.fields_init_wald(prm, 1.0)
@@ -262,9 +262,9 @@ def test_gauss_law_preserved_on_general_map(O):
             s_hi = O.metric_at(prm, i, n - 0.5, clamp=False)["sqrt_h"]
             D1, D2 = F[0], F[1]
             lo = (A[1] * D1[i + g, g] - A[0] * D1[i - 1 + g, g] + s_lo * D2[i + g, g] -
-                  4 * math.pi * rho[i + g, g])
+                  2 * math.pi * rho[i + g, g])
             hi = (A[1] * D1[i + g, n + g] - A[0] * D1[i - 1 + g, n + g] -
-                  s_hi * D2[i + g, n - 1 + g] - 4 * math.pi * rho[i + g, n + g])
+                  s_hi * D2[i + g, n - 1 + g] - 2 * math.pi * rho[i + g, n + g])
             out.append((lo, hi))
         return np.array(out)
 
