@@ -117,6 +117,11 @@ def _load(path):
     L.orc_courant_dt.argtypes = [P, c_double]
     L.orc_courant_dt.restype = c_double
     L.orc_num_threads.restype = c_int
+    L.orc_set_num_threads.argtypes = [c_int]
+    L.orc_inject_pairs.argtypes = [P, D, PP, c_double, c_double, c_int32, c_double, c_int32,
+                                   c_int32, c_uint64, c_uint32, c_int64]
+    L.orc_inject_pairs.restype = c_int64
+    L.orc_magnetisation.argtypes = [P, D, PP, D]
     L.orc_wald_potential_planes.argtypes = [P, c_double, D, D]
     L.orc_sqrt_h_plane.argtypes = [P, c_int, c_int, D]
     L.orc_gather.argtypes = [P, D, c_int32, c_double, c_int32, c_double, D, D]
@@ -316,6 +321,24 @@ def wald_fields(prm: Params, x1: float, x2: float, B0: float):
     return D, B
 
 
+def inject_pairs(prm: Params, F: np.ndarray, P: dict, sigma_th: float, T: float, n_inj: int,
+                 w_inj: float, i_lo: int, i_hi: int, seed: int, call: int, first_free: int) -> int:
+    """Pair injection where sigma >= sigma_th (Sec. 4.4, 4.5; reading R30): writes the
+    new pairs into slots first_free, first_free + 1, ... of P and returns their count."""
+    s = _pstruct(P)
+    return lib().orc_inject_pairs(ctypes.byref(prm), _dp(F), ctypes.byref(s), sigma_th, T,
+                                  int(n_inj), w_inj, int(i_lo), int(i_hi), int(seed), int(call),
+                                  int(first_free))
+
+
+def magnetisation(prm: Params, F: np.ndarray, P: dict) -> np.ndarray:
+    """sigma = B_i B^i / (4 pi n) at every cell centre, shape (n_r, n_th)."""
+    out = np.zeros((prm.n_r, prm.n_th))
+    s = _pstruct(P)
+    lib().orc_magnetisation(ctypes.byref(prm), _dp(F), ctypes.byref(s), _dp(out))
+    return out
+
+
 def energy_momentum(prm: Params, P: dict, B0: float):
     n = len(P["tag"])
     E = np.zeros(n)
@@ -351,6 +374,11 @@ def sqrt_h_plane(prm: Params, o1: int, o2: int) -> np.ndarray:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP thread count of later oracle calls (for timing the oracle)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def courant_dt(prm: Params, cfl: float) -> float:

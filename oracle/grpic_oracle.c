@@ -162,6 +162,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* thread count of the following parallel regions (timing of the oracle only) */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* charge-to-mass ratio per species tag (R12): e+ = +1, e- = -1, neutral = 0 */
 static double tag_qm(uint8_t t)
 {
@@ -1220,6 +1230,16 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* counter (idx, sub, stream, k): sub = 0 for the initial loading, 1 + call for
+ * the injection call `call` */
+static void draw_sub(uint64_t seed, uint32_t idx, uint32_t sub, uint32_t stream, uint32_t k,
+                     uint32_t out[4])
+{
+  uint32_t ctr[4] = {idx, sub, stream, k};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
 static void draw(uint64_t seed, uint32_t idx, uint32_t stream, uint32_t k, uint32_t out[4])
 {
   uint32_t ctr[4] = {idx, 0u, stream, k};
@@ -1235,19 +1255,19 @@ static void draw(uint64_t seed, uint32_t idx, uint32_t stream, uint32_t k, uint3
  * (units of m c^2) by Sobol's rejection method as given by Zenitani (2015,
  * Phys. Plasmas 22, 042116): u = -T ln(X1 X2 X3), eta = -T ln(X1 X2 X3 X4),
  * accept if eta^2 - u^2 > 1; direction from two more uniforms. */
-static void mj_sample(uint64_t seed, uint32_t q, double T, double uh[3])
+static void mj_sample(uint64_t seed, uint32_t q, uint32_t sub, double T, double uh[3])
 {
   double u = 0.0;
   for (uint32_t k = 0; k < 4096u; ++k) {
     uint32_t w[4];
-    draw(seed, q, 1u, k, w);
+    draw_sub(seed, q, sub, 1u, k, w);
     double x1 = U01_OPEN0(w[0]), x2 = U01_OPEN0(w[1]), x3 = U01_OPEN0(w[2]), x4 = U01_OPEN0(w[3]);
     u = -T * log(x1 * x2 * x3);
     double eta = -T * log(x1 * x2 * x3 * x4);
     if (eta * eta - u * u > 1.0) break;
   }
   uint32_t w[4];
-  draw(seed, q, 2u, 0u, w);
+  draw_sub(seed, q, sub, 2u, 0u, w);
   double x5 = U01_HALF(w[0]), x6 = U01_HALF(w[1]);
   double st = 2.0 * u * sqrt(x5 * (1.0 - x5));
   uh[0] = u * (2.0 * x5 - 1.0);
@@ -1286,7 +1306,7 @@ void orc_particles_init(const orc_params* p, orc_particles* P, int64_t n_pairs, 
     for (int s = 0; s < 2; ++s) {
       int64_t q = 2 * k + s;
       double uh[3], u[3];
-      mj_sample(seed, (uint32_t)q, T, uh);
+      mj_sample(seed, (uint32_t)q, 0u, T, uh);
       orc_hat_to_cov(&m, uh, u);
       P->i1[q] = i1; P->i2[q] = i2; P->dx1[q] = dx1; P->dx2[q] = dx2;
       P->i1p[q] = i1; P->i2p[q] = i2; P->dx1p[q] = dx1; P->dx2p[q] = dx2;
@@ -1324,6 +1344,120 @@ void orc_particles_init(const orc_params* p, orc_particles* P, int64_t n_pairs, 
     P->w[q] = 1.0; P->phi[q] = 0.0;
     P->tag[q] = 3;
   }
+}
+
+/* ------------------------------------------------------ pair injection */
+
+/*
+ * Pair injection where the plasma is strongly magnetised (Sec. 4.4 and
+ * Sec. 4.5: e+- pairs at temperature T are added wherever the local
+ * magnetisation sigma = B_i B^i / (4 pi n m) exceeds a threshold; reading R30):
+ *
+ *  - sigma per cell (i, j), i in [i_lo, i_hi), j in [0, n_th), at the cell
+ *    centre (i + 1/2, j + 1/2): B^1 is the mean of its two r-faces' values
+ *    (stored at (i, j + 1/2) and (i + 1, j + 1/2)), B^2 the mean of its two
+ *    theta-faces' ((i + 1/2, j), (i + 1/2, j + 1)), B^3 its own value; plane B
+ *    of the field set;  B_i B^i = h_ij B^i B^j with the code-unit spatial
+ *    metric at the centre;
+ *  - n = kappa sum w / sqrt(h) over the live, not leaving e+ and e- (species
+ *    1, 2, any slot) whose cell is (i, j): the number density with the normalisation
+ *    of the deposited charge (sqrt(h) rho = kappa q sum w S), m = 1;
+ *  - a cell injects when B_i B^i > 0 and B_i B^i >= 4 pi sigma_th n (an
+ *    empty magnetised cell has sigma = infinity);
+ *  - every injecting cell, in the order c = i n_th + j, adds n_inj pairs;
+ *    pair k (counted over the call) fills slots first_free + 2k (e+, tag 1)
+ *    and first_free + 2k + 1 (e-, tag 2) at one position (zero net charge),
+ *    offsets uniform in the cell, momenta isotropic Maxwell-Juttner at T in
+ *    the FIDO tetrad frame at that position, weight w_inj, phi = 0; pairs
+ *    that would not fit below n are not injected;
+ *  - random numbers: Philox4x32-10 with key = seed and counter
+ *    (index, 1 + call, stream, k): streams 0 position (pair index k),
+ *    1 momentum attempts and 2 direction (particle index 2k + s).
+ * Returns the number of pairs injected.
+ */
+/* weight sum of the live, not leaving e+ and e- per cell (n_r x n_th) */
+static double* cell_weights(const orc_params* p, const orc_particles* P)
+{
+  double* wsum = (double*)calloc((size_t)p->n_r * p->n_th, sizeof(double));
+  for (int64_t q = 0; q < P->n; ++q) {
+    uint8_t t = P->tag[q];
+    int s = t & TAG_SPECIES;
+    if (t == 0 || (t & TAG_LEAVING) || (s != 1 && s != 2)) continue;
+    int i = P->i1[q], j = P->i2[q];
+    if (i < 0 || i >= p->n_r || j < 0 || j >= p->n_th) continue;
+    wsum[(int64_t)i * p->n_th + j] += P->w[q];
+  }
+  return wsum;
+}
+
+/* B_i B^i and the number density n at the centre of cell (i, j) */
+static void cell_magnetisation(const orc_params* p, const double* F, const double* wsum, int i, int j,
+                               double* bb, double* n)
+{
+  const int64_t pl = g_plane(p);
+  const double *B1 = F + P_B * pl, *B2 = F + (P_B + 1) * pl, *B3 = F + (P_B + 2) * pl;
+  orc_metric m;
+  orc_metric_at(p, i + 0.5, j + 0.5, 0, &m);
+  double b1 = 0.5 * (B1[IX(p, i, j)] + B1[IX(p, i + 1, j)]);
+  double b2 = 0.5 * (B2[IX(p, i, j)] + B2[IX(p, i, j + 1)]);
+  double b3 = B3[IX(p, i, j)];
+  *bb = m.hl11 * b1 * b1 + 2.0 * m.hl13 * b1 * b3 + m.hl22 * b2 * b2 + m.hl33 * b3 * b3;
+  *n = p->charge_scale * wsum[(int64_t)i * p->n_th + j] / m.sqrt_h;
+}
+
+int64_t orc_inject_pairs(const orc_params* p, const double* F, orc_particles* P, double sigma_th,
+                         double T, int32_t n_inj, double w_inj, int32_t i_lo, int32_t i_hi,
+                         uint64_t seed, uint32_t call, int64_t first_free)
+{
+  double* wsum = cell_weights(p, P);
+  int64_t k = 0;
+  const uint32_t sub = call + 1u;
+  if (i_lo < 0) i_lo = 0;
+  if (i_hi > p->n_r) i_hi = p->n_r;
+  for (int i = i_lo; i < i_hi; ++i) {
+    for (int j = 0; j < p->n_th; ++j) {
+      double bb, n;
+      cell_magnetisation(p, F, wsum, i, j, &bb, &n);
+      if (!(bb > 0.0 && bb >= 4.0 * M_PI * sigma_th * n)) continue;
+      for (int32_t e = 0; e < n_inj; ++e, ++k) {
+        int64_t q0 = first_free + 2 * k;
+        if (q0 + 1 >= P->n) { free(wsum); return k; }
+        uint32_t w[4];
+        draw_sub(seed, (uint32_t)k, sub, 0u, 0u, w);
+        double dx1 = U01_LOW(w[0]), dx2 = U01_LOW(w[1]);
+        orc_metric mp;
+        orc_metric_at(p, i + dx1, j + dx2, 1, &mp);
+        for (int s = 0; s < 2; ++s) {
+          int64_t q = q0 + s;
+          double uh[3], u[3];
+          mj_sample(seed, (uint32_t)(2 * k + s), sub, T, uh);
+          orc_hat_to_cov(&mp, uh, u);
+          P->i1[q] = i; P->i2[q] = j; P->dx1[q] = dx1; P->dx2[q] = dx2;
+          P->i1p[q] = i; P->i2p[q] = j; P->dx1p[q] = dx1; P->dx2p[q] = dx2;
+          P->u1[q] = u[0]; P->u2[q] = u[1]; P->u3[q] = u[2];
+          P->w[q] = w_inj; P->phi[q] = 0.0;
+          P->tag[q] = (uint8_t)(s == 0 ? 1 : 2);
+        }
+      }
+    }
+  }
+  free(wsum);
+  return k;
+}
+
+/* magnetisation sigma of every cell (the quantity the injection tests;
+ * +infinity in a magnetised empty cell, 0 where B = 0), written to an
+ * n_r x n_th array */
+void orc_magnetisation(const orc_params* p, const double* F, const orc_particles* P, double* sigma)
+{
+  double* wsum = cell_weights(p, P);
+  for (int i = 0; i < p->n_r; ++i)
+    for (int j = 0; j < p->n_th; ++j) {
+      double bb, n;
+      cell_magnetisation(p, F, wsum, i, j, &bb, &n);
+      sigma[(int64_t)i * p->n_th + j] = bb <= 0.0 ? 0.0 : (n > 0.0 ? bb / (4.0 * M_PI * n) : INFINITY);
+    }
+  free(wsum);
 }
 
 /* ------------------------------------------------------ diagnostics */
