@@ -243,6 +243,50 @@ grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t 
 grpic_status grpic_sort(grpic_ctx* ctx, const grpic_particles* src, const grpic_particles* dst,
                         int64_t* n_live, void* stream);
 
+/* Parameters of grpic_inject_pairs. */
+typedef struct {
+  double sigma_th;      /* magnetisation threshold (the paper's runs: 1000 and
+                           2000), > 0                                        */
+  double temperature;   /* T of the injected pairs in units of m c^2 (the
+                           paper's runs: 0.5), > 0                           */
+  double weight;        /* weight of every injected particle                 */
+  int32_t n_pairs;      /* pairs added per injecting cell per call, >= 0     */
+  int32_t i_lo, i_hi;   /* radial cells i_lo <= i < i_hi may inject (clipped
+                           to the grid)                                      */
+  int32_t reserved;     /* must be 0                                         */
+  uint64_t seed;        /* Philox4x32-10 key                                 */
+  uint32_t call;        /* index of this injection call, < 2^32 - 1: counter
+                           word 1 is call + 1 (0 is the initial loading's)   */
+} grpic_inject_params;
+
+/* Pair injection where the plasma is strongly magnetised (Sec. 4.4 and
+ * Sec. 4.5: e+- pairs at temperature T are added wherever the magnetisation
+ * sigma = B_i B^i / (4 pi n m) reaches a threshold).
+ *  - sigma of cell (i, j) at its centre: B^1 and B^2 the means of the values
+ *    on its two faces, B^3 its own value, all from plane B;
+ *    B_i B^i = h_ij B^i B^j; n = charge_scale * (sum of the weights of the
+ *    live, not leaving e+ and e- in the cell, any slot) / sqrt(h); m = 1.
+ *    The cell injects when B_i B^i > 0 and B_i B^i >= 4 pi sigma_th n (FP64,
+ *    also in the GRPIC_FP32 form), so a magnetised empty cell injects.
+ *  - Every injecting cell, in the order c = i n_th + j, adds n_pairs pairs:
+ *    pair k (counted over the call) fills slots first_free + 2k (e+, tag 1)
+ *    and first_free + 2k + 1 (e-, tag 2) at one position (no net charge),
+ *    offsets uniform in the cell, isotropic Maxwell-Juttner momenta at T in
+ *    the local tetrad frame (as grpic_particles_init), the given weight,
+ *    phi = 0, previous position = position.  Pairs that would not fit below
+ *    P->n are not written (whole pairs only).  Random numbers: Philox4x32-10,
+ *    key seed, counter (index, call + 1, stream, attempt).
+ *  - The slots from first_free on must be empty (after grpic_sort they are
+ *    from its n_live on); first_free in [0, P->n].
+ *  - If n_injected is non-null, waits for the stream and stores the number of
+ *    pairs written.
+ *  - Uses the context's scratch: the cell sort's counters and one FP64 value
+ *    per cell, allocated by the first call (GRPIC_ENOMEM if that fails).
+ *    Calls on one context must not overlap on different streams. */
+grpic_status grpic_inject_pairs(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,
+                                const grpic_inject_params* params, int64_t first_free,
+                                int64_t* n_injected, void* stream);
+
 /* Diagnostics (Sec. 2.3 conserved E, L at the time-centred position, the
  * midpoint of the previous position recorded by the last grpic_push and the
  * current one; Gauss's law Sec. 3.2).  E_out, L_out: optional device arrays of P->n reals (NaN for

@@ -12,6 +12,7 @@
 #include "grpic.h"
 #include "adjoint.hpp"
 #include "diag.hpp"
+#include "inject.hpp"
 #include "sort.hpp"
 
 using namespace grpic;
@@ -28,6 +29,7 @@ struct grpic_ctx {
   int* sort_off;   // n_cells + 1 counts / offsets, then block sums, then n_live
   int* sort_sums;
   int* sort_live;
+  double* inj_w;   // per-cell e+- weight of the pair injection (allocated on first use)
 };
 
 namespace grpic {
@@ -386,6 +388,33 @@ grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t sta
 }
 
 template <class T>
+grpic_status inject_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, const InjectArgs& a,
+                         hipStream_t s) {
+  const Grid& g = c->g;
+  const int64_t ncell = (int64_t)g.n_r * g.n_th, nkeys = ncell + 1;
+  const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(fill_kernel<double>, dim3(blocks(ncell)), dim3(kB), 0, s, ncell, c->inj_w, 0.0);
+  LAUNCH_CHECK("fill");
+  if (P->n > 0) {
+    hipLaunchKernelGGL(inject_weights_kernel<T>, dim3(blocks(P->n)), dim3(kB), 0, s, g, arrays<T>(P), c->inj_w);
+    LAUNCH_CHECK("inject_weights");
+  }
+  hipLaunchKernelGGL(inject_cells_kernel<T>, dim3(blocks(nkeys)), dim3(kB), 0, s, g, c->tab, (const T*)F->B[0],
+                     (const T*)F->B[1], (const T*)F->B[2], (const double*)c->inj_w, a, c->sort_off);
+  LAUNCH_CHECK("inject_cells");
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, c->sort_off, nkeys, c->sort_sums);
+  LAUNCH_CHECK("scan_blocks");
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, c->sort_sums, nb);
+  LAUNCH_CHECK("scan_sums");
+  hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, c->sort_off, nkeys, c->sort_sums);
+  LAUNCH_CHECK("scan_add");
+  hipLaunchKernelGGL(inject_pairs_kernel<T>, dim3(blocks(ncell)), dim3(kB), 0, s, g, arrays<T>(P),
+                     (const int*)c->sort_off, a);
+  LAUNCH_CHECK("inject_pairs");
+  return GRPIC_OK;
+}
+
+template <class T>
 grpic_status diagnostics_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, double B0,
                               void* E_out, void* L_out, void* gauss_res, hipStream_t s) {
   const Grid& g = c->g;
@@ -623,6 +652,7 @@ grpic_status grpic_destroy(grpic_ctx* c) {
   (void)hipFree(c->tables);
   (void)hipFree(c->acc);
   (void)hipFree(c->sort_off);
+  if (c->inj_w) (void)hipFree(c->inj_w);
   delete c;
   return GRPIC_OK;
 }
@@ -730,6 +760,53 @@ grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_pa
     HIP_TRY(hipMemcpyAsync(&h, c->sort_live, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *n_live = h;
+  }
+  return GRPIC_OK;
+}
+
+grpic_status grpic_inject_pairs(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P,
+                                const grpic_inject_params* ip, int64_t first_free, int64_t* n_injected,
+                                void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
+  if (!ip) return fail(GRPIC_EINVAL, "null injection parameters");
+  if (!(ip->sigma_th > 0.0 && std::isfinite(ip->sigma_th))) return fail(GRPIC_EINVAL, "sigma_th must be > 0");
+  if (!(ip->temperature > 0.0 && std::isfinite(ip->temperature)))
+    return fail(GRPIC_EINVAL, "temperature must be > 0");
+  if (!std::isfinite(ip->weight)) return fail(GRPIC_EINVAL, "weight must be finite");
+  if (ip->n_pairs < 0) return fail(GRPIC_EINVAL, "n_pairs must be >= 0");
+  if (ip->reserved != 0) return fail(GRPIC_EINVAL, "reserved must be 0");
+  if (ip->call == 0xFFFFFFFFu) return fail(GRPIC_EINVAL, "call must be below 2^32 - 1");
+  if (first_free < 0 || first_free > P->n) return fail(GRPIC_EINVAL, "first_free %lld outside [0, %lld]",
+                                                      (long long)first_free, (long long)P->n);
+  const Grid& g = c->g;
+  const int64_t ncell = (int64_t)g.n_r * g.n_th;
+  if ((int64_t)ip->n_pairs * ncell > INT_MAX) return fail(GRPIC_EINVAL, "n_pairs times the cells exceeds 2^31 - 1");
+  if (P->n > 0xFFFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^32 slots");
+  if (!c->inj_w) {
+    hipError_t e = hipMalloc(&c->inj_w, (size_t)ncell * sizeof(double));
+    if (e != hipSuccess) {
+      c->inj_w = nullptr;
+      return fail(GRPIC_ENOMEM, "injection scratch allocation: %s", hipGetErrorString(e));
+    }
+  }
+  InjectArgs a;
+  a.sigma_th = ip->sigma_th;
+  a.temp = ip->temperature;
+  a.weight = ip->weight;
+  a.n_pairs = ip->n_pairs;
+  a.i_lo = std::max(ip->i_lo, 0);
+  a.i_hi = std::min(ip->i_hi, g.n_r);
+  a.seed = ip->seed;
+  a.sub = ip->call + 1u;
+  a.first_free = first_free;
+  hipStream_t s = S(stream);
+  if ((st = c->f32 ? inject_impl<float>(c, F, P, a, s) : inject_impl<double>(c, F, P, a, s))) return st;
+  if (n_injected) {
+    int total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, c->sort_off + ncell, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_injected = std::min<int64_t>(total, (P->n - first_free) / 2);
   }
   return GRPIC_OK;
 }

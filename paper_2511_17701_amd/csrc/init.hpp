@@ -26,11 +26,12 @@ __host__ __device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) 
   }
 }
 
-// counter (index, 0, stream, attempt), key = seed
+// counter (index, sub, stream, attempt), key = seed; sub = 0 for the initial
+// loading, 1 + call for the pair-injection call `call`
 __device__ inline void draw4(uint64_t seed, uint32_t idx, uint32_t stream, uint32_t k,
-                             uint32_t out[4]) {
+                             uint32_t out[4], uint32_t sub = 0u) {
   out[0] = idx;
-  out[1] = 0u;
+  out[1] = sub;
   out[2] = stream;
   out[3] = k;
   philox(out, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -44,18 +45,19 @@ __device__ inline double u_low(uint32_t w) { return (double)w * 0x1p-32; }      
 // rejection method (as given by Zenitani 2015): u = -T ln(X1 X2 X3),
 // eta = -T ln(X1 X2 X3 X4), accept when eta^2 - u^2 > 1; direction from two
 // further uniforms.
-__device__ inline void maxwell_juttner(uint64_t seed, uint32_t q, double T, double uh[3]) {
+__device__ inline void maxwell_juttner(uint64_t seed, uint32_t q, double T, double uh[3],
+                                       uint32_t sub = 0u) {
   double u = 0.0;
   for (uint32_t k = 0; k < 4096u; ++k) {
     uint32_t w[4];
-    draw4(seed, q, 1u, k, w);
+    draw4(seed, q, 1u, k, w, sub);
     const double x123 = u_open0(w[0]) * u_open0(w[1]) * u_open0(w[2]);
     u = -T * log(x123);
     const double eta = -T * log(x123 * u_open0(w[3]));
     if (eta * eta - u * u > 1.0) break;
   }
   uint32_t w[4];
-  draw4(seed, q, 2u, 0u, w);
+  draw4(seed, q, 2u, 0u, w, sub);
   const double x5 = u_mid(w[0]), x6 = u_mid(w[1]);
   const double st = 2.0 * u * sqrt(x5 * (1.0 - x5));
   double sn, cs;
@@ -110,7 +112,8 @@ __device__ inline double x2_of_theta(const Grid& g, double th) {
 
 template <class T>
 __device__ inline void store_particle(ParticleArraysT<T>& P, int64_t q, int i1, int i2, double dx1,
-                                      double dx2, double u1, double u2, double u3, uint8_t tag) {
+                                      double dx2, double u1, double u2, double u3, uint8_t tag,
+                                      double w = 1.0) {
   P.i1[q] = i1;
   P.i2[q] = i2;
   P.dx1[q] = dx1;
@@ -122,7 +125,7 @@ __device__ inline void store_particle(ParticleArraysT<T>& P, int64_t q, int i1, 
   P.u1[q] = u1;
   P.u2[q] = u2;
   P.u3[q] = u3;
-  P.w[q] = 1.0;
+  P.w[q] = w;
   P.phi[q] = 0.0;
   P.tag[q] = tag;
 }

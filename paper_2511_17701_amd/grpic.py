@@ -61,6 +61,12 @@ class Particles(ctypes.Structure):
                 ("dx1p", c_void_p), ("dx2p", c_void_p), ("tag", c_void_p)]
 
 
+class InjectParams(ctypes.Structure):
+    _fields_ = [("sigma_th", c_double), ("temperature", c_double), ("weight", c_double),
+                ("n_pairs", c_int32), ("i_lo", c_int32), ("i_hi", c_int32), ("reserved", c_int32),
+                ("seed", c_uint64), ("call", ctypes.c_uint32)]
+
+
 class Diag(ctypes.Structure):
     _fields_ = [("n_alive", c_int64 * 4), ("n_leaving", c_int64), ("n_empty", c_int64),
                 ("n_nonfinite", c_int64), ("sum_E", c_double * 4), ("sum_L", c_double * 4),
@@ -84,6 +90,8 @@ _sigs = {
                            c_int32),
     "grpic_field_advance": ([c_void_p, _F, c_int32, c_void_p], c_int32),
     "grpic_sort": ([c_void_p, _PP, _PP, POINTER(c_int64), c_void_p], c_int32),
+    "grpic_inject_pairs": ([c_void_p, _F, _PP, POINTER(InjectParams), c_int64, POINTER(c_int64),
+                            c_void_p], c_int32),
     "grpic_diagnostics": ([c_void_p, _F, _PP, c_double, POINTER(Diag), c_void_p, c_void_p,
                            c_void_p, c_void_p], c_int32),
 }
@@ -249,6 +257,21 @@ class Context:
         _check(_lib.grpic_sort(self._h, ctypes.byref(self._particles(P)),
                                ctypes.byref(self._particles(Q)),
                                ctypes.byref(n) if count else None, _stream()), "grpic_sort")
+        return n.value if count else None
+
+    def inject_pairs(self, F: torch.Tensor, P: dict, sigma_th: float, temperature: float,
+                     n_pairs: int, weight: float, i_lo: int, i_hi: int, seed: int, call: int,
+                     first_free: int, count: bool = True):
+        """grpic_inject_pairs: pairs where sigma >= sigma_th into the slots of P
+        from first_free on; returns the number written when count is True
+        (waits for the stream)."""
+        ip = InjectParams(sigma_th=sigma_th, temperature=temperature, weight=weight,
+                          n_pairs=n_pairs, i_lo=i_lo, i_hi=i_hi, reserved=0, seed=seed, call=call)
+        n = c_int64(0)
+        _check(_lib.grpic_inject_pairs(self._h, ctypes.byref(self._fields(F)),
+                                       ctypes.byref(self._particles(P)), ctypes.byref(ip),
+                                       int(first_free), ctypes.byref(n) if count else None,
+                                       _stream()), "grpic_inject_pairs")
         return n.value if count else None
 
     def diagnostics(self, F: torch.Tensor, P: dict, B0: float, per_particle: bool = False,
