@@ -46,9 +46,10 @@ FUSED_BYTES = {"fp64": 65 + 57, "fp32": 37 + 33}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2_512")
+    ap.add_argument("--workload", default="c5_4096")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
                     help="storage precision (default: the workload's)")
     ap.add_argument("--unfused", action="store_true",
@@ -60,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle steps of the CPU baseline (0: 8, or 2 above 2^23 particles)")
+    ap.add_argument("--cpu-single-pairs", type=int, default=1 << 15,
+                    help="pairs of the single-thread oracle figure (0: skip it)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the timing of the other precision form")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -136,37 +139,80 @@ def profile_figures(name):
     return out
 
 
+def cpu_model():
+    """The host CPU's model name and logical CPU count (as /proc/cpuinfo states them)."""
+    model, n = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    n += 1
+    except OSError:
+        pass
+    return model, n
+
+
 def cpu_baseline(w, dt):
     """The oracle (FP64 C, OpenMP over particles) timed on the host cores on a
-    bounded sample of the workload: `cpu_steps` full steps (8; 2 above 2^23
-    particles); workloads above 2^23 particles keep their grid and fields but
-    load 2^22 pairs in uniformly drawn cells."""
+    bounded sample of the workload.
+
+    Grids up to 2^20 cells: `cpu_steps` full PIC steps (8) of the whole
+    particle set (2^22 pairs in uniformly drawn cells above 2^23 particles).
+    Larger grids: the oracle's field stages alone take minutes per step there
+    (its field loops are serial), so the sample is the metric's own work,
+    gather + push + deposit, of 2^21 pairs in uniformly drawn cells for
+    `cpu_steps` steps (2) in the workload's initial fields.  A second figure
+    runs the same sample kind on one thread with `cpu_single_pairs` pairs."""
     import oracle as O
     prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, dt, n_iter=w.n_iter,
                         small_angle=w.small_angle, charge_scale=w.charge_scale,
                         n_filter=w.n_filter, n_absorb=w.n_absorb, r0=w.r0, h0=w.h0)
     F = O.fields_init_monopole(prm, w.B0) if w.init == "monopole" else O.fields_init_wald(prm, w.B0)
-    big = w.n_particles > 2 ** 23
-    if big:
-        P = O.particles_init(prm, 2 ** 22, 0, w.T, w.n_geo, w.seed)
-    else:
-        P = O.particles_init(prm, w.n_pairs_total if w.ppc == 0 else 0, w.ppc, w.T, w.n_geo,
-                             w.seed)
-    n = int((P["tag"] != 0).sum())
-    steps = ARGS.cpu_steps or (8 if not big else 2)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        if w.full_step:
-            O.step(prm, F, P)
+    big_grid = w.n_r * w.n_th > 2 ** 20
+    full = w.full_step and not big_grid
+
+    def sample(n_pairs, steps, threads):
+        if n_pairs is None:
+            P = O.particles_init(prm, w.n_pairs_total if w.ppc == 0 else 0, w.ppc, w.T, w.n_geo,
+                                 w.seed)
         else:
-            O.push(prm, F, P)
-            O.deposit(prm, F, P)
-    t = time.perf_counter() - t0
-    what = f"{n} particles ({'2^22 pairs in uniformly drawn cells' if big else 'all'})"
-    return {"value": n * steps / t, "unit": "particle pushes/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} full FP64 steps of the {w.name} workload ({w.n_r}x{w.n_th} grid, "
-                      f"{what}), {t:.1f} s"}
+            P = O.particles_init(prm, n_pairs, 0, w.T, w.n_geo, w.seed)
+        n = int((P["tag"] != 0).sum())
+        Fs = F.copy()
+        O.set_num_threads(threads)
+        used = O.num_threads()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            if full:
+                O.step(prm, Fs, P)
+            else:
+                O.push(prm, Fs, P)
+                O.deposit(prm, Fs, P)
+        return n * steps / (time.perf_counter() - t0), n, time.perf_counter() - t0, used
+
+    host_threads = O.num_threads()
+    if big_grid:
+        n_pairs, steps = 2 ** 21, ARGS.cpu_steps or 2
+    elif w.n_particles > 2 ** 23:
+        n_pairs, steps = 2 ** 22, ARGS.cpu_steps or 2
+    else:
+        n_pairs, steps = None, ARGS.cpu_steps or 8
+    value, n, t, used = sample(n_pairs, steps, host_threads)
+    kind = "full FP64 PIC steps" if full else "FP64 gather + push + deposit passes (no field stages)"
+    what = f"{n} particles ({'all' if n_pairs is None else f'{n_pairs} pairs in uniformly drawn cells'})"
+    model, logical = cpu_model()
+    out = {"value": value, "unit": "particle pushes/s", "cores": used, "kind": "oracle",
+           "sample": f"{steps} {kind} of the {w.name} workload ({w.n_r}x{w.n_th} grid, {what}), "
+                     f"{t:.1f} s",
+           "cpu_model": model, "host_logical_cpus": logical}
+    if ARGS.cpu_single_pairs > 0:
+        v1, n1, t1, _ = sample(ARGS.cpu_single_pairs, 1, 1)
+        out["single_thread"] = {"value": v1, "unit": "particle pushes/s", "cores": 1,
+                                "sample": f"1 {'full FP64 PIC step' if full else 'FP64 gather + push + deposit pass'}"
+                                          f" of {n1} particles in uniformly drawn cells, {t1:.1f} s"}
+    O.set_num_threads(host_threads)
+    return out
 
 
 def copy_calibration():
@@ -274,6 +320,8 @@ def main():
     from paper_2511_17701_amd.workloads import WORKLOADS
 
     w = WORKLOADS[ARGS.workload]
+    if ARGS.steps is None:
+        ARGS.steps = w.steps
     precision = ARGS.precision or w.precision
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
@@ -285,10 +333,11 @@ def main():
     kname = "push" if ARGS.unfused else "push_deposit"
 
     figs = profile_figures(f"{kname}_{w.name}_{precision}_pmc.txt")
-    flops_pp = float(figs["flops_per_particle"]) if "flops_per_particle" in figs else None
+    current = figs.get("source_sha256") == source_hash()
+    flops_pp = float(figs["flops_per_particle"]) if current and "flops_per_particle" in figs else None
     achieved = flops_pp * live / (k1 * 1e-3) / 1e12 if flops_pp else None
     traffic = None
-    if figs.get("source_sha256") == source_hash() and "hbm_bytes_per_particle" in figs:
+    if current and "hbm_bytes_per_particle" in figs:
         traffic = float(figs["hbm_bytes_per_particle"]) * live
     gbs = FUSED_BYTES[precision] * live / (k1 * 1e-3) / 1e9
     roofline = {
@@ -297,9 +346,17 @@ def main():
         "frac": achieved / PEAK_VECTOR_TFLOPS if achieved else None,
         "traffic": traffic, "avg_launch_ms": k1, "particles_per_launch": live,
         "flops_per_particle": flops_pp,
+        "frac_basis": "FLOPs are the counted VALU lane slots of the kernel (wave instructions x 64, "
+                      "FMA = 2), lanes masked off in divergent iterations included",
         "peak_basis": "256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz: FP64 and non-packed FP32 "
                       "vector issue (packed FP32, the chip's 157.3 TFLOP/s, is not used by this code)",
     }
+    if current and "valu_instructions_per_particle" in figs:
+        # a wave64 VALU instruction occupies its SIMD (16 lanes) for 4 cycles
+        vi = float(figs["valu_instructions_per_particle"])
+        cycles = vi * live / 64.0 * 4.0
+        roofline["valu_issue"] = {"instructions_per_particle": vi,
+                                  "frac_of_issue_cycles": cycles / (1024 * 2.4e9 * k1 * 1e-3)}
     if not ARGS.unfused:
         roofline["hbm_view"] = {"algorithmic_bytes_per_particle": FUSED_BYTES[precision],
                                 "GB_per_s": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}

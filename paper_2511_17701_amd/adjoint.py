@@ -1,7 +1,9 @@
 """Differentiable frozen-field particle push (the differentiation form).
 
 `FrozenFieldPush.apply(u0, B0, run)` advances particles `run.steps` push
-steps (grpic_push) in the frozen field B0 * F1 and returns their final state
+steps (grpic_push) in the frozen initial field of amplitude B0 (the Wald
+field, or the monopole field of the BZ test, built by the library's
+grpic_fields_init_* call for that B0) and returns their final state
 (x1, x2, u1, u2, u3) as an (n, 5) float64 tensor, x = cell + offset.  Its
 backward is the adjoint sweep: the forward pass keeps the particle state
 every `run.every` steps (checkpoints); the backward pass replays each segment
@@ -28,11 +30,22 @@ STATE_KEYS = ("i1", "i2", "dx1", "dx2", "u1", "u2", "u3", "w", "phi", "i1p", "i2
 class FrozenRun:
     """What the differentiable push needs besides (u0, B0)."""
     ctx: "grpic.Context"       # FP64 context; n_iter large enough for the fixed points
-    F1: torch.Tensor           # unit-amplitude field set (planes D and B0 are read)
     start: dict                # particle arrays; u1..u3 are replaced by u0
     steps: int
     every: int = 10
+    init: str = "wald"         # initial field: "wald" or "monopole" (linear in B0)
     stats: dict = field(default_factory=dict)
+
+    def fields(self, b0: float) -> torch.Tensor:
+        """The frozen field set of amplitude b0, built by libgrpic."""
+        F = self.ctx.new_fields(self.start["u1"].device)
+        if self.init == "wald":
+            self.ctx.fields_init_wald(F, b0)
+        elif self.init == "monopole":
+            self.ctx.fields_init_monopole(F, b0)
+        else:
+            raise ValueError(f"unknown initial field {self.init!r}")
+        return F
 
 
 def _copy(P):
@@ -50,7 +63,7 @@ class FrozenFieldPush(torch.autograd.Function):
         if u0.dtype != torch.float64 or u0.dim() != 2 or u0.shape[1] != 3:
             raise ValueError("u0 must be an (n, 3) float64 tensor")
         b0 = float(B0)
-        F = run.F1 * b0
+        F = run.fields(b0)
         P = _copy(run.start)
         P["u1"], P["u2"], P["u3"] = (u0[:, c].contiguous().clone() for c in range(3))
         checkpoints = []

@@ -54,7 +54,7 @@ def gpu_gradients(w, ctx, F1, P, steps, every=10):
     from paper_2511_17701_amd.adjoint import FrozenFieldPush, FrozenRun
     u0 = torch.stack([P["u1"], P["u2"], P["u3"]], 1).clone().requires_grad_(True)
     B0 = torch.tensor(w.B0, dtype=torch.float64, requires_grad=True)
-    run = FrozenRun(ctx, F1, P, steps, every)
+    run = FrozenRun(ctx, P, steps, every)
     out = FrozenFieldPush.apply(u0, B0, run)
     loss = loss_of(w, out)
     loss.backward()
@@ -104,7 +104,8 @@ def forward_loss(w, ctx, F1, P, u0, B0, steps):
     from paper_2511_17701_amd.adjoint import final_state
     Q = {k: v.clone() for k, v in P.items()}
     Q["u1"], Q["u2"], Q["u3"] = (u0[:, c].contiguous().clone() for c in range(3))
-    F = F1 * B0
+    F = ctx.new_fields()
+    ctx.fields_init_wald(F, B0)
     h = torch.zeros_like(Q["i1"], dtype=torch.int64)
     axis = (Q["i2"] == 0) | (Q["i2"] == w.n_th - 1)
     for s in range(steps):

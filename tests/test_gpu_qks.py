@@ -194,7 +194,7 @@ def test_qks_adjoint_matches_reference_gradient(O, G):
     steps = 10
     u0 = torch.stack([P["u1"], P["u2"], P["u3"]], 1).clone().requires_grad_(True)
     B0 = torch.tensor(w.B0, dtype=torch.float64, requires_grad=True)
-    run = FrozenRun(ctx, F1, P, steps, 5)
+    run = FrozenRun(ctx, P, steps, 5)
     out = FrozenFieldPush.apply(u0, B0, run)
     dxi = math.log((w.r_max - QKS["r0"]) / (w.r_min - QKS["r0"])) / 24
     loss = (out[:, 2] / (dxi * (w.r_min - QKS["r0"]) * torch.exp(out[:, 0] * dxi))).mean()
