@@ -243,6 +243,24 @@ grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t 
 grpic_status grpic_sort(grpic_ctx* ctx, const grpic_particles* src, const grpic_particles* dst,
                         int64_t* n_live, void* stream);
 
+/* grpic_sort for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sort, with the same kernels and results, whose scratch is a static
+ * device array of the library instead of the context's (no hipMalloc, no
+ * hipFree, no allocating library call).
+ *  - Limit: grids of at most 2^24 cells (4096 x 4096); larger grids return
+ *    GRPIC_EINVAL before anything is enqueued.  The array (2^24 + 16387 ints,
+ *    64.1 MiB) is held on every GPU the library runs on until the process
+ *    ends.
+ *  - Every call on one GPU uses that GPU's one array: calls that overlap on
+ *    one GPU (several streams, threads or contexts) race.  The counters are
+ *    cleared by the call itself.
+ *  - n_live_device: optional device int32; receives the number of live slots
+ *    (enqueued, no wait), so the call never synchronises the stream.
+ * Arguments and errors otherwise as grpic_sort. */
+grpic_status grpic_sort_noalloc(grpic_ctx* ctx, const grpic_particles* src, const grpic_particles* dst,
+                                int32_t* n_live_device, void* stream);
+
 /* Parameters of grpic_inject_pairs. */
 typedef struct {
   double sigma_th;      /* magnetisation threshold (the paper's runs: 1000 and

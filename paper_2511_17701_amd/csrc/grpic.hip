@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "grpic.h"
@@ -30,7 +31,18 @@ struct grpic_ctx {
   int* sort_sums;
   int* sort_live;
   double* inj_w;   // per-cell e+- weight of the pair injection (allocated on first use)
+  int* static_scratch;  // this device's address of `scratch` (grpic_sort_noalloc)
 };
+
+// Scratch of grpic_sort_noalloc, which allocates nothing: the cell counters /
+// offsets of grids of up to kStaticSortCells cells, the scan's block sums and
+// the live count (kStaticSortInts ints, 64.1 MiB).  Every GPU the library runs
+// on holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress gives on that device.
+constexpr int64_t kStaticSortCells = (int64_t)1 << 24;  // 4096 x 4096
+constexpr int64_t kStaticSortKeys = kStaticSortCells + 1;
+constexpr int64_t kStaticSortInts = kStaticSortKeys + (kStaticSortKeys + grpic::kScanBlock - 1) / grpic::kScanBlock + 1;
+static __device__ __align__(256) int scratch[kStaticSortInts];
 
 namespace grpic {
 __global__ void fill_int_kernel(int64_t n, int* __restrict__ p, int v) {
@@ -319,25 +331,77 @@ grpic_status deposit_impl(grpic_ctx* c, const grpic_particles* P, const grpic_fi
   return GRPIC_OK;
 }
 
+// Device scratch of one sort: n_cells + 1 counters / offsets, the scan's
+// block sums, the live count.
+struct SortScratch {
+  int* off;
+  int* sums;
+  int* live;
+};
+
 template <class T>
-grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst, hipStream_t s) {
+grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst, const SortScratch& w,
+                       hipStream_t s) {
   const Grid& g = c->g;
   const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
   const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
   const ParticleArraysT<T> a = arrays<T>(src), b = arrays<T>(dst);
   const dim3 gsort((unsigned)((src->n + (int64_t)kB * kSortPer - 1) / ((int64_t)kB * kSortPer)));
-  hipLaunchKernelGGL(sort_count_kernel<T>, gsort, dim3(kB), 0, s, g, a, c->sort_off);
+  hipLaunchKernelGGL(sort_count_kernel<T>, gsort, dim3(kB), 0, s, g, a, w.off);
   LAUNCH_CHECK("sort_count");
-  hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, c->sort_off, nkeys, c->sort_sums);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, w.off, nkeys, w.sums);
   LAUNCH_CHECK("scan_blocks");
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, c->sort_sums, nb);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, w.sums, nb);
   LAUNCH_CHECK("scan_sums");
-  hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, c->sort_off, nkeys, c->sort_sums);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, w.off, nkeys, w.sums);
   LAUNCH_CHECK("scan_add");
-  hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, c->sort_off + (nkeys - 1), c->sort_live);
+  hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, w.off + (nkeys - 1), w.live);
   LAUNCH_CHECK("copy_int");
-  hipLaunchKernelGGL(sort_scatter_kernel<T>, gsort, dim3(kB), 0, s, g, a, b, c->sort_off);
+  hipLaunchKernelGGL(sort_scatter_kernel<T>, gsort, dim3(kB), 0, s, g, a, b, w.off);
   LAUNCH_CHECK("sort_scatter");
+  return GRPIC_OK;
+}
+
+// Argument checks and the launch sequence of a sort into the given scratch
+// (counters cleared by a fill kernel first).
+grpic_status sort_run(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst, const SortScratch& w,
+                      hipStream_t s) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_particles(src)) || (st = check_particles(dst))) return st;
+  if (src->n != dst->n) return fail(GRPIC_EINVAL, "source has %lld slots, destination %lld",
+                                    (long long)src->n, (long long)dst->n);
+  if (src->n > 0x7FFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^31 - 1 slots");
+  if (src->n > 0 && (src->tag == dst->tag || src->u1 == dst->u1))
+    return fail(GRPIC_EINVAL, "source and destination must not alias");
+  const Grid& g = c->g;
+  const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, nkeys, w.off, 0);
+  LAUNCH_CHECK("fill_int");
+  if (src->n > 0) {
+    if ((st = c->f32 ? sort_impl<float>(c, src, dst, w, s) : sort_impl<double>(c, src, dst, w, s))) return st;
+  } else {
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, (int64_t)1, w.live, 0);
+    LAUNCH_CHECK("fill_int");
+  }
+  return GRPIC_OK;
+}
+
+// This device's address of `scratch`, looked up once per device (with that
+// device current) and kept for the process.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_ptr[kMaxDevices] = {};
+
+grpic_status static_scratch_of(int device, int** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return fail(GRPIC_EINVAL, "device %d out of range", device);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(GRPIC_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<int*>(p);
+  }
+  *out = g_scratch_ptr[device];
   return GRPIC_OK;
 }
 
@@ -561,6 +625,13 @@ grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   }
 
   hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) {
+    grpic_status sst = static_scratch_of(c->device, &c->static_scratch);
+    if (sst != GRPIC_OK) {
+      delete c;
+      return sst;
+    }
+  }
   const int nr = p->n_r + 2 * p->n_ghost, nt = p->n_th + 2 * p->n_ghost;
   // r, 1/(R deta); sin, cos, 1/sin, T = dtheta/dx2, deta/T (integer, half-integer)
   const size_t nt_all = 4 * (size_t)nr + 10 * (size_t)nt;
@@ -738,28 +809,34 @@ grpic_status grpic_push_adjoint(grpic_ctx* c, const grpic_fields* F, double B0, 
 grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst,
                         int64_t* n_live, void* stream) {
   grpic_status st;
-  if ((st = check_ctx(c)) || (st = check_particles(src)) || (st = check_particles(dst))) return st;
-  if (src->n != dst->n) return fail(GRPIC_EINVAL, "source has %lld slots, destination %lld",
-                                    (long long)src->n, (long long)dst->n);
-  if (src->n > 0x7FFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^31 - 1 slots");
-  if (src->n > 0 && (src->tag == dst->tag || src->u1 == dst->u1))
-    return fail(GRPIC_EINVAL, "source and destination must not alias");
-  const Grid& g = c->g;
   hipStream_t s = S(stream);
-  const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
-  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, nkeys, c->sort_off, 0);
-  LAUNCH_CHECK("fill_int");
-  if (src->n > 0) {
-    if ((st = c->f32 ? sort_impl<float>(c, src, dst, s) : sort_impl<double>(c, src, dst, s))) return st;
-  } else {
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, (int64_t)1, c->sort_live, 0);
-    LAUNCH_CHECK("fill_int");
-  }
+  if (!c) return fail(GRPIC_EINVAL, "null context");
+  if ((st = sort_run(c, src, dst, SortScratch{c->sort_off, c->sort_sums, c->sort_live}, s))) return st;
   if (n_live) {
     int h = 0;
     HIP_TRY(hipMemcpyAsync(&h, c->sort_live, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *n_live = h;
+  }
+  return GRPIC_OK;
+}
+
+grpic_status grpic_sort_noalloc(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst,
+                                int32_t* n_live_device, void* stream) {
+  grpic_status st;
+  if (!c) return fail(GRPIC_EINVAL, "null context");
+  const int64_t ncell = (int64_t)c->g.n_r * c->g.n_th;
+  if (ncell > kStaticSortCells)
+    return fail(GRPIC_EINVAL, "grid of %lld cells exceeds the static sort scratch (%lld cells)", (long long)ncell,
+                (long long)kStaticSortCells);
+  int* base = c->static_scratch;
+  const int64_t nkeys = ncell + 1;
+  const int64_t nb = (nkeys + kScanBlock - 1) / kScanBlock;
+  hipStream_t s = S(stream);
+  if ((st = sort_run(c, src, dst, SortScratch{base, base + nkeys, base + nkeys + nb}, s))) return st;
+  if (n_live_device) {
+    hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, (const int*)(base + nkeys + nb), n_live_device);
+    LAUNCH_CHECK("copy_int");
   }
   return GRPIC_OK;
 }

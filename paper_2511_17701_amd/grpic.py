@@ -90,6 +90,7 @@ _sigs = {
                            c_int32),
     "grpic_field_advance": ([c_void_p, _F, c_int32, c_void_p], c_int32),
     "grpic_sort": ([c_void_p, _PP, _PP, POINTER(c_int64), c_void_p], c_int32),
+    "grpic_sort_noalloc": ([c_void_p, _PP, _PP, c_void_p, c_void_p], c_int32),
     "grpic_inject_pairs": ([c_void_p, _F, _PP, POINTER(InjectParams), c_int64, POINTER(c_int64),
                             c_void_p], c_int32),
     "grpic_diagnostics": ([c_void_p, _F, _PP, c_double, POINTER(Diag), c_void_p, c_void_p,
@@ -258,6 +259,17 @@ class Context:
                                ctypes.byref(self._particles(Q)),
                                ctypes.byref(n) if count else None, _stream()), "grpic_sort")
         return n.value if count else None
+
+    def sort_noalloc(self, P: dict, Q: dict, n_live=None):
+        """grpic_sort_noalloc: the cell sort of P into Q with the library's
+        static scratch; n_live: optional int32 device tensor of one element
+        that receives the number of live slots (no wait)."""
+        if n_live is not None and (n_live.dtype != torch.int32 or not n_live.is_cuda):
+            raise ValueError("n_live must be an int32 device tensor")
+        _check(_lib.grpic_sort_noalloc(self._h, ctypes.byref(self._particles(P)),
+                                       ctypes.byref(self._particles(Q)),
+                                       c_void_p(n_live.data_ptr() if n_live is not None else 0),
+                                       _stream()), "grpic_sort_noalloc")
 
     def inject_pairs(self, F: torch.Tensor, P: dict, sigma_th: float, temperature: float,
                      n_pairs: int, weight: float, i_lo: int, i_hi: int, seed: int, call: int,
