@@ -139,10 +139,13 @@ def test_inject_keeps_gauss(O, G):
     Pg, Fg = up(P), up({"F": F})["F"]
     d0 = ctx.diagnostics(Fg, Pg, w.B0, gauss_plane=True)
     R0 = d0["gauss_res"].clone()
-    k = ctx.inject_pairs(Fg, Pg, 1e300, 0.5, 1, 1.0, 0, 32, 1, 0, n0)
-    assert k == 0                               # nothing reaches sigma = 1e300 but empty cells
-    k = ctx.inject_pairs(Fg, Pg, threshold(O, prm, F, P, 0.5), 0.5, 1, 1.0, 0, 32, 1, 0, n0)
-    assert k > 50
+    # sigma = 1e300: only the empty magnetised cells (sigma = infinity) inject
+    k1 = ctx.inject_pairs(Fg, Pg, 1e300, 0.5, 1, 1.0, 0, 32, 1, 0, n0)
+    assert k1 == int(np.isinf(O.magnetisation(prm, F, P)).sum()) > 0
+    k2 = ctx.inject_pairs(Fg, Pg, threshold(O, prm, F, P, 0.5), 0.5, 1, 1.0, 0, 32, 1, 1,
+                          n0 + 2 * k1)
+    assert k2 > 50
+    k = k1 + k2
     d1 = ctx.diagnostics(Fg, Pg, w.B0, gauss_plane=True)
     assert d1["n_alive"][1] - d0["n_alive"][1] == k and d1["n_alive"][2] - d0["n_alive"][2] == k
     dR = (d1["gauss_res"] - R0).abs().max().item()
