@@ -64,7 +64,9 @@ def parse():
     ap.add_argument("--cpu-single-pairs", type=int, default=1 << 15,
                     help="pairs of the single-thread oracle figure (0: skip it)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the timing of the other precision form")
+                    help="skip the timing of the other precision form and of the adjoint")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the differentiation form (the adjoint leg) and exit")
     ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
 
@@ -306,6 +308,56 @@ class Run:
         return total / steps, k1, k2, live0, sum(d1["n_alive"])
 
 
+def adjoint_leg(grpic, dev):
+    """The differentiation form on its workload (C4: 256^2, a = 0.9, 10^6
+    particles, frozen Wald field, 50 push steps, checkpoints every 10): the
+    forward pass (grpic_push) and the adjoint sweep (the replay of each
+    segment plus one grpic_push_adjoint per step) timed with HIP events on the
+    launch stream, and the adjoint kernel alone."""
+    import torch
+    from paper_2511_17701_amd.adjoint import FrozenFieldPush, FrozenRun
+    from paper_2511_17701_amd.workloads import WORKLOADS
+    w = WORKLOADS["c4_256"]
+    ctx = grpic.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, cfl=w.cfl, n_iter=w.n_iter,
+                        small_angle=w.small_angle)
+    P = ctx.new_particles(2 * w.n_pairs, dev)
+    ctx.particles_init(P, w.n_pairs, 0, w.T, 0, w.seed)
+    run = FrozenRun(ctx, P, w.steps, 10)
+    he = HipEvents()
+    ev = [he.create() for _ in range(3)]
+    u0 = torch.stack([P["u1"], P["u2"], P["u3"]], 1).clone().requires_grad_(True)
+    B0 = torch.tensor(w.B0, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    he.record(ev[0])
+    out = FrozenFieldPush.apply(u0, B0, run)
+    he.record(ev[1])
+    out[:, 2].mean().backward()
+    he.record(ev[2])
+    torch.cuda.synchronize()
+    fwd, bwd = he.elapsed(ev[0], ev[1]), he.elapsed(ev[1], ev[2])
+    # the adjoint kernel alone, 10 launches from the final state
+    F = run.fields(w.B0)
+    n = P["tag"].numel()
+    g = torch.ones((5, n), dtype=torch.float64, device=dev)
+    gB = torch.zeros(n, dtype=torch.float64, device=dev)
+    ctx.push_adjoint(F, w.B0, P, g, g, gB)
+    torch.cuda.synchronize()
+    he.record(ev[0])
+    for _ in range(10):
+        ctx.push_adjoint(F, w.B0, P, g, g, gB)
+    he.record(ev[1])
+    torch.cuda.synchronize()
+    k_ms = he.elapsed(ev[0], ev[1]) / 10
+    for e in ev:
+        he.destroy(e)
+    return {"workload": w.name, "particles": n, "steps": w.steps, "checkpoint_every": 10,
+            "forward_ms": fwd, "backward_ms": bwd,
+            "gradient_particle_steps_per_s": n * w.steps / ((fwd + bwd) * 1e-3),
+            "adjoint_kernel_ms": k_ms, "adjoint_particles_per_s": n / (k_ms * 1e-3),
+            "accuracy": "tests/test_gpu_adjoint.py: adjoint against the oracle's reference gradient "
+                        "and against central differences on the full C4 workload"}
+
+
 def main():
     global ARGS
     ARGS = parse()
@@ -319,6 +371,10 @@ def main():
     from paper_2511_17701_amd import grpic
     from paper_2511_17701_amd.workloads import WORKLOADS
 
+    if ARGS.adjoint_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"differentiation": adjoint_leg(grpic, torch.device("cuda:0"))}), flush=True)
+        return
     w = WORKLOADS[ARGS.workload]
     if ARGS.steps is None:
         ARGS.steps = w.steps
@@ -398,11 +454,14 @@ def main():
             other: {"ms_per_step": ms2, "value": 0.5 * (a0 + a1) / (ms2 * 1e-3),
                     f"{kname}_ms": k12},
             "fp32_speedup_over_fp64": t64 / t32,
-            "fp32_accuracy": "checked by tests/test_gpu_fp32.py (100 steps, p99 momentum "
-                             "error <= 1e-5; Gauss drift <= 1e-6)",
-            "differentiation": "checked by tests/test_gpu_adjoint.py (C4: adjoint vs reference "
-                               "gradient and vs central differences, p99.9 <= 1e-6)"}
+            "fp32_accuracy": "tests/test_gpu_fullsize.py: C3 at 2048^2, 100 full steps against "
+                             "the FP64 form, every particle above 1e-5 attributed; C5 Gauss drift "
+                             "over 200 steps at 4096^2 <= 1e-6; tests/test_gpu_fp32_oracle.py: "
+                             "one step against the oracle",
+        }
         del r2
+        torch.cuda.empty_cache()
+        out["precision_forms"]["differentiation"] = adjoint_leg(grpic, dev)
         torch.cuda.empty_cache()
     if not ARGS.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, dt)

@@ -235,8 +235,9 @@ grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t 
  * slots of src into dst ordered by cell c = i1 * n_th + i2; empty slots and
  * slots with the leaving bit (already deposited) go last, emptied (tag 0).
  * The order of particles within one cell is unspecified.  The previous-
- * position arrays of dst are left as they were (call it after the deposit
- * that reads them, not between grpic_push and grpic_deposit).  src and dst must
+ * position arrays of dst are left as they were, and src's i1p is overwritten
+ * (it holds each slot's rank within its cell during the sort): call it after
+ * the deposit that reads them, not between grpic_push and grpic_deposit.  src and dst must
  * have the same n and must not alias.  If n_live is non-null, waits for the
  * stream and stores the number of live slots (they occupy dst[0 .. n_live)).
  * Uses scratch owned by the context (n_r n_th + 1 counters). */

@@ -218,10 +218,12 @@ __global__ void faraday_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> 
 // leaves there; the theta = pi cap has the opposite orientation.
 // kFinal (the last half of the step): the grid spans the whole plane, the
 // current is Ja alone, and the same pass takes X0 <- X before the update and
-// rotates the currents, Jb <- Ja and Ja <- 0, after it.
+// rotates the currents after it: Jb <- Ja, and the deposit's accumulator is
+// zeroed (Jclear, or Ja itself when Jclear is null: the filter leaves the
+// filtered current in the scratch set or in the accumulator).
 template <class T, bool kFinal, bool kQ>
 __global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H, TriT<T> Ja, TriT<T> Jb, double wa,
-                              double wb, double polar_k, TriT<T> X0) {
+                              double wb, double polar_k, TriT<T> X0, TriT<T> Jclear) {
   int i, j;
   if (kFinal) {
     const PlaneIdx q = plane_idx(g);
@@ -271,7 +273,7 @@ __global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       Jb.p[c][o] = Ja.p[c][o];
-      Ja.p[c][o] = 0.0;
+      (Jclear.p[0] ? Jclear.p[c] : Ja.p[c])[o] = 0.0;
     }
   }
 }
@@ -386,39 +388,122 @@ __device__ inline int axis_mirror(int j, int n, int hs) {
   return j;
 }
 
-// One binomial pass (1,2,1)/4 x (1,2,1)/4 of S into X (Sec. 3.3.4) over the
-// whole plane.  Ghost columns of S are read as their axis reflections
-// (parity par[c]) instead of being stored first; X receives the filtered
-// values for i in [1 - ng, n_r + ng - 2] on the evolved columns, the
-// reflections of S on its ghost columns, and S itself on the two outermost
-// rows.  Passes alternate between two plane sets.
+// The value one binomial pass (1,2,1)/4 x (1,2,1)/4 (Sec. 3.3.4) gives at
+// plane point (i, j) of a component of x2-staggering hs and axis parity par,
+// from the source values at(i', j'): ghost columns take the source's axis
+// reflection, the two outermost rows keep the source, every other point is
+// the stencil with its theta neighbours read as axis reflections where they
+// fall past an axis (so at() is only asked for evolved columns there).
+template <class T, class At>
+__device__ inline T filter_point(const Grid& g, int i, int j, int hs, double par, const At& at) {
+  const int n = g.n_th;
+  if (j < 0 || j > n - hs) return (T)(par * (double)at(i, axis_mirror(j, n, hs)));
+  if (i < 1 - g.ng || i > g.n_r + g.ng - 2) return at(i, j);
+  const int jm = axis_mirror(j - 1, n, hs), jp = axis_mirror(j + 1, n, hs);
+  const double pm = jm == j - 1 ? 1.0 : par, pp = jp == j + 1 ? 1.0 : par;
+  const double r0 = pm * (double)at(i - 1, jm) + 2.0 * (double)at(i - 1, j) + pp * (double)at(i - 1, jp);
+  const double r1 = pm * (double)at(i, jm) + 2.0 * (double)at(i, j) + pp * (double)at(i, jp);
+  const double r2 = pm * (double)at(i + 1, jm) + 2.0 * (double)at(i + 1, j) + pp * (double)at(i + 1, jp);
+  return (T)(0.0625 * (r0 + 2.0 * r1 + r2));
+}
+
+// One binomial pass of S into X over the whole plane (filter_point per
+// point).  Passes alternate between two plane sets.
 template <class T>
 __global__ void filter_kernel(Grid g, TriT<T> X, CTriT<T> S, int3 half2, int3 parity, int ncomp) {
   const PlaneIdx q = plane_idx(g);
   if (!q.ok) return;
-  const int i = q.i, j = q.j, n = g.n_th;
   const int hs[3] = {half2.x, half2.y, half2.z};
   const int ps[3] = {parity.x, parity.y, parity.z};
-  const int64_t o = ix(g, i, j), ld = g.ld;
-  const bool inner = i >= 1 - g.ng && i <= g.n_r + g.ng - 2;
+  const int64_t o = ix(g, q.i, q.j);
   for (int c = 0; c < ncomp; ++c) {
     const T* s = S.p[c];
-    const double par = (double)ps[c];
-    if (j < 0 || j > n - hs[c]) {
-      X.p[c][o] = (T)(par * (double)s[ix(g, i, axis_mirror(j, n, hs[c]))]);
-      continue;
-    }
-    if (!inner) {
-      X.p[c][o] = s[o];
-      continue;
-    }
-    const int jm = axis_mirror(j - 1, n, hs[c]), jp = axis_mirror(j + 1, n, hs[c]);
+    auto at = [&](int i, int j) -> T { return s[ix(g, i, j)]; };
+    X.p[c][o] = filter_point<T>(g, q.i, q.j, hs[c], (double)ps[c], at);
+  }
+}
+
+// Up to kFMaxPasses binomial passes of S into X in one launch.  A block
+// (64 x 4 threads) owns an output tile of kFTI rows x kFTJ plane columns and
+// stages it in LDS with a halo as wide as the number of passes (and, at the
+// far axis, the columns its ghost columns reflect).  Each pass runs in two
+// LDS sweeps, the theta sums of every row (pm S[j-1] + 2 S[j] + pp S[j+1],
+// FP64), then the radial combination (R[i-1] + 2 R[i] + R[i+1]) / 16 rounded
+// to T, exactly the arithmetic of filter_point; ghost columns take the axis
+// reflection and the two outermost plane rows are copied.  Points whose
+// neighbours lie outside the staged region are not computed: the stale values
+// at the region's edge move inwards by one point per pass, so after `passes`
+// passes the tile (at depth `passes`) is exact; at the plane's edges nothing
+// outside is needed.  X must not alias S (other blocks read S's halo).
+// n_ghost = 2.
+constexpr int kFTI = 32, kFTJ = 48, kFMaxPasses = 4;
+constexpr int kFLI = kFTI + 2 * kFMaxPasses, kFLJ = 64;  // kFTJ + 2 passes + 6 far-axis columns <= 64
+
+template <class T>
+__global__ void __launch_bounds__(256) filter_fused_kernel(Grid g, TriT<T> X, CTriT<T> S, int3 half2,
+                                                           int3 parity, int ncomp, int passes) {
+  __shared__ T buf[2][kFLI][kFLJ];
+  __shared__ double rs[kFLI][kFLJ];
+  const int hs3[3] = {half2.x, half2.y, half2.z};
+  const int ps3[3] = {parity.x, parity.y, parity.z};
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int n = g.n_th;
+  const int i0 = (int)blockIdx.y * kFTI - g.ng;  // first output row (plane row index i)
+  const int J0 = (int)blockIdx.x * kFTJ;         // first output column (storage column, j + ng)
+  const int far = J0 + kFTJ > n + g.ng - 4 ? 2 * g.ng + 2 : 0;
+  const int ilo = max(i0 - passes, -g.ng), ihi = min(i0 + kFTI + passes, g.n_r + g.ng);
+  const int Jlo = max(J0 - passes - far, 0), Jhi = min(J0 + kFTJ + passes, g.ld);
+  const int ni = ihi - ilo, nj = Jhi - Jlo;
+  const int j = Jlo + tx - g.ng;  // this thread's plane column
+  for (int c = 0; c < ncomp; ++c) {
+    const int hs = hs3[c];
+    const double par = (double)ps3[c];
+    const bool ghost = j < 0 || j > n - hs;
+    // LDS columns this thread reads: the axis reflection (ghost column) or
+    // the two theta neighbours with their parities
+    const int jr = axis_mirror(j, n, hs) + g.ng - Jlo;
+    const int jm = axis_mirror(j - 1, n, hs), jp = axis_mirror(j + 1, n, hs);
     const double pm = jm == j - 1 ? 1.0 : par, pp = jp == j + 1 ? 1.0 : par;
-    const int64_t om = ix(g, i, jm), op = ix(g, i, jp);
-    const double r0 = pm * (double)s[om - ld] + 2.0 * s[o - ld] + pp * (double)s[op - ld];
-    const double r1 = pm * (double)s[om] + 2.0 * s[o] + pp * (double)s[op];
-    const double r2 = pm * (double)s[om + ld] + 2.0 * s[o + ld] + pp * (double)s[op + ld];
-    X.p[c][o] = 0.0625 * (r0 + 2.0 * r1 + r2);
+    const int lm = jm + g.ng - Jlo, lp = jp + g.ng - Jlo;
+    const bool col = tx < nj;
+    const bool sums = col && !ghost && lm >= 0 && lm < nj && lp >= 0 && lp < nj;
+    const bool refl = col && ghost && jr >= 0 && jr < nj;
+    const T* s = S.p[c];
+    if (col)
+      for (int li = ty; li < ni; li += 4) buf[0][li][tx] = s[(int64_t)(ilo + li + g.ng) * g.ld + (Jlo + tx)];
+    __syncthreads();
+    int cur = 0;
+    for (int p = 0; p < passes; ++p) {
+      if (sums)
+        for (int li = ty; li < ni; li += 4)
+          rs[li][tx] = pm * (double)buf[cur][li][lm] + 2.0 * (double)buf[cur][li][tx] + pp * (double)buf[cur][li][lp];
+      __syncthreads();
+      if (col)
+        for (int li = ty; li < ni; li += 4) {
+          const int i = ilo + li;
+          T v;
+          if (ghost) {
+            if (!refl) continue;
+            v = (T)(par * (double)buf[cur][li][jr]);
+          } else if (i < 1 - g.ng || i > g.n_r + g.ng - 2) {
+            v = buf[cur][li][tx];
+          } else {
+            if (li == 0 || li == ni - 1) continue;  // the staged region's edge: neighbours not staged
+            v = (T)(0.0625 * (rs[li - 1][tx] + 2.0 * rs[li][tx] + rs[li + 1][tx]));
+          }
+          buf[cur ^ 1][li][tx] = v;
+        }
+      __syncthreads();
+      cur ^= 1;
+    }
+    T* x = X.p[c];
+    const int J = Jlo + tx;
+    if (col && J >= J0 && J < J0 + kFTJ)
+      for (int li = ty; li < ni; li += 4) {
+        const int i = ilo + li;
+        if (i >= i0 && i < i0 + kFTI) x[(int64_t)(i + g.ng) * g.ld + J] = buf[cur][li][tx];
+      }
+    __syncthreads();
   }
 }
 

@@ -170,23 +170,27 @@ grpic_status field_bc(grpic_ctx* c, TriT<T> X, TriT<T> L, CTriT<T> X0, bool is_B
 
 // n_f binomial passes over ncomp planes, alternating between A and B and
 // ending in A (an odd count starts with one copy A -> B).
+// n_f binomial passes (Sec. 3.3.4) over the ncomp planes of A, up to
+// kFMaxPasses per launch of the LDS-tiled kernel, alternating between A and B;
+// *out is the triple that holds the result (A when n_f = 0).
 template <class T>
-grpic_status filter_passes(grpic_ctx* c, TriT<T> A, TriT<T> B, int ncomp, int3 half2, int3 parity,
-                           hipStream_t s) {
+grpic_status filter_passes(grpic_ctx* c, TriT<T> A, TriT<T> B, int ncomp, int3 half2, int3 parity, hipStream_t s,
+                           TriT<T>* out) {
   const Grid& g = c->g;
-  const int n = g.n_filter;
-  if (n % 2)
-    for (int k = 0; k < ncomp; ++k)
-      HIP_TRY(hipMemcpyAsync(B.p[k], A.p[k], g.plane * sizeof(T), hipMemcpyDeviceToDevice, s));
-  const dim3 gpl2 = grid2(g.n_r + 2 * g.ng, g.n_th + 2 * g.ng);
-  for (int p = 0; p < n; ++p) {
-    const bool from_A = (n - p) % 2 == 0;
-    TriT<T> dst = from_A ? B : A;
-    TriT<T> src = from_A ? A : B;
+  const dim3 grid((unsigned)((g.ld + kFTJ - 1) / kFTJ), (unsigned)((g.n_r + 2 * g.ng + kFTI - 1) / kFTI));
+  bool in_A = true;  // where the latest result is
+  for (int done = 0; done < g.n_filter;) {
+    const int passes = std::min(kFMaxPasses, g.n_filter - done);
+    const TriT<T>& src = in_A ? A : B;
+    const TriT<T>& dst = in_A ? B : A;
     CTriT<T> srcc{{src.p[0], src.p[1], src.p[2]}};
-    hipLaunchKernelGGL(filter_kernel<T>, gpl2, kBlock2, 0, s, g, dst, srcc, half2, parity, ncomp);
-    LAUNCH_CHECK("filter");
+    hipLaunchKernelGGL(filter_fused_kernel<T>, grid, dim3(64, 4), 0, s, g, dst, srcc, half2, parity, ncomp, passes);
+    LAUNCH_CHECK("filter_fused");
+    done += passes;
+    in_A = !in_A;
   }
+  const TriT<T>& res = in_A ? A : B;
+  for (int k = 0; k < 3; ++k) out->p[k] = res.p[k];
   return GRPIC_OK;
 }
 
@@ -346,9 +350,9 @@ grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_par
   const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
   const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
   const ParticleArraysT<T> a = arrays<T>(src), b = arrays<T>(dst);
-  const dim3 gsort((unsigned)((src->n + (int64_t)kB * kSortPer - 1) / ((int64_t)kB * kSortPer)));
-  hipLaunchKernelGGL(sort_count_kernel<T>, gsort, dim3(kB), 0, s, g, a, w.off);
-  LAUNCH_CHECK("sort_count");
+  const dim3 grank((unsigned)((src->n + (int64_t)kB * kSortPer - 1) / ((int64_t)kB * kSortPer)));
+  hipLaunchKernelGGL(sort_rank_kernel<T>, grank, dim3(kB), 0, s, g, a, w.off);
+  LAUNCH_CHECK("sort_rank");
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, w.off, nkeys, w.sums);
   LAUNCH_CHECK("scan_blocks");
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, w.sums, nb);
@@ -357,7 +361,7 @@ grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_par
   LAUNCH_CHECK("scan_add");
   hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, w.off + (nkeys - 1), w.live);
   LAUNCH_CHECK("copy_int");
-  hipLaunchKernelGGL(sort_scatter_kernel<T>, gsort, dim3(kB), 0, s, g, a, b, w.off);
+  hipLaunchKernelGGL(sort_scatter_kernel<T>, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, b, (const int*)w.off);
   LAUNCH_CHECK("sort_scatter");
   return GRPIC_OK;
 }
@@ -427,7 +431,9 @@ grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t sta
   }
   // current filter (n_f passes) on the freshly deposited J^{n+1/2}, T as the
   // second plane set
-  if ((st = filter_passes<T>(c, tri<T>(F->J), tri<T>(F->T), 3, kStagD2, int3{1, -1, -1}, s))) return st;
+  TriT<T> Jf;  // the filtered current: J itself, or the scratch set T
+  if ((st = filter_passes<T>(c, tri<T>(F->J), tri<T>(F->T), 3, kStagD2, int3{1, -1, -1}, s, &Jf))) return st;
+  const TriT<T> Jclear = Jf.p[0] == (T*)F->J[0] ? none<T>() : tri<T>(F->J);
   // E, H from (B0, D); B0 <- B and B += Faraday(E)
   hipLaunchKernelGGL((aux_kernel<T, true, true, kQ>), gaux, kBlock2, 0, s, g, c->tab, ctri<T>(F->B0),
                      ctri<T>(F->D), tri<T>(F->E), tri<T>(F->H));
@@ -438,7 +444,7 @@ grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t sta
   if ((st = field_bc<T>(c, tri<T>(F->B), comp<T>(c, F->Bc), ctri<T>(F->Binit), true, s))) return st;
   // D0 += Ampere(H, (J0 + J)/2)
   hipLaunchKernelGGL((ampere_kernel<T, false, kQ>), gupd, kBlock2, 0, s, g, c->tab, tri<T>(F->D0), none<T>(),
-                     ctri<T>(F->H), tri<T>(F->J0), tri<T>(F->J), 0.5, 0.5, c->polar_k, none<T>());
+                     ctri<T>(F->H), tri<T>(F->J0), Jf, 0.5, 0.5, c->polar_k, none<T>(), none<T>());
   LAUNCH_CHECK("ampere");
   if ((st = field_bc<T>(c, tri<T>(F->D0), none<T>(), ctri<T>(F->Dinit), false, s))) return st;
   // H from (B, D0); D0 <- D, D += Ampere(H, J), J0 <- J, J <- 0
@@ -446,7 +452,7 @@ grpic_status field_advance_impl(grpic_ctx* c, const grpic_fields* F, int32_t sta
                      ctri<T>(F->D0), none<T>(), tri<T>(F->H));
   LAUNCH_CHECK("aux_h");
   hipLaunchKernelGGL((ampere_kernel<T, true, kQ>), gpl2, kBlock2, 0, s, g, c->tab, tri<T>(F->D), comp<T>(c, F->Dc),
-                     ctri<T>(F->H), tri<T>(F->J), tri<T>(F->J0), 1.0, 0.0, c->polar_k, tri<T>(F->D0));
+                     ctri<T>(F->H), Jf, tri<T>(F->J0), 1.0, 0.0, c->polar_k, tri<T>(F->D0), Jclear);
   LAUNCH_CHECK("ampere");
   return field_bc<T>(c, tri<T>(F->D), comp<T>(c, F->Dc), ctri<T>(F->Dinit), false, s);
 }
@@ -498,8 +504,9 @@ grpic_status diagnostics_impl(grpic_ctx* c, const grpic_fields* F, const grpic_p
   }
   {
     grpic_status st;
-    TriT<T> A{{Q, nullptr, nullptr}}, B{{tmp, nullptr, nullptr}};
-    if ((st = filter_passes<T>(c, A, B, 1, int3{0, 0, 0}, int3{1, 1, 1}, s))) return st;
+    TriT<T> A{{Q, nullptr, nullptr}}, B{{tmp, nullptr, nullptr}}, out;
+    if ((st = filter_passes<T>(c, A, B, 1, int3{0, 0, 0}, int3{1, 1, 1}, s, &out))) return st;
+    Q = out.p[0];
   }
   if (gauss_res) {
     hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks(g.plane)), dim3(kB), 0, s, g.plane, (T*)gauss_res, 0.0);

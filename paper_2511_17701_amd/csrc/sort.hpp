@@ -45,26 +45,44 @@ __device__ inline Run wave_run(int key) {
   return r;
 }
 
-// Each wavefront takes kSortPer consecutive chunks of 64 slots (one slot per
-// lane in each), so that one round trip of its cell-offset atomics covers
-// kSortPer chunks.
-constexpr int kSortPer = 4;
+// Each wavefront of the rank pass takes kSortPer consecutive chunks of 64
+// slots (one slot per lane in each), so that one round trip of its counter
+// atomics covers kSortPer chunks.
+constexpr int kSortPer = 8;
 
 __device__ inline int64_t sort_first_slot() {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   return wave * 64 * kSortPer + (threadIdx.x & 63);
 }
 
+// Counts the slots of each key and gives every slot its rank among the slots
+// of its key: the first lane of each run claims the run's ranks with one
+// returning atomic on the key's counter (all of a wavefront's kSortPer
+// claims are in flight before the first is waited for), the other lanes of
+// the run follow it.  The rank is written to the source's i1p (the previous
+// position is scratch between a push and its deposit, and the sort does not
+// carry it), so the scatter needs no atomics.
 template <class T>
-__global__ void __launch_bounds__(256) sort_count_kernel(Grid g, ParticleArraysT<T> P,
-                                                         int* __restrict__ counts) {
+__global__ void __launch_bounds__(256) sort_rank_kernel(Grid g, ParticleArraysT<T> P, int* __restrict__ counts) {
   const int64_t k0 = sort_first_slot();
+  int key[kSortPer], base[kSortPer];
+  Run r[kSortPer];
 #pragma unroll
   for (int c = 0; c < kSortPer; ++c) {
     const int64_t k = k0 + 64 * c;
-    const int key = k < P.n ? sort_key(g, P, k) : -1;  // -1: past the end (own run)
-    const Run r = wave_run(key);
-    if (r.first && key >= 0) atomicAdd(counts + key, r.len);
+    key[c] = k < P.n ? sort_key(g, P, k) : -1;  // -1: past the end (own run)
+  }
+#pragma unroll
+  for (int c = 0; c < kSortPer; ++c) {
+    r[c] = wave_run(key[c]);
+    base[c] = 0;
+    if (r[c].first && key[c] >= 0) base[c] = atomicAdd(counts + key[c], r[c].len);
+  }
+#pragma unroll
+  for (int c = 0; c < kSortPer; ++c) {
+    const int b = __shfl(base[c], r[c].head, 64);
+    const int64_t k = k0 + 64 * c;
+    if (key[c] >= 0) P.i1p[k] = b + ((threadIdx.x & 63) - r[c].head);
   }
 }
 
@@ -127,72 +145,33 @@ __global__ void scan_add_kernel(int* __restrict__ a, int64_t n, const int* __res
   if (i < n) a[i] += sums[i / kScanBlock];
 }
 
-// Moves slot k of S to its cell's next free slots in D; emptied slots get tag
-// 0.  The previous position (scratch between a push and its deposit) is not
-// carried.  A run of equal keys in a chunk takes consecutive slots in lane
-// order; the order of runs of one cell follows the order of the atomics.  All
-// of a wavefront's slots are read, and all its offsets claimed, before the
-// first offset is waited for.
-template <class T>
-struct SlotT {
-  int i1, i2;
-  T dx1, dx2, u1, u2, u3, w, phi;
-  uint8_t tag;
-};
-
+// Moves slot k of S to slot off[key] + rank of D (rank from sort_rank_kernel,
+// in S.i1p; off the exclusive scan of the key counts); emptied slots get tag
+// 0.  No atomics: every load and store of a wavefront is independent, so the
+// pass streams at the memory system's rate.  The previous position (scratch
+// between a push and its deposit) is not carried.
 template <class T>
 __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArraysT<T> S, ParticleArraysT<T> D,
-                                                           int* __restrict__ off) {
-  const int64_t k0 = sort_first_slot();
+                                                           const int* __restrict__ off) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= S.n) return;
   const int ncell = g.n_r * g.n_th;
-  int key[kSortPer];
-  SlotT<T> v[kSortPer];
-#pragma unroll
-  for (int c = 0; c < kSortPer; ++c) {
-    const int64_t k = k0 + 64 * c;
-    key[c] = k < S.n ? sort_key(g, S, k) : -1;
-    v[c] = SlotT<T>{};
-    if (key[c] >= 0 && key[c] < ncell) {
-      v[c].i1 = S.i1[k];
-      v[c].i2 = S.i2[k];
-      v[c].dx1 = S.dx1[k];
-      v[c].dx2 = S.dx2[k];
-      v[c].u1 = S.u1[k];
-      v[c].u2 = S.u2[k];
-      v[c].u3 = S.u3[k];
-      v[c].w = S.w[k];
-      v[c].phi = S.phi[k];
-      v[c].tag = S.tag[k];
-    }
+  const int key = sort_key(g, S, k);
+  const int64_t o = (int64_t)off[key] + S.i1p[k];
+  if (key == ncell) {
+    D.tag[o] = 0;
+    return;
   }
-  Run r[kSortPer];
-  int base[kSortPer];
-#pragma unroll
-  for (int c = 0; c < kSortPer; ++c) {
-    r[c] = wave_run(key[c]);
-    base[c] = 0;
-    if (r[c].first && key[c] >= 0) base[c] = atomicAdd(off + key[c], r[c].len);
-  }
-#pragma unroll
-  for (int c = 0; c < kSortPer; ++c) {
-    const int b = __shfl(base[c], r[c].head, 64);
-    if (key[c] < 0) continue;
-    const int64_t o = (int64_t)b + ((threadIdx.x & 63) - r[c].head);
-    if (key[c] == ncell) {
-      D.tag[o] = 0;
-      continue;
-    }
-    D.i1[o] = v[c].i1;
-    D.i2[o] = v[c].i2;
-    D.dx1[o] = v[c].dx1;
-    D.dx2[o] = v[c].dx2;
-    D.u1[o] = v[c].u1;
-    D.u2[o] = v[c].u2;
-    D.u3[o] = v[c].u3;
-    D.w[o] = v[c].w;
-    D.phi[o] = v[c].phi;
-    D.tag[o] = v[c].tag;
-  }
+  D.i1[o] = S.i1[k];
+  D.i2[o] = S.i2[k];
+  D.dx1[o] = S.dx1[k];
+  D.dx2[o] = S.dx2[k];
+  D.u1[o] = S.u1[k];
+  D.u2[o] = S.u2[k];
+  D.u3[o] = S.u3[k];
+  D.w[o] = S.w[k];
+  D.phi[o] = S.phi[k];
+  D.tag[o] = S.tag[k];
 }
 
 }  // namespace grpic

@@ -343,11 +343,14 @@ def test_push_deposit_fused_equals_separate(O, G):
 
 # ---------------------------------------------------------------- fields
 
-def test_field_advance_parity(O, G):
-    """Both field stages from a perturbed Wald state with currents, 2 filter
-    passes and a 6-cell absorbing layer."""
-    w = wl("c1_64", 48)
-    prm, ctx = pair(O, G, w, charge_scale=0.05, n_filter=2, n_absorb=6)
+@pytest.mark.parametrize("n_r,n_th,n_f", [(48, 48, 2), (40, 126, 3), (36, 61, 5), (24, 64, 1)])
+def test_field_advance_parity(O, G, n_r, n_th, n_f):
+    """Both field stages from a perturbed Wald state with currents, n_f filter
+    passes and a 6-cell absorbing layer.  The grids put the far axis's ghost
+    columns in a filter tile of their own (126: 130 stored columns) and take
+    the passes in two launches (n_f = 5: four, then one)."""
+    w = wl("c1_64").scaled(n_r, n_th)
+    prm, ctx = pair(O, G, w, charge_scale=0.05, n_filter=n_f, n_absorb=6)
     F = O.fields_init_wald(prm, w.B0)
     g = np.random.default_rng(0)
     F[:12] *= 1 + 0.1 * g.normal(size=F[:12].shape)
