@@ -307,3 +307,24 @@ def test_absorbing_layer_absorption_pin_fails_planted_mistake(O):
     with O.planted(("double x0 = (double)(p->n_r - p->n_absorb);", "double x0 = (double)(p->n_r + p->n_absorb);")):
         layer = reflected_pulse(O, 16)
     assert not np.all(bare >= 10.0 * layer), (bare, layer)
+
+
+def test_absorbing_ramp_shape(O):
+    """R16's ramp: lambda is 0 up to the layer's inner edge x0 = n_r - n_absorb,
+    grows monotonically to 1 at the outer edge and stays 1 beyond it, and
+    starts with zero slope and curvature (a smooth onset reflects nothing at
+    the edge to second order: finite differences of lambda at x0 vanish like
+    h^3)."""
+    prm = O.Params.make(0.9, 1.0, 1.3, 20.0, 64, 32, 0.01, n_absorb=16)
+    x0, xe = 64 - 16, 64.0
+    xs = np.linspace(0.0, 70.0, 7001)
+    lam = np.array([O.match_lambda(prm, x) for x in xs])
+    assert (lam[xs <= x0] == 0.0).all()
+    assert (lam[xs >= xe] == 1.0).all()
+    assert (np.diff(lam) >= 0.0).all()
+    assert ((lam > 0) & (lam < 1))[(xs > x0) & (xs < xe)].all()
+    h = np.array([1e-1, 1e-2])
+    vals = np.array([O.match_lambda(prm, x0 + d) for d in h])
+    assert vals[0] / vals[1] == pytest.approx(1e3, rel=1e-6)    # ~ h^3 at the onset
+    bare = O.Params.make(0.9, 1.0, 1.3, 20.0, 64, 32, 0.01, n_absorb=0)
+    assert all(O.match_lambda(bare, x) == 0.0 for x in (0.0, 40.0, 63.9, 64.0, 70.0))
