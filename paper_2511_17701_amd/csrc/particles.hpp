@@ -99,9 +99,9 @@ __device__ inline T interp(const Grid& g, const T* __restrict__ F, int i1, T dx1
   return a0 + w1 * (a1 - a0);
 }
 
-// Relativistic Boris step for duration tau in an orthonormal frame, returned
-// as the change of u: both electric half kicks plus the rotation of the
-// half-kicked u_minus, (u_minus + u_minus x t) x s.
+// Relativistic Boris step for duration tau in an orthonormal frame: u_minus
+// = u + k E, the rotation (u_minus + u_minus x t) x s, the second electric
+// half kick.  Returns the change of u (both kicks plus the rotation term).
 template <class R>
 __device__ inline void boris_delta(R ux, R uy, R uz, const R E[3], const R B[3], R k /* = qm tau / 2 */,
                                    R& dx, R& dy, R& dz) {
@@ -119,22 +119,50 @@ __device__ inline void boris_delta(R ux, R uy, R uz, const R E[3], const R B[3],
   dz = (px * sy - py * sx) + k2 * E[2];
 }
 
+// The same Boris step applied to u in place.
+template <class R>
+__device__ inline void boris(R& ux, R& uy, R& uz, const R E[3], const R B[3], R k /* = qm tau / 2 */) {
+  const R mx = ux + k * E[0], my = uy + k * E[1], mz = uz + k * E[2];
+  const R ig = k / sqrt((R)1 + mx * mx + my * my + mz * mz);
+  const R tx = B[0] * ig, ty = B[1] * ig, tz = B[2] * ig;
+  const R f = (R)2 / ((R)1 + tx * tx + ty * ty + tz * tz);
+  const R sx = f * tx, sy = f * ty, sz = f * tz;
+  const R px = mx + (my * tz - mz * ty);
+  const R py = my + (mz * tx - mx * tz);
+  const R pz = mz + (mx * ty - my * tx);
+  ux = mx + (py * sz - pz * sy) + k * E[0];
+  uy = my + (pz * sx - px * sz) + k * E[1];
+  uz = mz + (px * sy - py * sx) + k * E[2];
+}
+
 // EM half step: covariant -> tetrad (App. A), Boris, tetrad -> covariant.
-// Only the change of the tetrad components is taken back and added to the
-// covariant u, so u carries one rounding per half step instead of those of a
-// full round trip through the tetrad (which would dominate the error of the
-// single-precision form over many steps).
+// Single precision takes only the change of the tetrad components back and
+// adds it to the covariant u, so u carries one rounding per half step instead
+// of those of a full round trip through the tetrad (which would dominate the
+// error of the single-precision form over many steps).  Double precision
+// (and the adjoint's tangent numbers) take the whole vector back: the round
+// trip costs nothing visible there, and it keeps fewer values live.
 template <class R>
 __device__ inline void em_half(const FrameT<R>& f, const R E[3], const R B[3], R k, R& u1, R& u2,
                                R& u3) {
-  const R x = f.s11 * (u1 - f.k13 * u3);
-  const R y = u2 / f.s22;
-  const R z = u3 / f.s33;
-  R dx, dy, dz;
-  boris_delta(x, y, z, E, B, k, dx, dy, dz);
-  u1 = u1 + (dx / f.s11 + f.k13 * f.s33 * dz);
-  u2 = u2 + f.s22 * dy;
-  u3 = u3 + f.s33 * dz;
+  if constexpr (sizeof(R) == 4) {
+    const R x = f.s11 * (u1 - f.k13 * u3);
+    const R y = u2 / f.s22;
+    const R z = u3 / f.s33;
+    R dx, dy, dz;
+    boris_delta(x, y, z, E, B, k, dx, dy, dz);
+    u1 = u1 + (dx / f.s11 + f.k13 * f.s33 * dz);
+    u2 = u2 + f.s22 * dy;
+    u3 = u3 + f.s33 * dz;
+  } else {
+    R x = f.s11 * (u1 - f.k13 * u3);
+    R y = u2 / f.s22;
+    R z = u3 / f.s33;
+    boris(x, y, z, E, B, k);
+    u1 = x / f.s11 + f.k13 * f.s33 * z;
+    u2 = f.s22 * y;
+    u3 = f.s33 * z;
+  }
 }
 
 // Implicit-midpoint geodesic momentum update at fixed x^n (eq.
