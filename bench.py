@@ -391,7 +391,11 @@ def main():
     figs = profile_figures(f"{kname}_{w.name}_{precision}_pmc.txt")
     current = figs.get("source_sha256") == source_hash()
     flops_pp = float(figs["flops_per_particle"]) if current and "flops_per_particle" in figs else None
-    achieved = flops_pp * live / (k1 * 1e-3) / 1e12 if flops_pp else None
+    lanes = float(figs["valu_active_lane_fraction"]) if current and "valu_active_lane_fraction" in figs else None
+    executed = flops_pp * live / (k1 * 1e-3) / 1e12 if flops_pp else None
+    # the method's own FLOPs: the counted lane slots times the fraction of lanes
+    # active in the kernel's VALU instructions (masked-off lanes do no work)
+    achieved = executed * lanes if executed and lanes else executed
     traffic = None
     if current and "hbm_bytes_per_particle" in figs:
         traffic = float(figs["hbm_bytes_per_particle"]) * live
@@ -402,8 +406,12 @@ def main():
         "frac": achieved / PEAK_VECTOR_TFLOPS if achieved else None,
         "traffic": traffic, "avg_launch_ms": k1, "particles_per_launch": live,
         "flops_per_particle": flops_pp,
-        "frac_basis": "FLOPs are the counted VALU lane slots of the kernel (wave instructions x 64, "
-                      "FMA = 2), lanes masked off in divergent iterations included",
+        "frac_basis": ("FLOPs: the kernel's counted FP32/FP64 VALU lane slots (wave instructions x 64, "
+                       "FMA = 2) times the measured fraction of active lanes "
+                       f"({lanes:.3f})" if lanes else
+                       "FLOPs: the kernel's counted FP32/FP64 VALU lane slots (wave instructions x 64, "
+                       "FMA = 2), lanes masked off in divergent iterations included"),
+        "achieved_executed_lane_slots": executed,
         "peak_basis": "256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz: FP64 and non-packed FP32 "
                       "vector issue (packed FP32, the chip's 157.3 TFLOP/s, is not used by this code)",
     }
