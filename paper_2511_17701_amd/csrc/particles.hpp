@@ -105,10 +105,13 @@ __device__ inline T interp(const Grid& g, const T* __restrict__ F, int i1, T dx1
 template <class R>
 __device__ inline void boris_delta(R ux, R uy, R uz, const R E[3], const R B[3], R k /* = qm tau / 2 */,
                                    R& dx, R& dy, R& dz) {
+  // (single precision: reciprocal and reciprocal square root from the
+  // hardware seeds with a Newton step, about an ulp, in place of the
+  // correctly rounded division and square root)
   const R mx = ux + k * E[0], my = uy + k * E[1], mz = uz + k * E[2];
-  const R ig = k / sqrt((R)1 + mx * mx + my * my + mz * mz);
+  const R ig = k * rsqrt((R)1 + mx * mx + my * my + mz * mz);
   const R tx = B[0] * ig, ty = B[1] * ig, tz = B[2] * ig;
-  const R f = (R)2 / ((R)1 + tx * tx + ty * ty + tz * tz);
+  const R f = (R)2 * rcp((R)1 + tx * tx + ty * ty + tz * tz);
   const R sx = f * tx, sy = f * ty, sz = f * tz;
   const R px = mx + (my * tz - mz * ty);
   const R py = my + (mz * tx - mx * tz);
@@ -147,11 +150,11 @@ __device__ inline void em_half(const FrameT<R>& f, const R E[3], const R B[3], R
                                R& u3) {
   if constexpr (sizeof(R) == 4) {
     const R x = f.s11 * (u1 - f.k13 * u3);
-    const R y = u2 / f.s22;
-    const R z = u3 / f.s33;
+    const R y = u2 * rcp(f.s22);
+    const R z = u3 * rcp(f.s33);
     R dx, dy, dz;
     boris_delta(x, y, z, E, B, k, dx, dy, dz);
-    u1 = u1 + (dx / f.s11 + f.k13 * f.s33 * dz);
+    u1 = u1 + (dx * rcp(f.s11) + f.k13 * f.s33 * dz);
     u2 = u2 + f.s22 * dy;
     u3 = u3 + f.s33 * dz;
   } else {
@@ -613,9 +616,9 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
     const float B1 = interp<0, 1>(g, fp.B[0], i1, dx1, i2, dx2);
     const float B2 = interp<1, 0>(g, fp.B[1], i1, dx1, i2, dx2);
     const float B3 = interp<1, 1>(g, fp.B[2], i1, dx1, i2, dx2);
-    const float al = f.c.alpha;
-    const float E[3] = {al * D1 / f.s11, al * f.s22 * D2, al * f.s33 * (f.k13 * D1 + D3)};
-    const float B[3] = {al * B1 / f.s11, al * f.s22 * B2, al * f.s33 * (f.k13 * B1 + B3)};
+    const float al = f.c.alpha, ais11 = al * rcp(f.s11);
+    const float E[3] = {ais11 * D1, al * f.s22 * D2, al * f.s33 * (f.k13 * D1 + D3)};
+    const float B[3] = {ais11 * B1, al * f.s22 * B2, al * f.s33 * (f.k13 * B1 + B3)};
     const float kb = 0.25f * qm * (float)g.dt;
     em_half(f, E, B, kb, u1, u2, u3);
     geodesic_u(g, f, d, u1, u2, u3, 1.0f);
