@@ -17,9 +17,9 @@ struct DiagAcc {
 
 constexpr int kDiagBlock = 256;
 
-template <class T>
+template <class T, int SER>
 __global__ void __launch_bounds__(kDiagBlock)
-diag_particles_kernel(Grid g, ParticleArraysT<T> P, double B0, T* __restrict__ Eout,
+diag_particles_kernel(Grid g, Tables tab, ParticleArraysT<T> P, double B0, T* __restrict__ Eout,
                       T* __restrict__ Lout, DiagAcc* acc) {
   __shared__ unsigned long long sc[8][kDiagBlock / 64];
   __shared__ double ss[8][kDiagBlock / 64];
@@ -42,13 +42,17 @@ diag_particles_kernel(Grid g, ParticleArraysT<T> P, double B0, T* __restrict__ E
         cnt[6] = 1;
       const double x1 = 0.5 * (((double)P.i1p[k] + P.dx1p[k]) + ((double)P.i1[k] + d1));
       const double x2 = 0.5 * (((double)P.i2p[k] + P.dx2p[k]) + ((double)P.i2[k] + d2));
-      const Coeffs m = coeffs_at(g, x1, x2);
-      double r, rd, th, td, dtd;
-      map_r(g, x1, &r, &rd);
-      map_theta(g, x2, &th, &td, &dtd);
-      double s, c;
-      sincos(clamp_theta(g, th), &s, &c);
-      const WaldPot w = wald_pot(g, r, s, c, B0);
+      // r, the clamped sin and cos at the time-centred position, once, for the
+      // metric and the Wald potential (the in-cell series of the push on fine
+      // grids, the library functions otherwise)
+      // (a stale previous position -- the fused pass and the sort do not keep
+      // it -- may put the midpoint anywhere: the tables are read only for a
+      // midpoint within the grid's cells)
+      const double f1 = floor(x1), f2 = floor(x2);
+      const bool tabled = f1 >= -1.0 && f1 <= (double)g.n_r && f2 >= 0.0 && f2 <= (double)g.n_th;
+      const RSC p = tabled ? rsc_near<SER>(g, tab, (int)f1, x1, (int)f2, x2) : rsc_direct(g, x1, x2);
+      const Coeffs m = coeffs_from(g, p);
+      const WaldPot w = wald_pot(g, p.r, p.s, p.c, B0);
       const double qm = species_sign(t);
       E = m.alpha * gamma_of(m, u1, u2, u3, mass2_of(t)) - m.beta1 * u1 - qm * w.A0;
       L = u3 + qm * w.A3;

@@ -315,7 +315,7 @@ grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_
     switch (c->g.ser) {
       case 2: hipLaunchKernelGGL((push_deposit_kernel<2>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
       case 1: hipLaunchKernelGGL((push_deposit_kernel<1>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
-      default: hipLaunchKernelGGL((push_deposit_kernel<0>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
+      default: hipLaunchKernelGGL(push_deposit_kernel_lib, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
     }
   }
   LAUNCH_CHECK("push_deposit");
@@ -489,8 +489,12 @@ grpic_status diagnostics_impl(grpic_ctx* c, const grpic_fields* F, const grpic_p
                               void* E_out, void* L_out, void* gauss_res, hipStream_t s) {
   const Grid& g = c->g;
   if (P->n > 0) {
-    hipLaunchKernelGGL(diag_particles_kernel<T>, dim3(blocks(P->n)), dim3(kDiagBlock), 0, s, g, arrays<T>(P),
-                       B0, (T*)E_out, (T*)L_out, c->acc);
+    const dim3 gd(blocks(P->n)), bd(kDiagBlock);
+    switch (g.ser) {
+      case 2: hipLaunchKernelGGL((diag_particles_kernel<T, 2>), gd, bd, 0, s, g, c->tab, arrays<T>(P), B0, (T*)E_out, (T*)L_out, c->acc); break;
+      case 1: hipLaunchKernelGGL((diag_particles_kernel<T, 1>), gd, bd, 0, s, g, c->tab, arrays<T>(P), B0, (T*)E_out, (T*)L_out, c->acc); break;
+      default: hipLaunchKernelGGL((diag_particles_kernel<T, 0>), gd, bd, 0, s, g, c->tab, arrays<T>(P), B0, (T*)E_out, (T*)L_out, c->acc); break;
+    }
     LAUNCH_CHECK("diag_particles");
   }
   // Gauss residual: charge into T[0], filtered like the currents (T[1] scratch)

@@ -1115,6 +1115,17 @@ push_deposit_kernel(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays
   deposit_block(g, cp, act, c);
 }
 
+// library path in FP64 (coarse grids and the general quasi-spherical map):
+// the library exp and sincos and the map factors need more registers than the
+// series paths; three wavefronts per SIMD leave room for them without spills
+__global__ void __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(3)))
+push_deposit_kernel_lib(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp) {
+  const Move<double> mv = push_one<0, false>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  ContribT<double> c;
+  const bool act = make_contrib<double, 0>(g, tab, mv, c);
+  deposit_block(g, cp, act, c);
+}
+
 template <int SER>
 __device__ inline void push_deposit_f32(const Grid& g, const Tables& tab, const GatherPlanesT<float>& fp,
                                         const ParticleArraysT<float>& P, const CurrentPlanesT<float>& cp) {
