@@ -380,6 +380,68 @@ __global__ void fill_kernel(int64_t n, T* __restrict__ p, double v) {
   if (k < n) p[k] = v;
 }
 
+// ---------------------------------------------------------------- filter
+// Binomial passes (1,2,1)/4 x (1,2,1)/4 of a current plane (Sec. 3.3.4), in
+// the arithmetic of one pass at plane point (i, j) of a component of
+// x2-staggering hs and axis parity par, reading the source S of the pass:
+//  - ghost columns (j < 0 or j > n_th - hs) take the source's axis reflection
+//    par S(i, mirror(j));
+//  - the two outermost plane rows keep the source;
+//  - every other point is (R(i-1) + 2 R(i) + R(i+1)) / 16 rounded to T, with
+//    the FP64 row sums R(i) = pm S(i, j-1) + 2 S(i, j) + pp S(i, j+1), whose
+//    theta neighbours past an axis are read as reflections (pm, pp = par
+//    there, 1 elsewhere).
+// Every product is by 1, 2 or a power of two, so the result does not depend
+// on how the compiler contracts the sums.
+//
+// Up to kFMaxPasses passes run in one launch.  A wavefront owns a strip of
+// 64 plane columns (one per lane) and kSR output rows, and holds its rows plus
+// a halo of P rows on each side in registers for the whole run: the theta
+// neighbours come from the adjacent lanes by DPP wave shifts and the axis
+// reflections by a lane permute (only in strips that touch an axis); the
+// radial sums slide down the rows.  No LDS and no barriers.  Values whose
+// neighbours lie outside the strip (the wave's first and last lane, the first
+// and last staged row) are not computed: the stale points move inwards by one
+// per pass, so after P passes the 56 middle lanes and the kSR middle rows are
+// exact; at the plane's edges nothing outside is needed and the strip outputs
+// up to the edge.  The last strip of a row is shifted to end at the plane's
+// last column, so the far-axis reflections it reads are exact (the columns it
+// shares with its neighbour get identical values twice).  X must not alias S.
+constexpr int kFMaxPasses = 4;
+constexpr int kFLanes = 64, kFOut = kFLanes - 2 * kFMaxPasses;  // 56 output columns per strip
+
+// number of 64-column strips that cover a plane row of ld stored columns,
+// and the first stored column of strip b (the last one ends at the plane's
+// last column)
+__host__ __device__ inline int filter_strips_theta(int ld) {
+  return ld <= kFLanes ? 1 : (ld - (kFLanes - kFMaxPasses) + kFOut - 1) / kFOut + 1;
+}
+__host__ __device__ inline int filter_strip_lo(int b, int ld) {
+  return min(b * kFOut, max(ld - kFLanes, 0));
+}
+// whether strip b touches an axis (a column j <= 0 or j >= n_th - 1)
+__host__ __device__ inline bool filter_strip_axis(int b, int ld, int n, int ng) {
+  const int lo = filter_strip_lo(b, ld);
+  return lo <= ng || lo + kFLanes - 1 >= n - 1 + ng;
+}
+
+// the lane's value one lane down (wave_shr:1) and one lane up (wave_shl:1);
+// the first / last lane reads 0
+__device__ inline int lane_down(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ inline int lane_up(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+__device__ inline float lane_down(float v) { return __int_as_float(lane_down(__float_as_int(v))); }
+__device__ inline float lane_up(float v) { return __int_as_float(lane_up(__float_as_int(v))); }
+__device__ inline double lane_down(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_down((int)(b & 0xffffffffll)), hi = lane_down((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+__device__ inline double lane_up(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_up((int)(b & 0xffffffffll)), hi = lane_up((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
 // Column j reflected across the axis for a component of x2-staggering hs
 // (node rows run 0..n, half rows 0..n-1); interior columns map to themselves.
 __device__ inline int axis_mirror(int j, int n, int hs) {
@@ -388,123 +450,153 @@ __device__ inline int axis_mirror(int j, int n, int hs) {
   return j;
 }
 
-// The value one binomial pass (1,2,1)/4 x (1,2,1)/4 (Sec. 3.3.4) gives at
-// plane point (i, j) of a component of x2-staggering hs and axis parity par,
-// from the source values at(i', j'): ghost columns take the source's axis
-// reflection, the two outermost rows keep the source, every other point is
-// the stencil with its theta neighbours read as axis reflections where they
-// fall past an axis (so at() is only asked for evolved columns there).
-template <class T, class At>
-__device__ inline T filter_point(const Grid& g, int i, int j, int hs, double par, const At& at) {
-  const int n = g.n_th;
-  if (j < 0 || j > n - hs) return (T)(par * (double)at(i, axis_mirror(j, n, hs)));
-  if (i < 1 - g.ng || i > g.n_r + g.ng - 2) return at(i, j);
-  const int jm = axis_mirror(j - 1, n, hs), jp = axis_mirror(j + 1, n, hs);
-  const double pm = jm == j - 1 ? 1.0 : par, pp = jp == j + 1 ? 1.0 : par;
-  const double r0 = pm * (double)at(i - 1, jm) + 2.0 * (double)at(i - 1, j) + pp * (double)at(i - 1, jp);
-  const double r1 = pm * (double)at(i, jm) + 2.0 * (double)at(i, j) + pp * (double)at(i, jp);
-  const double r2 = pm * (double)at(i + 1, jm) + 2.0 * (double)at(i + 1, j) + pp * (double)at(i + 1, jp);
-  return (T)(0.0625 * (r0 + 2.0 * r1 + r2));
-}
+// Lane-constant data of one component in a strip that touches an axis.
+struct FilterAxis {
+  bool lo, hi;     // j == 0 / j == n - hs: the theta neighbour past the axis is a reflection
+  bool ghost;      // ghost column
+  int src;         // lane of the reflected column (ghost lanes)
+  bool hs;         // half-staggered in x2
+  double par;      // axis parity
+};
 
-// One binomial pass of S into X over the whole plane (filter_point per
-// point).  Passes alternate between two plane sets.
-template <class T>
-__global__ void filter_kernel(Grid g, TriT<T> X, CTriT<T> S, int3 half2, int3 parity, int ncomp) {
-  const PlaneIdx q = plane_idx(g);
-  if (!q.ok) return;
-  const int hs[3] = {half2.x, half2.y, half2.z};
-  const int ps[3] = {parity.x, parity.y, parity.z};
-  const int64_t o = ix(g, q.i, q.j);
-  for (int c = 0; c < ncomp; ++c) {
-    const T* s = S.p[c];
-    auto at = [&](int i, int j) -> T { return s[ix(g, i, j)]; };
-    X.p[c][o] = filter_point<T>(g, q.i, q.j, hs[c], (double)ps[c], at);
+// FP64 theta row sum of the pass at this lane
+template <class T, bool kAxis>
+__device__ inline double filter_row_sum(T a, const FilterAxis& ax) {
+  const T dn = lane_down(a), up = lane_up(a);
+  double lv = (double)dn, rv = (double)up;
+  if (kAxis) {
+    if (ax.lo) lv = ax.par * (double)(ax.hs ? a : up);
+    if (ax.hi) rv = ax.par * (double)(ax.hs ? a : dn);
   }
+  return (lv + 2.0 * (double)a) + rv;
 }
 
-// Up to kFMaxPasses binomial passes of S into X in one launch.  A block
-// (64 x 4 threads) owns an output tile of kFTI rows x kFTJ plane columns and
-// stages it in LDS with a halo as wide as the number of passes (and, at the
-// far axis, the columns its ghost columns reflect).  Each pass runs in two
-// LDS sweeps, the theta sums of every row (pm S[j-1] + 2 S[j] + pp S[j+1],
-// FP64), then the radial combination (R[i-1] + 2 R[i] + R[i+1]) / 16 rounded
-// to T, exactly the arithmetic of filter_point; ghost columns take the axis
-// reflection and the two outermost plane rows are copied.  Points whose
-// neighbours lie outside the staged region are not computed: the stale values
-// at the region's edge move inwards by one point per pass, so after `passes`
-// passes the tile (at depth `passes`) is exact; at the plane's edges nothing
-// outside is needed.  X must not alias S (other blocks read S's halo).
-// n_ghost = 2.
-constexpr int kFTI = 32, kFTJ = 48, kFMaxPasses = 4;
-constexpr int kFLI = kFTI + 2 * kFMaxPasses, kFLJ = 64;  // kFTJ + 2 passes + 6 far-axis columns <= 64
-
-template <class T>
-__global__ void __launch_bounds__(256) filter_fused_kernel(Grid g, TriT<T> X, CTriT<T> S, int3 half2,
-                                                           int3 parity, int ncomp, int passes) {
-  __shared__ T buf[2][kFLI][kFLJ];
-  __shared__ double rs[kFLI][kFLJ];
-  const int hs3[3] = {half2.x, half2.y, half2.z};
-  const int ps3[3] = {parity.x, parity.y, parity.z};
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int n = g.n_th;
-  const int i0 = (int)blockIdx.y * kFTI - g.ng;  // first output row (plane row index i)
-  const int J0 = (int)blockIdx.x * kFTJ;         // first output column (storage column, j + ng)
-  const int far = J0 + kFTJ > n + g.ng - 4 ? 2 * g.ng + 2 : 0;
-  const int ilo = max(i0 - passes, -g.ng), ihi = min(i0 + kFTI + passes, g.n_r + g.ng);
-  const int Jlo = max(J0 - passes - far, 0), Jhi = min(J0 + kFTJ + passes, g.ld);
-  const int ni = ihi - ilo, nj = Jhi - Jlo;
-  const int j = Jlo + tx - g.ng;  // this thread's plane column
-  for (int c = 0; c < ncomp; ++c) {
-    const int hs = hs3[c];
-    const double par = (double)ps3[c];
-    const bool ghost = j < 0 || j > n - hs;
-    // LDS columns this thread reads: the axis reflection (ghost column) or
-    // the two theta neighbours with their parities
-    const int jr = axis_mirror(j, n, hs) + g.ng - Jlo;
-    const int jm = axis_mirror(j - 1, n, hs), jp = axis_mirror(j + 1, n, hs);
-    const double pm = jm == j - 1 ? 1.0 : par, pp = jp == j + 1 ? 1.0 : par;
-    const int lm = jm + g.ng - Jlo, lp = jp + g.ng - Jlo;
-    const bool col = tx < nj;
-    const bool sums = col && !ghost && lm >= 0 && lm < nj && lp >= 0 && lp < nj;
-    const bool refl = col && ghost && jr >= 0 && jr < nj;
-    const T* s = S.p[c];
-    if (col)
-      for (int li = ty; li < ni; li += 4) buf[0][li][tx] = s[(int64_t)(ilo + li + g.ng) * g.ld + (Jlo + tx)];
-    __syncthreads();
-    int cur = 0;
-    for (int p = 0; p < passes; ++p) {
-      if (sums)
-        for (int li = ty; li < ni; li += 4)
-          rs[li][tx] = pm * (double)buf[cur][li][lm] + 2.0 * (double)buf[cur][li][tx] + pp * (double)buf[cur][li][lp];
-      __syncthreads();
-      if (col)
-        for (int li = ty; li < ni; li += 4) {
-          const int i = ilo + li;
-          T v;
-          if (ghost) {
-            if (!refl) continue;
-            v = (T)(par * (double)buf[cur][li][jr]);
-          } else if (i < 1 - g.ng || i > g.n_r + g.ng - 2) {
-            v = buf[cur][li][tx];
-          } else {
-            if (li == 0 || li == ni - 1) continue;  // the staged region's edge: neighbours not staged
-            v = (T)(0.0625 * (rs[li - 1][tx] + 2.0 * rs[li][tx] + rs[li + 1][tx]));
-          }
-          buf[cur ^ 1][li][tx] = v;
-        }
-      __syncthreads();
-      cur ^= 1;
-    }
-    T* x = X.p[c];
-    const int J = Jlo + tx;
-    if (col && J >= J0 && J < J0 + kFTJ)
-      for (int li = ty; li < ni; li += 4) {
-        const int i = ilo + li;
-        if (i >= i0 && i < i0 + kFTI) x[(int64_t)(i + g.ng) * g.ld + J] = buf[cur][li][tx];
+// One component of a strip: load, P passes, store rows [rlo, rhi).  kAxis:
+// the strip touches an axis (reflected neighbours, ghost columns); kRows: a
+// plane of fewer rows than a strip stages (rows outside the plane, the two
+// kept rows inside the strip).  Otherwise the strips are placed so that the
+// kept rows are a strip's first or last staged row, which no pass updates.
+template <class T, int P, int kSR, bool kAxis, bool kRows>
+__device__ __forceinline__ void filter_strip_comp(const Grid& g, T* __restrict__ x, const T* __restrict__ s, int J, bool col,
+                                         bool out, int ifirst, int rlo, int rhi, const FilterAxis& ax) {
+  constexpr int R = kSR + 2 * P;
+  // one wavefront-uniform base (the strip's first staged row) and 32-bit
+  // per-lane byte offsets (a strip spans R rows: far below 4 GiB)
+  const int64_t row0 = (int64_t)(ifirst + g.ng) * g.ld;
+  const char* __restrict__ sb = (const char*)(s + row0);
+  const uint32_t rowb = (uint32_t)(g.ld * sizeof(T));
+  uint32_t lb = (uint32_t)(J * sizeof(T));
+  asm volatile("" : "+v"(lb));  // row offsets computed here, not hoisted out of the component loop
+  T v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = ifirst + r;
+    v[r] = col && (!kRows || (i >= -g.ng && i < g.n_r + g.ng)) ? *(const T*)(sb + (lb + (uint32_t)r * rowb))
+                                                                : (T)0;
+    if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);  // 8 row offsets live at a time
+  }
+#pragma unroll 1
+  for (int p = 0; p < P; ++p) {
+    double s_prev = 0.0, s_cur = filter_row_sum<T, kAxis>(v[0], ax);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double s_next = r + 1 < R ? filter_row_sum<T, kAxis>(v[r + 1], ax) : 0.0;
+      const int i = ifirst + r;
+      T nv = v[r];
+      if (r >= 1 && r <= R - 2 && (!kRows || (i >= 1 - g.ng && i <= g.n_r + g.ng - 2)))
+        nv = (T)(0.0625 * ((s_prev + 2.0 * s_cur) + s_next));
+      if (kAxis) {
+        const T m = __shfl(v[r], ax.src);
+        if (ax.ghost) nv = (T)(ax.par * (double)m);
       }
-    __syncthreads();
+      v[r] = nv;
+      s_prev = s_cur;
+      s_cur = s_next;
+      __builtin_amdgcn_sched_barrier(0);  // row by row: a few sums live, not all
+    }
   }
+  if (out) {
+    // recompute the offsets here instead of keeping the loads' alive
+    uint32_t lbs = lb;
+    asm volatile("" : "+v"(lbs));
+    char* __restrict__ db = (char*)(x + row0);
+    auto put = [&](int r) { *(T*)(db + (lbs + (uint32_t)r * rowb)) = v[r]; };
+    if (kRows) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r >= rlo && r < rhi && ifirst + r < g.n_r + g.ng) put(r);
+    } else {  // rows [rlo, rhi) = [P or 0, P + kSR or R)
+#pragma unroll
+      for (int r = P; r < P + kSR; ++r) put(r);
+      if (rlo == 0) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) put(r);
+      }
+      if (rhi == R) {
+#pragma unroll
+        for (int r = P + kSR; r < R; ++r) put(r);
+      }
+    }
+  }
+}
+
+// number of row strips of a plane with nrow rows (kRows: nrow < kSR + 2 P)
+template <int P, int kSR, bool kRows>
+__host__ __device__ inline int filter_strips_r(int nrow) {
+  return kRows ? (nrow + kSR - 1) / kSR : (nrow - (kSR + 2 * P) + kSR - 1) / kSR + 1;
+}
+
+// P passes of S into X, plane blockIdx.z.  Grid: (filter_strips_theta(ld),
+// ceil(filter_strips_r / 4), number of planes); 256 threads = 4 wavefronts on
+// consecutive row strips.  Strip s stages rows from min(s kSR - ng, n_r + ng - R) (kRows:
+// s kSR - ng - P) and writes the rows it has exact: from its first row in
+// the first strip, to its last in the last one.  The register budget (four
+// wavefronts per SIMD, two for a single pass) keeps the compiler from
+// computing every row sum of a pass ahead of the radial combinations.
+template <class T, int P, int kSR, bool kRows>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 ? 2 : 4)))
+filter_strip_kernel(Grid g, TriT<T> X, CTriT<T> S, int3 half2, int3 parity) {
+  constexpr int R = kSR + 2 * P;
+  const int lane = (int)threadIdx.x & (kFLanes - 1);
+  const int strip = (int)blockIdx.y * 4 + ((int)threadIdx.x >> 6);
+  const int nrow = g.n_r + 2 * g.ng;
+  if (strip >= filter_strips_r<P, kSR, kRows>(nrow)) return;  // whole wavefront
+  int ifirst, rlo, rhi;
+  if (kRows) {
+    ifirst = strip * kSR - g.ng - P;
+    rlo = P;
+    rhi = P + kSR;
+  } else {
+    ifirst = min(strip * kSR - g.ng, g.n_r + g.ng - R);
+    rlo = strip == 0 ? 0 : P;
+    rhi = ifirst + R >= g.n_r + g.ng ? R : P + kSR;
+  }
+  const int ld = (int)g.ld, n = g.n_th;
+  const int b = (int)blockIdx.x;
+  const int Jlo = filter_strip_lo(b, ld);
+  const int out_lo = b == 0 ? 0 : Jlo + kFMaxPasses;
+  const int out_hi = Jlo + kFLanes >= ld ? ld : Jlo + kFLanes - kFMaxPasses;
+  const int J = Jlo + lane, j = J - g.ng;
+  const bool col = J < ld, out = col && J >= out_lo && J < out_hi;
+  // one component per grid.z (plane pointers selected with scalar code)
+  const int c = (int)blockIdx.z;
+  const int hs = c == 0 ? half2.x : c == 1 ? half2.y : half2.z;
+  T* const x = c == 0 ? X.p[0] : c == 1 ? X.p[1] : X.p[2];
+  const T* const sp = c == 0 ? S.p[0] : c == 1 ? S.p[1] : S.p[2];
+  FilterAxis ax{};
+  const bool axis = filter_strip_axis(b, ld, n, g.ng);  // whole wavefront
+  if (axis) {
+    ax.hs = hs != 0;
+    ax.par = (double)(c == 0 ? parity.x : c == 1 ? parity.y : parity.z);
+    ax.lo = j == 0;
+    ax.hi = j == n - hs;
+    ax.ghost = j < 0 || j > n - hs;
+    ax.src = ax.ghost ? lane + axis_mirror(j, n, hs) - j : lane;
+  }
+  if (axis)
+    filter_strip_comp<T, P, kSR, true, kRows>(g, x, sp, J, col, out, ifirst, rlo, rhi, ax);
+  else
+    filter_strip_comp<T, P, kSR, false, kRows>(g, x, sp, J, col, out, ifirst, rlo, rhi, ax);
 }
 
 }  // namespace grpic

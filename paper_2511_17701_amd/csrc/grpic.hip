@@ -168,24 +168,42 @@ grpic_status field_bc(grpic_ctx* c, TriT<T> X, TriT<T> L, CTriT<T> X0, bool is_B
   return GRPIC_OK;
 }
 
-// n_f binomial passes over ncomp planes, alternating between A and B and
-// ending in A (an odd count starts with one copy A -> B).
 // n_f binomial passes (Sec. 3.3.4) over the ncomp planes of A, up to
-// kFMaxPasses per launch of the LDS-tiled kernel, alternating between A and B;
-// *out is the triple that holds the result (A when n_f = 0).
+// kFMaxPasses per launch of the register-strip kernel, alternating between A
+// and B; *out is the triple that holds the result (A when n_f = 0).
+constexpr int kFStripRows = 32;  // output rows per wavefront (48 and 64: within 3 % at 4096^2)
+
+template <class T, int P>
+void launch_filter_strips(const Grid& g, int ncomp, TriT<T> dst, CTriT<T> src, int3 half2, int3 parity,
+                          hipStream_t s) {
+  constexpr int kSR = kFStripRows;
+  const int nrow = g.n_r + 2 * g.ng;
+  const bool small = nrow < kSR + 2 * P;  // fewer plane rows than a strip stages
+  const int strips = small ? filter_strips_r<P, kSR, true>(nrow) : filter_strips_r<P, kSR, false>(nrow);
+  const dim3 grid((unsigned)filter_strips_theta((int)g.ld), (unsigned)((strips + 3) / 4), (unsigned)ncomp);
+  if (small)
+    hipLaunchKernelGGL((filter_strip_kernel<T, P, kSR, true>), grid, dim3(256), 0, s, g, dst, src, half2, parity);
+  else
+    hipLaunchKernelGGL((filter_strip_kernel<T, P, kSR, false>), grid, dim3(256), 0, s, g, dst, src, half2, parity);
+}
+
 template <class T>
 grpic_status filter_passes(grpic_ctx* c, TriT<T> A, TriT<T> B, int ncomp, int3 half2, int3 parity, hipStream_t s,
                            TriT<T>* out) {
   const Grid& g = c->g;
-  const dim3 grid((unsigned)((g.ld + kFTJ - 1) / kFTJ), (unsigned)((g.n_r + 2 * g.ng + kFTI - 1) / kFTI));
   bool in_A = true;  // where the latest result is
   for (int done = 0; done < g.n_filter;) {
     const int passes = std::min(kFMaxPasses, g.n_filter - done);
-    const TriT<T>& src = in_A ? A : B;
     const TriT<T>& dst = in_A ? B : A;
+    const TriT<T>& src = in_A ? A : B;
     CTriT<T> srcc{{src.p[0], src.p[1], src.p[2]}};
-    hipLaunchKernelGGL(filter_fused_kernel<T>, grid, dim3(64, 4), 0, s, g, dst, srcc, half2, parity, ncomp, passes);
-    LAUNCH_CHECK("filter_fused");
+    switch (passes) {
+      case 1: launch_filter_strips<T, 1>(g, ncomp, dst, srcc, half2, parity, s); break;
+      case 2: launch_filter_strips<T, 2>(g, ncomp, dst, srcc, half2, parity, s); break;
+      case 3: launch_filter_strips<T, 3>(g, ncomp, dst, srcc, half2, parity, s); break;
+      default: launch_filter_strips<T, 4>(g, ncomp, dst, srcc, half2, parity, s); break;
+    }
+    LAUNCH_CHECK("filter_strip");
     done += passes;
     in_A = !in_A;
   }
