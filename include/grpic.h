@@ -232,11 +232,13 @@ grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t 
                                  void* stream);
 
 /* Cell sort (a layout device, not part of the paper's method): writes the
- * slots of src into dst ordered by cell c = i1 * n_th + i2; empty slots and
- * slots with the leaving bit (already deposited) go last, emptied (tag 0).
- * The order of particles within one cell is unspecified.  The previous-
- * position arrays of dst are left as they were, and src's i1p is overwritten
- * (it holds each slot's rank within its cell during the sort): call it after
+ * live slots of src into dst ordered by cell c = i1 * n_th + i2; empty slots
+ * and slots with the leaving bit (already deposited) are dropped, and dst's
+ * slots after the live ones get tag 0 (their other arrays are left as they
+ * were).  The order of particles within one cell is unspecified.  The
+ * previous-position arrays of dst are left as they were, and src's i1p is
+ * overwritten for the live slots (it holds each slot's rank within its cell
+ * during the sort): call it after
  * the deposit that reads them, not between grpic_push and grpic_deposit.  src and dst must
  * have the same n and must not alias.  If n_live is non-null, waits for the
  * stream and stores the number of live slots (they occupy dst[0 .. n_live)).

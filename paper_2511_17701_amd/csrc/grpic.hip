@@ -368,7 +368,7 @@ grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_par
   const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
   const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
   const ParticleArraysT<T> a = arrays<T>(src), b = arrays<T>(dst);
-  const dim3 grank((unsigned)((src->n + (int64_t)kB * kSortPer - 1) / ((int64_t)kB * kSortPer)));
+  const dim3 grank((unsigned)((src->n + kRankBlock - 1) / kRankBlock));
   hipLaunchKernelGGL(sort_rank_kernel<T>, grank, dim3(kB), 0, s, g, a, w.off);
   LAUNCH_CHECK("sort_rank");
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, w.off, nkeys, w.sums);
@@ -381,6 +381,8 @@ grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_par
   LAUNCH_CHECK("copy_int");
   hipLaunchKernelGGL(sort_scatter_kernel<T>, dim3(blocks(src->n)), dim3(kB), 0, s, g, a, b, (const int*)w.off);
   LAUNCH_CHECK("sort_scatter");
+  hipLaunchKernelGGL(sort_clear_tail_kernel, dim3(1024), dim3(kB), 0, s, b.tag, dst->n, (const int*)w.live);
+  LAUNCH_CHECK("sort_clear_tail");
   return GRPIC_OK;
 }
 

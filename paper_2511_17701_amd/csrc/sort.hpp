@@ -4,7 +4,8 @@
 // cell adjacent in memory, so that a wavefront streams contiguous SoA data,
 // gathers from a few neighbouring field entries, and the deposit's per-block
 // footprint stays inside its shared-memory tile.  Empty and leaving slots get
-// the key n_cells and end up (emptied) after all live particles.
+// the key n_cells: they take no counter and no rank and are not moved; the
+// destination's slots after the live particles get tag 0.
 #pragma once
 
 #include "particles.hpp"
@@ -23,67 +24,76 @@ __device__ inline int sort_key(const Grid& g, const ParticleArraysT<T>& P, int64
   return i1 * g.n_th + i2;
 }
 
-// Runs of equal keys in consecutive lanes of a wavefront (particles arrive
-// nearly sorted, so a wave holds a few runs): one atomic per run.
-struct Run {
-  int key, head, len;  // this lane's key, its run's first lane, the run length
-  bool first;          // lane is the first of its run
-};
+// The rank pass takes kRankBlock consecutive slots per block of 256 threads
+// (8 per thread) and counts them in an LDS hash table of kRankTable cells.
+constexpr int kRankBlock = 2048, kRankTable = 4096;
 
-__device__ inline Run wave_run(int key) {
-  const int lane = threadIdx.x & 63;
-  const int prev = __shfl_up(key, 1, 64);
-  const bool first = lane == 0 || prev != key;
-  const unsigned long long heads = __ballot(first);
-  const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1);
-  Run r;
-  r.key = key;
-  r.first = first;
-  r.head = 63 - __clzll(heads & upto);
-  const unsigned long long after = lane == 63 ? 0ull : (heads >> (lane + 1));
-  r.len = first ? (after ? __ffsll((long long)after) : 64 - lane) : 0;
-  return r;
-}
+// Counts the live slots of each cell and gives every live slot its rank among
+// the slots of its cell.  Ten steps after a sort, neighbouring slots mostly
+// hold particles of different (nearby) cells, so runs of equal cells are
+// short (about 2 slots at 16 particles per cell), while a block's slots fall
+// in a few hundred distinct cells (C5: 262 of 2048, C6: 83).  So the block
+// counts its slots per cell in an LDS hash table (open addressing, linear
+// probing; a slot's rank inside the block is the count its cell had when it
+// was added), then claims each cell's ranks with one returning atomic on the
+// cell's global counter, and every slot takes its cell's base plus its rank
+// inside the block.  Empty and leaving slots (key n_cells) claim nothing.
+// The rank is written to the source's i1p (the previous position is scratch
+// between a push and its deposit, and the sort does not carry it), so the
+// scatter needs no atomics.
+__device__ inline int rank_hash(int key) { return (int)(((uint32_t)key * 0x9E3779B1u) >> 20); }  // 12 bits
 
-// Each wavefront of the rank pass takes kSortPer consecutive chunks of 64
-// slots (one slot per lane in each), so that one round trip of its counter
-// atomics covers kSortPer chunks.
-constexpr int kSortPer = 8;
-
-__device__ inline int64_t sort_first_slot() {
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  return wave * 64 * kSortPer + (threadIdx.x & 63);
-}
-
-// Counts the slots of each key and gives every slot its rank among the slots
-// of its key: the first lane of each run claims the run's ranks with one
-// returning atomic on the key's counter (all of a wavefront's kSortPer
-// claims are in flight before the first is waited for), the other lanes of
-// the run follow it.  The rank is written to the source's i1p (the previous
-// position is scratch between a push and its deposit, and the sort does not
-// carry it), so the scatter needs no atomics.
 template <class T>
 __global__ void __launch_bounds__(256) sort_rank_kernel(Grid g, ParticleArraysT<T> P, int* __restrict__ counts) {
-  const int64_t k0 = sort_first_slot();
-  int key[kSortPer], base[kSortPer];
-  Run r[kSortPer];
-#pragma unroll
-  for (int c = 0; c < kSortPer; ++c) {
-    const int64_t k = k0 + 64 * c;
-    key[c] = k < P.n ? sort_key(g, P, k) : -1;  // -1: past the end (own run)
+  static_assert(kRankTable == 4096, "rank_hash gives 12 bits");
+  __shared__ int tab_key[kRankTable];
+  __shared__ int tab_n[kRankTable];  // count in the block, then the cell's base
+  const int ncell = g.n_r * g.n_th;
+  const int64_t k0 = (int64_t)blockIdx.x * kRankBlock;
+  const int t = threadIdx.x;
+  for (int e = t; e < kRankTable; e += 256) {
+    tab_key[e] = -1;
+    tab_n[e] = 0;
   }
+  __syncthreads();
+  constexpr int kQ = kRankBlock / 256;
+  int entry[kQ], local[kQ];
 #pragma unroll
-  for (int c = 0; c < kSortPer; ++c) {
-    r[c] = wave_run(key[c]);
-    base[c] = 0;
-    if (r[c].first && key[c] >= 0) base[c] = atomicAdd(counts + key[c], r[c].len);
+  for (int q = 0; q < kQ; ++q) {
+    const int64_t k = k0 + q * 256 + t;  // consecutive threads on consecutive slots
+    const int key = k < P.n ? sort_key(g, P, k) : ncell;
+    entry[q] = -1;
+    if (key < ncell) {
+      // at most kRankBlock distinct keys in kRankTable cells: a free cell is
+      // always found
+      int h = rank_hash(key);
+      for (;;) {
+        const int old = atomicCAS(&tab_key[h], -1, key);
+        if (old == -1 || old == key) break;
+        h = (h + 1) & (kRankTable - 1);
+      }
+      entry[q] = h;
+      local[q] = atomicAdd(&tab_n[h], 1);
+    }
   }
+  __syncthreads();
+  // one claim per cell present in the block (all of a thread's claims in
+  // flight before the first is waited for)
+  constexpr int kE = kRankTable / 256;
+  int base[kE];
 #pragma unroll
-  for (int c = 0; c < kSortPer; ++c) {
-    const int b = __shfl(base[c], r[c].head, 64);
-    const int64_t k = k0 + 64 * c;
-    if (key[c] >= 0) P.i1p[k] = b + ((threadIdx.x & 63) - r[c].head);
+  for (int e = 0; e < kE; ++e) {
+    const int h = e * 256 + t;
+    const int key = tab_key[h];
+    base[e] = key >= 0 ? atomicAdd(counts + key, tab_n[h]) : 0;
   }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kE; ++e) tab_n[e * 256 + t] = base[e];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kQ; ++q)
+    if (entry[q] >= 0) P.i1p[k0 + q * 256 + t] = tab_n[entry[q]] + local[q];
 }
 
 // Exclusive scan of n ints in place, three phases: per-block scan (block sums
@@ -145,11 +155,13 @@ __global__ void scan_add_kernel(int* __restrict__ a, int64_t n, const int* __res
   if (i < n) a[i] += sums[i / kScanBlock];
 }
 
-// Moves slot k of S to slot off[key] + rank of D (rank from sort_rank_kernel,
-// in S.i1p; off the exclusive scan of the key counts); emptied slots get tag
-// 0.  No atomics: every load and store of a wavefront is independent, so the
-// pass streams at the memory system's rate.  The previous position (scratch
-// between a push and its deposit) is not carried.
+// Moves live slot k of S to slot off[key] + rank of D (rank from
+// sort_rank_kernel, in S.i1p; off the exclusive scan of the cell counts).  No
+// atomics: every load and store of a wavefront is independent, so the pass
+// streams at the memory system's rate.  Empty and leaving slots are not
+// moved (sort_clear_tail_kernel empties the destination after the live
+// slots).  The previous position (scratch between a push and its deposit) is
+// not carried.
 template <class T>
 __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArraysT<T> S, ParticleArraysT<T> D,
                                                            const int* __restrict__ off) {
@@ -157,11 +169,8 @@ __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArray
   if (k >= S.n) return;
   const int ncell = g.n_r * g.n_th;
   const int key = sort_key(g, S, k);
+  if (key == ncell) return;
   const int64_t o = (int64_t)off[key] + S.i1p[k];
-  if (key == ncell) {
-    D.tag[o] = 0;
-    return;
-  }
   D.i1[o] = S.i1[k];
   D.i2[o] = S.i2[k];
   D.dx1[o] = S.dx1[k];
@@ -172,6 +181,14 @@ __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArray
   D.w[o] = S.w[k];
   D.phi[o] = S.phi[k];
   D.tag[o] = S.tag[k];
+}
+
+// Tag 0 on the destination slots from the live count (*live, the scan's
+// total) to n: a grid-stride loop, so the launch can be small.
+__global__ void __launch_bounds__(256) sort_clear_tail_kernel(uint8_t* __restrict__ tag, int64_t n,
+                                                              const int* __restrict__ live) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)*live + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) tag[k] = 0;
 }
 
 }  // namespace grpic

@@ -300,6 +300,7 @@ def test_fp32_sort(G):
     for _ in range(3):
         c32.step(F32, P32)
     Q = c32.new_particles(P32["tag"].numel())
+    Q["tag"].fill_(1)  # the slots after the live ones must come back empty
     n_live = c32.sort(P32, Q, count=True)
     a, b = host(P32), host(Q)
     live_a = (a["tag"] != 0) & ((a["tag"] & 0x80) == 0)

@@ -577,8 +577,10 @@ def test_monopole_full_size_fused_launch(O, G, name):
 
 def test_sort_is_a_cell_ordered_permutation(O, G):
     """The cell sort moves every live slot unchanged (the multiset of particle
-    states is preserved bit for bit), orders live slots by cell, empties the
-    leaving and empty slots and puts them last; n_live is their count."""
+    states is preserved bit for bit), orders live slots by cell and drops the
+    leaving and empty slots; n_live is the live count, the destination's slots
+    after them get tag 0 and keep their other values (the destination starts
+    out filled with sentinels)."""
     import torch
     w = wl("c1_64", 40)
     prm, ctx = pair(O, G, w, charge_scale=0.1)
@@ -593,13 +595,16 @@ def test_sort_is_a_cell_ordered_permutation(O, G):
     Qg = ctx.new_particles(len(P["tag"]))
     for k in PREV:
         Qg[k].fill_(-7)
+    Qg["tag"].fill_(3)
+    Qg["u1"].fill_(-9.0)
     n_live = ctx.sort(Pg, Qg, count=True)
     for k in PREV:  # not carried: left as they were
         assert (Qg[k] == -7).all(), k
     Q = down(Qg)
     live_in = (P["tag"] != 0) & ((P["tag"] & 0x80) == 0)
-    assert n_live == int(live_in.sum())
+    assert n_live == int(live_in.sum()) and n_live < len(P["tag"])
     assert (Q["tag"][:n_live] != 0).all() and (Q["tag"][n_live:] == 0).all()
+    assert (Q["u1"][n_live:] == -9.0).all()
     key = Q["i1"][:n_live].astype(np.int64) * 40 + Q["i2"][:n_live]
     assert (np.diff(key) >= 0).all()
     cols = ["i1", "i2", "dx1", "dx2", "u1", "u2", "u3", "w", "phi", "tag"]  # not the scratch PREV
