@@ -462,9 +462,9 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
     const double B1 = interp<0, 1>(g, fp.B[0], i1, dx1, i2, dx2);
     const double B2 = interp<1, 0>(g, fp.B[1], i1, dx1, i2, dx2);
     const double B3 = interp<1, 1>(g, fp.B[2], i1, dx1, i2, dx2);
-    const double al = f.c.alpha;
-    const double E[3] = {al * D1 / f.s11, al * f.s22 * D2, al * f.s33 * (f.k13 * D1 + D3)};
-    const double B[3] = {al * B1 / f.s11, al * f.s22 * B2, al * f.s33 * (f.k13 * B1 + B3)};
+    const double al = f.c.alpha, ais11 = al * rcp(f.s11);
+    const double E[3] = {ais11 * D1, al * f.s22 * D2, al * f.s33 * (f.k13 * D1 + D3)};
+    const double B[3] = {ais11 * B1, al * f.s22 * B2, al * f.s33 * (f.k13 * B1 + B3)};
     const double kb = 0.25 * qm * g.dt;
     em_half(f, E, B, kb, u1, u2, u3);
     geodesic_u(g, f, d, u1, u2, u3, 1.0);
