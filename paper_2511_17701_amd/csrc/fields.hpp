@@ -279,65 +279,91 @@ __global__ void ampere_kernel(Grid g, Tables t, TriT<T> X, TriT<T> L, CTriT<T> H
 }
 
 // ---------------------------------------------------------------- boundaries
-// One block per plane row i in [-ng, n_r + ng - 1], the radial conditions
-// first, then the axis:
+// The radial conditions (bc_radial_kernel), then the axis (bc_axis_kernel):
 //  - constant layer inside the horizon (rows i <= n_f take row n_f + 1) and
 //    the absorbing layer (F <- F - lambda (F - F_init), lambda a cubic ramp
 //    over the last n_absorb cells), on every column;  half1[c] = staggering of
 //    component c in x1;
 //  - axis reflection (Sec. 3.3.3): r-components even, theta and phi
-//    components odd, ghost columns from the row's own updated values; with
+//    components odd, ghost columns from the row's updated values; with
 //    zero_comp, the theta component of B (B^2) or the phi component of D (D^3)
 //    vanishes on the axis rows.  half2[c] = staggering in x2.
-// Rows i <= n_f read row n_f + 1, which neither layer changes; the axis pass of
-// that row may run first and only rewrites entries that each row's own axis
-// pass rewrites again.
-// With radial = 0 only the axis reflection is applied (initial data).
+// Rows i <= n_f read row n_f + 1, which neither layer changes.  Initial data
+// take only the axis reflection.
+
+// Rows of the two layers: the horizon rows [-ng, n_f] and the absorbing rows
+// [abs_begin, n_r + ng) (a row in both is a horizon row).
+struct BcRows {
+  int n_hor, n_abs;  // number of horizon / absorbing rows
+  int abs_begin;     // first absorbing row
+};
+
+__host__ __device__ inline BcRows bc_rows(const Grid& g) {
+  BcRows b;
+  const int top = g.n_r + g.ng;                  // one past the last plane row
+  const int hor_end = min(g.n_filter + 1, top);  // horizon rows: i <= n_f
+  b.abs_begin = g.n_absorb > 0 ? max(hor_end, g.n_r - g.n_absorb) : top;
+  b.n_hor = hor_end + g.ng;
+  b.n_abs = top - b.abs_begin;
+  return b;
+}
+
+// One thread per (layer row, stored column): grid (ceil(ld / 256), n_hor +
+// n_abs), 256 threads.
 template <class T>
-__global__ void bc_kernel(Grid g, TriT<T> X, TriT<T> L, CTriT<T> X0, int3 half1, int3 half2, int zero_comp,
-                          int radial) {
-  const int i = (int)blockIdx.x - g.ng;
+__global__ void bc_radial_kernel(Grid g, TriT<T> X, TriT<T> L, CTriT<T> X0, int3 half1) {
+  const BcRows rows = bc_rows(g);
+  const int r = (int)blockIdx.y;
+  const bool horizon = r < rows.n_hor;
+  const int i = horizon ? r - g.ng : rows.abs_begin + (r - rows.n_hor);
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x) - g.ng;
+  if (j >= g.n_th + g.ng) return;
   const int h1[3] = {half1.x, half1.y, half1.z};
-  const int h2[3] = {half2.x, half2.y, half2.z};
   const bool comp = sizeof(T) == 4 && L.p[0];
-  const bool horizon = i <= g.n_filter;
   const double x0 = (double)(g.n_r - g.n_absorb);
-  if (radial && (horizon || (g.n_absorb > 0 && (double)i + 0.5 > x0))) {
-    for (int j = (int)threadIdx.x - g.ng; j < g.n_th + g.ng; j += blockDim.x) {
-      const int64_t o = ix(g, i, j);
+  const int64_t o = ix(g, i, j);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (horizon) {
-          const int64_t src = ix(g, g.n_filter + 1, j);
-          X.p[c][o] = X.p[c][src];
-          if (comp) L.p[c][o] = L.p[c][src];
+  for (int c = 0; c < 3; ++c) {
+    if (horizon) {
+      const int64_t src = ix(g, g.n_filter + 1, j);
+      X.p[c][o] = X.p[c][src];
+      if (comp) L.p[c][o] = L.p[c][src];
+    } else {
+      const double x = (double)i + 0.5 * h1[c];
+      if (x > x0) {
+        const double sr = fmin((x - x0) / g.n_absorb, 1.0);
+        const double lam = sr * sr * sr;
+        if (comp) {
+          const double v = (double)X.p[c][o] + (double)L.p[c][o];
+          const double w = v - lam * (v - X0.p[c][o]);
+          const T h = (T)w;
+          X.p[c][o] = h;
+          L.p[c][o] = (T)(w - (double)h);
         } else {
-          const double x = (double)i + 0.5 * h1[c];
-          if (x > x0) {
-            const double sr = fmin((x - x0) / g.n_absorb, 1.0);
-            const double lam = sr * sr * sr;
-            if (comp) {
-              const double v = (double)X.p[c][o] + (double)L.p[c][o];
-              const double w = v - lam * (v - X0.p[c][o]);
-              const T h = (T)w;
-              X.p[c][o] = h;
-              L.p[c][o] = (T)(w - (double)h);
-            } else {
-              X.p[c][o] = X.p[c][o] - lam * (X.p[c][o] - X0.p[c][o]);
-            }
-          }
+          X.p[c][o] = X.p[c][o] - lam * (X.p[c][o] - X0.p[c][o]);
         }
       }
     }
   }
-  __syncthreads();
-  // one lane per (component, ghost column): the 2 ng ghost columns of each
-  // component, each the reflection of its mirror column (node rows run 0..n,
-  // half rows 0..n-1); the mirrors are interior columns, which this pass only
-  // zeroes at j = 0, n for zero_comp, and never reads
-  const int t = threadIdx.x;
-  if (t >= 3 * 2 * g.ng) return;
-  const int c = t / (2 * g.ng), q = t % (2 * g.ng);
+}
+
+// 6 ng lanes per plane row, one per (component, ghost column): bc_axis_rows
+// rows per block of `threads`.
+__host__ __device__ inline int bc_axis_rows(const Grid& g, int threads) { return threads / (6 * g.ng); }
+
+// Axis reflection of every plane row: each ghost column of a component is
+// the reflection of its mirror column (node rows run 0..n, half rows
+// 0..n-1); the mirrors are interior columns, which this pass only zeroes at
+// j = 0, n for zero_comp, and never reads.
+template <class T>
+__global__ void bc_axis_kernel(Grid g, TriT<T> X, TriT<T> L, int3 half2, int zero_comp) {
+  const int lanes = 6 * g.ng, rpb = bc_axis_rows(g, (int)blockDim.x);
+  const int t = (int)threadIdx.x;
+  const int i = (int)blockIdx.x * rpb + t / lanes - g.ng;
+  if (t >= rpb * lanes || i >= g.n_r + g.ng) return;
+  const int h2[3] = {half2.x, half2.y, half2.z};
+  const bool comp = sizeof(T) == 4 && L.p[0];
+  const int c = (t % lanes) / (2 * g.ng), q = (t % lanes) % (2 * g.ng);
   const int n = g.n_th;
   T* C = X.p[c];
   const int j = q < g.ng ? -1 - q : n - h2[c] + 1 + (q - g.ng);  // ghost column

@@ -157,14 +157,22 @@ const dim3 kBlock2(64, 4);
 const int3 kStagD1 = {1, 0, 0}, kStagD2 = {0, 1, 0};  // x1 / x2 staggering of D^i, J^i
 const int3 kStagB1 = {0, 1, 1}, kStagB2 = {1, 0, 1};  // x1 / x2 staggering of B^i
 
-// boundaries of an updated triple: horizon layer + absorbing layer, then axis
+// boundaries of an updated triple: horizon layer + absorbing layer (radial =
+// 1), then the axis
 template <class T>
 grpic_status field_bc(grpic_ctx* c, TriT<T> X, TriT<T> L, CTriT<T> X0, bool is_B, hipStream_t s,
                       int radial = 1) {
   const Grid& g = c->g;
-  hipLaunchKernelGGL(bc_kernel<T>, dim3(g.n_r + 2 * g.ng), dim3(kB), 0, s, g, X, L, X0,
-                     is_B ? kStagB1 : kStagD1, is_B ? kStagB2 : kStagD2, is_B ? 1 : 2, radial);
-  LAUNCH_CHECK("bc");
+  const BcRows rows = bc_rows(g);
+  if (radial && rows.n_hor + rows.n_abs > 0) {
+    const dim3 grid((unsigned)((g.ld + kB - 1) / kB), (unsigned)(rows.n_hor + rows.n_abs));
+    hipLaunchKernelGGL(bc_radial_kernel<T>, grid, dim3(kB), 0, s, g, X, L, X0, is_B ? kStagB1 : kStagD1);
+    LAUNCH_CHECK("bc_radial");
+  }
+  const int rpb = bc_axis_rows(g, kB);
+  hipLaunchKernelGGL(bc_axis_kernel<T>, dim3((unsigned)((g.n_r + 2 * g.ng + rpb - 1) / rpb)), dim3(kB), 0, s, g, X,
+                     L, is_B ? kStagB2 : kStagD2, is_B ? 1 : 2);
+  LAUNCH_CHECK("bc_axis");
   return GRPIC_OK;
 }
 
