@@ -16,30 +16,35 @@ struct DiagAcc {
 };
 
 constexpr int kDiagBlock = 256;
+constexpr int kDiagMaxBlocks = 2048;  // grid-stride: few blocks, so few atomics on the accumulators
 
+// Per-slot diagnostics over a grid-stride loop (at most kDiagMaxBlocks
+// blocks): each thread accumulates the counts and sums of its slots, then a
+// wavefront reduction and one atomic per block and counter (the accumulators
+// share one cache line, whose atomics the memory system takes one at a time).
 template <class T, int SER>
 __global__ void __launch_bounds__(kDiagBlock)
 diag_particles_kernel(Grid g, Tables tab, ParticleArraysT<T> P, double B0, T* __restrict__ Eout,
                       T* __restrict__ Lout, DiagAcc* acc) {
   __shared__ unsigned long long sc[8][kDiagBlock / 64];
   __shared__ double ss[8][kDiagBlock / 64];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (k < P.n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P.n; k += stride) {
     const uint8_t t = P.tag[k];
     double E = __builtin_nan(""), L = __builtin_nan("");
     if (t == 0) {
-      cnt[5] = 1;
+      ++cnt[5];
     } else if (t & kInvalid) {
-      cnt[6] = 1;
+      ++cnt[6];
     } else {
       const int sp = t & kSpecies;
-      if (t & kLeaving) cnt[4] = 1; else cnt[sp] = 1;
+      if (t & kLeaving) ++cnt[4]; else ++cnt[sp];
       const double u1 = P.u1[k], u2 = P.u2[k], u3 = P.u3[k];
       const double d1 = P.dx1[k], d2 = P.dx2[k];
       if (!(isfinite(u1) && isfinite(u2) && isfinite(u3) && isfinite(d1) && isfinite(d2)))
-        cnt[6] = 1;
+        ++cnt[6];
       const double x1 = 0.5 * (((double)P.i1p[k] + P.dx1p[k]) + ((double)P.i1[k] + d1));
       const double x2 = 0.5 * (((double)P.i2p[k] + P.dx2p[k]) + ((double)P.i2[k] + d2));
       // r, the clamped sin and cos at the time-centred position, once, for the
@@ -57,8 +62,8 @@ diag_particles_kernel(Grid g, Tables tab, ParticleArraysT<T> P, double B0, T* __
       E = m.alpha * gamma_of(m, u1, u2, u3, mass2_of(t)) - m.beta1 * u1 - qm * w.A0;
       L = u3 + qm * w.A3;
       if (!(t & kLeaving)) {
-        sum[sp] = E;
-        sum[4 + sp] = L;
+        sum[sp] += E;
+        sum[4 + sp] += L;
       }
     }
     if (Eout) Eout[k] = E;
@@ -137,8 +142,10 @@ __global__ void __launch_bounds__(256) charge_kernel(Grid g, ParticleArraysT<T> 
 // take the polar-cap form of Sec. 3.3.2, A_{i+1/2} D^1(i+1/2) - A_{i-1/2}
 // D^1(i-1/2) +- sqrt(h) D^2 - 2 pi rho with the two-sided axis-row charge (the
 // D^2 flux enters with the opposite orientation at theta = pi).
+constexpr int kGaussWaves = 4;  // wavefronts per block of gauss_kernel (64 x 4 threads)
+
 template <class T, bool kQ>
-__global__ void gauss_kernel(Grid g, Tables t, double polar_k, int i_hi, const T* __restrict__ D1,
+__global__ void __launch_bounds__(256) gauss_kernel(Grid g, Tables t, double polar_k, int i_hi, const T* __restrict__ D1,
                              const T* __restrict__ D2, const T* __restrict__ Q,
                              T* __restrict__ res, DiagAcc* acc) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,13 +179,22 @@ __global__ void gauss_kernel(Grid g, Tables t, double polar_k, int i_hi, const T
     if (res) res[o] = r;
     rmax = fabs(r);
   }
+  // wavefront maxima, then the block's (one atomic per block and maximum)
+  __shared__ double bm[2][kGaussWaves];
   for (int off = 32; off > 0; off >>= 1) {
     rmax = fmax(rmax, __shfl_down(rmax, off, 64));
     smax = fmax(smax, __shfl_down(smax, off, 64));
   }
-  if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0) {
-    atomicMax(&acc->gmax_bits, (unsigned long long)__double_as_longlong(rmax));
-    atomicMax(&acc->gscale_bits, (unsigned long long)__double_as_longlong(smax));
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  if (tid % 64 == 0) {
+    bm[0][tid / 64] = rmax;
+    bm[1][tid / 64] = smax;
+  }
+  __syncthreads();
+  if (tid < 2) {
+    double m = bm[tid][0];
+    for (int w = 1; w < kGaussWaves; ++w) m = fmax(m, bm[tid][w]);
+    atomicMax(tid == 0 ? &acc->gmax_bits : &acc->gscale_bits, (unsigned long long)__double_as_longlong(m));
   }
 }
 

@@ -503,16 +503,15 @@ __device__ inline double filter_row_sum(T a, const FilterAxis& ax) {
 // kept rows inside the strip).  Otherwise the strips are placed so that the
 // kept rows are a strip's first or last staged row, which no pass updates.
 template <class T, int P, int kSR, bool kAxis, bool kRows>
-__device__ __forceinline__ void filter_strip_comp(const Grid& g, T* __restrict__ x, const T* __restrict__ s, int J, bool col,
-                                         bool out, int ifirst, int rlo, int rhi, const FilterAxis& ax) {
+__device__ __forceinline__ void filter_strip_comp(const Grid& g, T* __restrict__ x, const T* __restrict__ s,
+                                                  int J, bool col, bool out, int ifirst, int rlo, int rhi,
+                                                  const FilterAxis& ax) {
   constexpr int R = kSR + 2 * P;
   // one wavefront-uniform base (the strip's first staged row) and 32-bit
   // per-lane byte offsets (a strip spans R rows: far below 4 GiB)
   const int64_t row0 = (int64_t)(ifirst + g.ng) * g.ld;
   const char* __restrict__ sb = (const char*)(s + row0);
-  const uint32_t rowb = (uint32_t)(g.ld * sizeof(T));
-  uint32_t lb = (uint32_t)(J * sizeof(T));
-  asm volatile("" : "+v"(lb));  // row offsets computed here, not hoisted out of the component loop
+  const uint32_t rowb = (uint32_t)(g.ld * sizeof(T)), lb = (uint32_t)(J * sizeof(T));
   T v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -542,7 +541,8 @@ __device__ __forceinline__ void filter_strip_comp(const Grid& g, T* __restrict__
     }
   }
   if (out) {
-    // recompute the offsets here instead of keeping the loads' alive
+    // an opaque copy of the lane offset: the stores recompute their row
+    // offsets instead of keeping the loads' live through the passes
     uint32_t lbs = lb;
     asm volatile("" : "+v"(lbs));
     char* __restrict__ db = (char*)(x + row0);
@@ -574,9 +574,9 @@ __host__ __device__ inline int filter_strips_r(int nrow) {
 
 // P passes of S into X, plane blockIdx.z.  Grid: (filter_strips_theta(ld),
 // ceil(filter_strips_r / 4), number of planes); 256 threads = 4 wavefronts on
-// consecutive row strips.  Strip s stages rows from min(s kSR - ng, n_r + ng - R) (kRows:
-// s kSR - ng - P) and writes the rows it has exact: from its first row in
-// the first strip, to its last in the last one.  The register budget (four
+// consecutive row strips.  Strip s stages rows from min(s kSR - ng,
+// n_r + ng - R) (kRows: s kSR - ng - P) and writes the rows it has exact:
+// from its first row in the first strip, to its last in the last one.  The register budget (four
 // wavefronts per SIMD, two for a single pass) keeps the compiler from
 // computing every row sum of a pass ahead of the radial combinations.
 template <class T, int P, int kSR, bool kRows>

@@ -517,7 +517,7 @@ grpic_status diagnostics_impl(grpic_ctx* c, const grpic_fields* F, const grpic_p
                               void* E_out, void* L_out, void* gauss_res, hipStream_t s) {
   const Grid& g = c->g;
   if (P->n > 0) {
-    const dim3 gd(blocks(P->n)), bd(kDiagBlock);
+    const dim3 gd(std::min(blocks(P->n), (unsigned)kDiagMaxBlocks)), bd(kDiagBlock);
     switch (g.ser) {
       case 2: hipLaunchKernelGGL((diag_particles_kernel<T, 2>), gd, bd, 0, s, g, c->tab, arrays<T>(P), B0, (T*)E_out, (T*)L_out, c->acc); break;
       case 1: hipLaunchKernelGGL((diag_particles_kernel<T, 1>), gd, bd, 0, s, g, c->tab, arrays<T>(P), B0, (T*)E_out, (T*)L_out, c->acc); break;
