@@ -201,7 +201,10 @@ grpic_status filter_passes(grpic_ctx* c, TriT<T> A, TriT<T> B, int ncomp, int3 h
   const Grid& g = c->g;
   bool in_A = true;  // where the latest result is
   for (int done = 0; done < g.n_filter;) {
-    const int passes = std::min(kFMaxPasses, g.n_filter - done);
+    // at most kFMaxPasses per launch, and a single-pass launch only for n_f = 1
+    // (5 passes as 3 + 2: the single-pass kernel needs the most registers)
+    int passes = std::min(kFMaxPasses, g.n_filter - done);
+    if (g.n_filter - done - passes == 1) passes -= 1;
     const TriT<T>& dst = in_A ? B : A;
     const TriT<T>& src = in_A ? A : B;
     CTriT<T> srcc{{src.p[0], src.p[1], src.p[2]}};

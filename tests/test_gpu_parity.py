@@ -343,19 +343,21 @@ def test_push_deposit_fused_equals_separate(O, G):
 
 # ---------------------------------------------------------------- fields
 
-@pytest.mark.parametrize("n_r,n_th,n_f", [(48, 48, 2), (40, 126, 3), (36, 61, 5), (24, 64, 1), (20, 40, 4),
-                                         (30, 100, 2), (33, 70, 3), (100, 130, 4), (131, 57, 4)])
+@pytest.mark.parametrize("n_r,n_th,n_f", [(48, 48, 2), (40, 126, 3), (36, 61, 5), (36, 80, 4), (24, 64, 1),
+                                         (20, 40, 4), (30, 100, 2), (33, 70, 3), (100, 130, 4), (131, 57, 4),
+                                         (40, 70, 1)])
 def test_field_advance_parity(O, G, n_r, n_th, n_f):
     """Both field stages from a perturbed Wald state with currents, n_f filter
-    passes and a 6-cell absorbing layer.  The filter's wavefront strips are
-    64 stored columns by 32 rows plus a halo of one row per pass: the grids
-    take planes with fewer rows than a strip stages (24 x 64, 20 x 40, 30 x
-    100, 33 x 70: rows checked one by one), with exactly one strip of rows (36
-    x 61), with several and a last strip shifted to end at the last row (100,
-    131), three column strips with the last one shifted (126, 130: the far
-    axis in an overlapping strip), two strips that overlap almost entirely
-    (61: 65 stored columns), one strip narrower than a wavefront (57: 61), and
-    the passes in two launches (n_f = 5: four, then one)."""
+    passes and a 6-cell absorbing layer.  The filter's wavefront strips are 64
+    stored columns by 32 rows plus a halo of one row per pass.  The grids take
+    planes with fewer rows than a strip stages (24 x 64, 20 x 40, 30 x 100,
+    33 x 70: rows checked one by one), with exactly one strip of rows (36 x 80
+    at 4 passes), with several and a last strip shifted to end at the last row
+    (100, 131), three column strips with the last one shifted (126, 130: the
+    far axis in an overlapping strip), two strips that overlap almost entirely
+    (61: 65 stored columns), one strip narrower than a wavefront (57: 61), a
+    single pass on a plane of more rows than a strip stages (40 x 70), and the
+    passes in two launches (n_f = 5: three, then two)."""
     w = wl("c1_64").scaled(n_r, n_th)
     prm, ctx = pair(O, G, w, charge_scale=0.05, n_filter=n_f, n_absorb=6)
     F = O.fields_init_wald(prm, w.B0)
