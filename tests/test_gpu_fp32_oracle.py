@@ -10,7 +10,10 @@ same numbers), so the comparison measures what one FP32 step adds:
     bars, and with the FP64 convergence test of the implicit iterations on
     (iter_tol > 0; the oracle runs its fixed count);
   - one full PIC step with 4 filter passes and the absorbing layer (C5 recipe
-    at 128^2): D, B, J per plane within 1e-5 of their largest value.
+    at 128^2 and 32^2): D, B, J per plane within 1e-5 of their largest value;
+  - the benchmark's workload at full size (C5, 4096^2, 2.68e8 particles) in
+    the benchmark's launch configuration: 20,000 sampled slots after one
+    fused pass, to the particle bars above.
 Momenta scales c_i are the code-unit scales dr/dx1, r dth, r sin(theta).
 """
 import math
@@ -134,3 +137,45 @@ def test_fp32_full_step_against_oracle(O, G, n):
     assert x_err.max() <= 3e-6
     assert u_err.max() <= 1e-5 and np.median(u_err) <= 1e-6
     assert max(ferr) <= 1e-5
+
+
+def test_c5_fp32_fused_launch_sampled(O, G):
+    """The benchmark's workload at full size (C5: 4096^2, 16 ppc = 2.68e8
+    particles, FP32) in the launch configuration the benchmark times (the
+    single-precision series kernel of fine grids): after one fused push +
+    deposit pass, a sample of 20,000 slots matches the oracle's push of the
+    same pre-push states (widened to FP64) in the same widened fields, to the
+    bars of the 256^2 case."""
+    import torch
+    from paper_2511_17701_amd.workloads import WORKLOADS
+    w = WORKLOADS["c5_4096"]
+    c = G.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, cfl=w.cfl, n_iter=w.n_iter,
+                  small_angle=w.small_angle, charge_scale=w.charge_scale, n_filter=w.n_filter,
+                  n_absorb=w.n_absorb, precision=G.GRPIC_FP32)
+    prm = O.Params.make(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, c.dt, n_iter=w.n_iter,
+                        small_angle=w.small_angle, charge_scale=w.charge_scale,
+                        n_filter=w.n_filter, n_absorb=w.n_absorb)
+    n = w.n_particles
+    Pg = c.new_particles(n)
+    c.particles_init(Pg, 0, w.ppc, w.T, 0, w.seed)
+    Fg = c.new_fields()
+    c.fields_init_wald(Fg, w.B0)
+    idx = np.sort(np.random.default_rng(3).choice(n, 20000, replace=False))
+    it = torch.from_numpy(idx).cuda()
+    S = {k: v.index_select(0, it).cpu().numpy() for k, v in Pg.items()}
+    So = {k: (v.astype(np.float64) if v.dtype.kind == "f" else v) for k, v in S.items()}
+    Fo = Fg[:33].double().cpu().numpy()
+    c.push_deposit(Fg, Pg)
+    torch.cuda.synchronize()
+    O.push(prm, Fo, So)
+    Pd = {k: v.index_select(0, it) for k, v in Pg.items()}
+    x_err, u_err = particle_errors(w, Pd, So)
+    # cells whose inner edge lies below r = 3M take the FP64 metric in the push
+    dxi = math.log(w.r_max / w.r_min) / w.n_r
+    i_fp64 = math.ceil(math.log(3.0 * w.M / w.r_min) / dxi)
+    report(f"c5 full size, fused launch, 20000 sampled slots ({int((S['i1'] < i_fp64).sum())} "
+           f"in FP64-metric cells)", x_err, u_err)
+    assert x_err.max() <= 3e-6
+    assert u_err.max() <= 1e-5 and np.median(u_err) <= 1e-6
+    del Pg, Fg, Fo
+    torch.cuda.empty_cache()
