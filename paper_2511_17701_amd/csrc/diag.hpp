@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) charge_kernel(Grid g, ParticleArraysT<T> 
 // take the polar-cap form of Sec. 3.3.2, A_{i+1/2} D^1(i+1/2) - A_{i-1/2}
 // D^1(i-1/2) +- sqrt(h) D^2 - 2 pi rho with the two-sided axis-row charge (the
 // D^2 flux enters with the opposite orientation at theta = pi).
-constexpr int kGaussWaves = 4;  // wavefronts per block of gauss_kernel (64 x 4 threads)
+constexpr int kGaussWaves = 4;  // wavefronts per block of gauss_kernel (256 threads)
 
 template <class T, bool kQ>
 __global__ void __launch_bounds__(256) gauss_kernel(Grid g, Tables t, double polar_k, int i_hi, const T* __restrict__ D1,

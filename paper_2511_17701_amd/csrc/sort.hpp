@@ -158,35 +158,45 @@ __global__ void scan_add_kernel(int* __restrict__ a, int64_t n, const int* __res
   if (i < n) a[i] += sums[i / kScanBlock];
 }
 
+// Source loads of the scatter: non-temporal in the single-precision form,
+// which leaves the L2 to the destination lines that the wavefronts fill in
+// pieces (measured at 4096^2, 16 particles per cell: -3 % for a sort after 10
+// steps of motion, -18 % for a re-sort); plain in double precision, where the
+// same loads gained nothing (4096^2 at 16 and 2048^2 at 90 particles per
+// cell: the same or up to 5 % slower, against a spread of several per cent
+// between single sorts).
+template <class T, class V>
+__device__ inline V scatter_load(const V* p) {
+  if constexpr (sizeof(T) == 4) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 // Moves live slot k of S to slot off[key] + rank of D (rank from
 // sort_rank_kernel, in S.i1p; off the exclusive scan of the cell counts).  No
 // atomics: every load and store of a wavefront is independent, so the pass
-// streams at the memory system's rate.  The source is read once, with
-// non-temporal loads, which leave the L2 to the destination lines that the
-// wavefronts fill in pieces (measured at 4096^2, 16 particles per cell: -3 %
-// for a sort after 10 steps of motion, -18 % for a re-sort).  Empty and
-// leaving slots are not moved (sort_clear_tail_kernel empties the destination
-// after the live slots).  The previous position (scratch between a push and
-// its deposit) is not carried.
+// streams at the memory system's rate.  Empty and leaving slots are not
+// moved (sort_clear_tail_kernel empties the destination after the live
+// slots).  The previous position (scratch between a push and its deposit) is
+// not carried.
 template <class T>
 __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArraysT<T> S, ParticleArraysT<T> D,
                                                            const int* __restrict__ off) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= S.n) return;
-  const uint8_t t = __builtin_nontemporal_load(S.tag + k);
-  const int i1 = __builtin_nontemporal_load(S.i1 + k), i2 = __builtin_nontemporal_load(S.i2 + k);
+  const uint8_t t = scatter_load<T>(S.tag + k);
+  const int i1 = scatter_load<T>(S.i1 + k), i2 = scatter_load<T>(S.i2 + k);
   const int key = cell_key(g, t, i1, i2);
   if (key == g.n_r * g.n_th) return;
-  const int64_t o = (int64_t)off[key] + __builtin_nontemporal_load(S.i1p + k);
+  const int64_t o = (int64_t)off[key] + scatter_load<T>(S.i1p + k);
   D.i1[o] = i1;
   D.i2[o] = i2;
-  D.dx1[o] = __builtin_nontemporal_load(S.dx1 + k);
-  D.dx2[o] = __builtin_nontemporal_load(S.dx2 + k);
-  D.u1[o] = __builtin_nontemporal_load(S.u1 + k);
-  D.u2[o] = __builtin_nontemporal_load(S.u2 + k);
-  D.u3[o] = __builtin_nontemporal_load(S.u3 + k);
-  D.w[o] = __builtin_nontemporal_load(S.w + k);
-  D.phi[o] = __builtin_nontemporal_load(S.phi + k);
+  D.dx1[o] = scatter_load<T>(S.dx1 + k);
+  D.dx2[o] = scatter_load<T>(S.dx2 + k);
+  D.u1[o] = scatter_load<T>(S.u1 + k);
+  D.u2[o] = scatter_load<T>(S.u2 + k);
+  D.u3[o] = scatter_load<T>(S.u3 + k);
+  D.w[o] = scatter_load<T>(S.w + k);
+  D.phi[o] = scatter_load<T>(S.phi + k);
   D.tag[o] = t;
 }
 
