@@ -56,6 +56,10 @@ def parse():
                     help="separate push and deposit passes (default: one fused pass)")
     ap.add_argument("--sort-every", type=int, default=10,
                     help="cell-sort the particles every k steps (0: never)")
+    ap.add_argument("--sort-rank", choices=["auto", "fused", "separate"], default="auto",
+                    help="the sort's rank pass in the fused pass of the sort step (grpic_push_deposit_ranked) "
+                         "or as a kernel of its own; auto: fused in FP64, separate in FP32 (the faster of the "
+                         "two in each form at 4096^2 and 2048^2)")
     ap.add_argument("--iter-tol", type=float, default=0.0,
                     help="FP64 convergence test of the implicit iterations (0: fixed count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -228,6 +232,11 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}))
 
 
+def rank_in_pass(precision):
+    """Whether the sort step's fused pass also does the sort's rank pass."""
+    return ARGS.sort_rank == "fused" or (ARGS.sort_rank == "auto" and precision == "fp64")
+
+
 class Run:
     """A context, a field set and a particle set of a workload in one form."""
 
@@ -253,7 +262,12 @@ class Run:
         torch.cuda.synchronize()
 
     def step(self, ev=None):
+        """One step; on a sort step the fused pass also ranks the slots for
+        the sort (grpic_push_deposit_ranked, then grpic_sort_ranked).
+        Returns whether the fused pass ranked."""
         ctx, F, P, w = self.ctx, self.F, self.P, self.w
+        sort_now = ARGS.sort_every > 0 and (self.n + 1) % ARGS.sort_every == 0
+        ranked = sort_now and not ARGS.unfused and rank_in_pass(self.precision)
         if w.full_step:
             ctx.field_advance(F, self.G.PRE_PUSH)
         if ev is not None:
@@ -261,7 +275,7 @@ class Run:
         if ARGS.unfused:
             ctx.push(F, P)
         else:
-            ctx.push_deposit(F, P)
+            ctx.push_deposit(F, P, ranked=ranked)
         if ev is not None:
             ev[1]()
         if ARGS.unfused:
@@ -271,9 +285,10 @@ class Run:
         if w.full_step:
             ctx.field_advance(F, self.G.POST_DEPOSIT)
         self.n += 1
-        if ARGS.sort_every > 0 and self.n % ARGS.sort_every == 0:
-            ctx.sort(self.P, self.Q)
+        if sort_now:
+            ctx.sort(self.P, self.Q, ranked=ranked)
             self.P, self.Q = self.Q, self.P
+        return ranked
 
     def timed(self, steps, warmup):
         """Average ms per step, per-step kernel times (HIP events on the
@@ -291,12 +306,17 @@ class Run:
         t0, t1 = he.create(), he.create()
         torch.cuda.synchronize()
         he.record(t0)
-        for k in range(steps):
-            self.step([lambda e=e: he.record(e) for e in evs[k]])
+        ranked = [self.step([lambda e=e: he.record(e) for e in evs[k]]) for k in range(steps)]
         he.record(t1)
         torch.cuda.synchronize()
         total = he.elapsed(t0, t1)
-        k1 = sum(he.elapsed(e[0], e[1]) for e in evs) / steps
+        t_pass = [he.elapsed(e[0], e[1]) for e in evs]
+        # the fused pass of the steps without the rank pass (the kernel the
+        # roofline and the profiles describe), the ranked one separately
+        plain = [t for t, r in zip(t_pass, ranked) if not r] or t_pass
+        self.k1_all = sum(t_pass) / steps
+        self.k1_ranked = (sum(t for t, r in zip(t_pass, ranked) if r) / sum(ranked)) if any(ranked) else None
+        k1 = sum(plain) / len(plain)
         k2 = sum(he.elapsed(e[1], e[2]) for e in evs) / steps if ARGS.unfused else 0.0
         for e in evs:
             for x in e[:3 if ARGS.unfused else 2]:
@@ -445,10 +465,15 @@ def main():
                    "n_absorb": w.n_absorb, "precision": precision,
                    "charge_scale": w.charge_scale,
                    "pass": "unfused" if ARGS.unfused else "fused",
-                   "sort_every": ARGS.sort_every, "iter_tol": ARGS.iter_tol},
+                   "sort_every": ARGS.sort_every,
+                   "sort_rank": "in the fused pass" if not ARGS.unfused and rank_in_pass(precision)
+                   else "separate pass",
+                   "iter_tol": ARGS.iter_tol},
         "roofline": roofline,
         "kernels_ms_per_step": {kname: k1, **({"deposit": k2} if ARGS.unfused else {}),
-                                "fields_sort_rest": ms - k1 - k2},
+                                **({"push_deposit_ranked (sort steps)": run.k1_ranked}
+                                   if run.k1_ranked is not None else {}),
+                                "fields_sort_rest": ms - run.k1_all - k2},
         "live_particles": [live0, live1],
     }
     if not ARGS.no_forms:

@@ -207,6 +207,23 @@ grpic_status grpic_deposit(grpic_ctx* ctx, const grpic_particles* P, const grpic
 grpic_status grpic_push_deposit(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,
                                 void* stream);
 
+/* grpic_push_deposit that also does the first pass of the cell sort (a
+ * layout device, not part of the paper's method) on the state it leaves: per
+ * block of the pass, the live slots are counted per cell, each live slot's
+ * rank within its cell goes to P's i1p, and the cells' counts to scratch of
+ * the context (n_r n_th + 1 counters, plus the scan's block sums, allocated
+ * on the first call).  Complete the sort with grpic_sort_ranked on the same
+ * particle set: the two give what grpic_push_deposit then grpic_sort give
+ * (the particle state the same, the order within a cell unspecified).  At
+ * most 2^31 - 1 slots (GRPIC_EINVAL).  P's previous-position arrays other
+ * than i1p are left as they were.  Each block of the pass waits for its
+ * cells' claims at its end: measured on MI355X, the double-precision pass at
+ * 2048^2 with 90 particles per cell grows by a third of the separate rank
+ * pass's time, while the single-precision pass at 4096^2 with 16 per cell
+ * grows by more than that pass takes (grpic_sort is then the faster). */
+grpic_status grpic_push_deposit_ranked(grpic_ctx* ctx, const grpic_fields* F, const grpic_particles* P,
+                                       void* stream);
+
 /* Adjoint of one grpic_push step in a frozen field (the differentiation form;
  * GRPIC_FP64 contexts only).  The particle state is s = (x1, x2, u1, u2, u3),
  * x = cell + offset; the field set F holds B0 times a fixed field F1 (planes D
@@ -245,6 +262,18 @@ grpic_status grpic_field_advance(grpic_ctx* ctx, const grpic_fields* F, int32_t 
  * Uses scratch owned by the context (n_r n_th + 1 counters). */
 grpic_status grpic_sort(grpic_ctx* ctx, const grpic_particles* src, const grpic_particles* dst,
                         int64_t* n_live, void* stream);
+
+/* The cell sort of src into dst (as grpic_sort: same arguments, results and
+ * n_live) from the counts and ranks that the last grpic_push_deposit_ranked
+ * of this context left for src; it skips the sort's own counting pass.
+ * GRPIC_ESTATE if the last grpic_push_deposit_ranked of this context was not
+ * on src (the same i1p array and n), or if a call that changes particles
+ * (grpic_particles_init, grpic_push, grpic_push_deposit, grpic_sort,
+ * grpic_sort_noalloc, grpic_inject_pairs, or an earlier grpic_sort_ranked)
+ * came in between.  Changes to src made outside the library in between leave
+ * the result unspecified; every write stays inside dst. */
+grpic_status grpic_sort_ranked(grpic_ctx* ctx, const grpic_particles* src, const grpic_particles* dst,
+                               int64_t* n_live, void* stream);
 
 /* grpic_sort for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -32,6 +32,13 @@ struct grpic_ctx {
   int* sort_live;
   double* inj_w;   // per-cell e+- weight of the pair injection (allocated on first use)
   int* static_scratch;  // this device's address of `scratch` (grpic_sort_noalloc)
+  // grpic_push_deposit_ranked: the sort scratch its rank pass fills
+  // (allocated on first use) and the particle set it ranked, which the next
+  // grpic_sort_ranked must be given
+  int* rank_off;
+  bool ranked;
+  const void* ranked_i1p;
+  int64_t ranked_n;
 };
 
 // Scratch of grpic_sort_noalloc, which allocates nothing: the cell counters /
@@ -322,7 +329,11 @@ grpic_status push_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particle
   return GRPIC_OK;
 }
 
-grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, hipStream_t s) {
+// counts: null, or the sort's zeroed cell counters, which the ranked kernels
+// fill (with each live slot's rank in its cell written to i1p)
+template <bool kRank>
+void launch_push_deposit(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, int* counts,
+                         hipStream_t s) {
   const dim3 grid((unsigned)((P->n + kDepBlock - 1) / kDepBlock));
   if (c->f32) {
     GatherPlanesT<float> gp;
@@ -331,10 +342,11 @@ grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_
       gp.B[k] = (const float*)F->B0[k];
     }
     CurrentPlanesT<float> cp{{(float*)F->J[0], (float*)F->J[1], (float*)F->J[2]}};
+    const ParticleArraysT<float> a = arrays<float>(P);
     switch (c->g.ser) {
-      case 2: hipLaunchKernelGGL((push_deposit_kernel_f32<2>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
-      case 1: hipLaunchKernelGGL((push_deposit_kernel_f32<1>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
-      default: hipLaunchKernelGGL(push_deposit_kernel_f32_lib, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<float>(P), cp); break;
+      case 2: hipLaunchKernelGGL((push_deposit_kernel_f32<2, kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      case 1: hipLaunchKernelGGL((push_deposit_kernel_f32<1, kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      default: hipLaunchKernelGGL((push_deposit_kernel_f32_lib<kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
     }
   } else {
     GatherPlanesT<double> gp;
@@ -343,12 +355,19 @@ grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_
       gp.B[k] = (const double*)F->B0[k];
     }
     CurrentPlanesT<double> cp{{(double*)F->J[0], (double*)F->J[1], (double*)F->J[2]}};
+    const ParticleArraysT<double> a = arrays<double>(P);
     switch (c->g.ser) {
-      case 2: hipLaunchKernelGGL((push_deposit_kernel<2>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
-      case 1: hipLaunchKernelGGL((push_deposit_kernel<1>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
-      default: hipLaunchKernelGGL(push_deposit_kernel_lib, grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, arrays<double>(P), cp); break;
+      case 2: hipLaunchKernelGGL((push_deposit_kernel<2, kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      case 1: hipLaunchKernelGGL((push_deposit_kernel<1, kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      default: hipLaunchKernelGGL((push_deposit_kernel_lib<kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
     }
   }
+}
+
+grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, int* counts,
+                               hipStream_t s) {
+  if (counts) launch_push_deposit<true>(c, F, P, counts, s);
+  else launch_push_deposit<false>(c, F, P, nullptr, s);
   LAUNCH_CHECK("push_deposit");
   return GRPIC_OK;
 }
@@ -374,16 +393,19 @@ struct SortScratch {
   int* live;
 };
 
+// ranked: the counters and ranks are already there (grpic_push_deposit_ranked)
 template <class T>
 grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst, const SortScratch& w,
-                       hipStream_t s) {
+                       bool ranked, hipStream_t s) {
   const Grid& g = c->g;
   const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
   const int nb = (int)((nkeys + kScanBlock - 1) / kScanBlock);
   const ParticleArraysT<T> a = arrays<T>(src), b = arrays<T>(dst);
-  const dim3 grank((unsigned)((src->n + kRankBlock - 1) / kRankBlock));
-  hipLaunchKernelGGL(sort_rank_kernel<T>, grank, dim3(kB), 0, s, g, a, w.off);
-  LAUNCH_CHECK("sort_rank");
+  if (!ranked) {
+    const dim3 grank((unsigned)((src->n + kRankBlock - 1) / kRankBlock));
+    hipLaunchKernelGGL(sort_rank_kernel<T>, grank, dim3(kB), 0, s, g, a, w.off);
+    LAUNCH_CHECK("sort_rank");
+  }
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, s, w.off, nkeys, w.sums);
   LAUNCH_CHECK("scan_blocks");
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, w.sums, nb);
@@ -399,10 +421,7 @@ grpic_status sort_impl(grpic_ctx* c, const grpic_particles* src, const grpic_par
   return GRPIC_OK;
 }
 
-// Argument checks and the launch sequence of a sort into the given scratch
-// (counters cleared by a fill kernel first).
-grpic_status sort_run(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst, const SortScratch& w,
-                      hipStream_t s) {
+grpic_status sort_check(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst) {
   grpic_status st;
   if ((st = check_ctx(c)) || (st = check_particles(src)) || (st = check_particles(dst))) return st;
   if (src->n != dst->n) return fail(GRPIC_EINVAL, "source has %lld slots, destination %lld",
@@ -410,12 +429,25 @@ grpic_status sort_run(grpic_ctx* c, const grpic_particles* src, const grpic_part
   if (src->n > 0x7FFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^31 - 1 slots");
   if (src->n > 0 && (src->tag == dst->tag || src->u1 == dst->u1))
     return fail(GRPIC_EINVAL, "source and destination must not alias");
+  return GRPIC_OK;
+}
+
+// Argument checks and the launch sequence of a sort into the given scratch
+// (counters cleared by a fill kernel first, unless `ranked`: then the
+// scratch holds the counters of grpic_push_deposit_ranked).
+grpic_status sort_run(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst, const SortScratch& w,
+                      hipStream_t s, bool ranked = false) {
+  grpic_status st;
+  if ((st = sort_check(c, src, dst))) return st;
   const Grid& g = c->g;
   const int64_t nkeys = (int64_t)g.n_r * g.n_th + 1;
-  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, nkeys, w.off, 0);
-  LAUNCH_CHECK("fill_int");
+  if (!ranked) {
+    hipLaunchKernelGGL(fill_int_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, nkeys, w.off, 0);
+    LAUNCH_CHECK("fill_int");
+  }
   if (src->n > 0) {
-    if ((st = c->f32 ? sort_impl<float>(c, src, dst, w, s) : sort_impl<double>(c, src, dst, w, s))) return st;
+    if ((st = c->f32 ? sort_impl<float>(c, src, dst, w, ranked, s) : sort_impl<double>(c, src, dst, w, ranked, s)))
+      return st;
   } else {
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, (int64_t)1, w.live, 0);
     LAUNCH_CHECK("fill_int");
@@ -568,6 +600,12 @@ grpic_status diagnostics_impl(grpic_ctx* c, const grpic_fields* F, const grpic_p
 extern "C" {
 
 const char* grpic_last_error(void) { return g_err.c_str(); }
+
+// Calls that change a particle set end the validity of the ranks of
+// grpic_push_deposit_ranked (the next grpic_sort_ranked then fails).
+inline void drop_ranks(grpic_ctx* c) {
+  if (c) c->ranked = false;
+}
 
 grpic_status grpic_create(const grpic_params* p, grpic_ctx** out) {
   if (!p || !out) return fail(GRPIC_EINVAL, "null argument");
@@ -768,6 +806,7 @@ grpic_status grpic_destroy(grpic_ctx* c) {
   (void)hipFree(c->acc);
   (void)hipFree(c->sort_off);
   if (c->inj_w) (void)hipFree(c->inj_w);
+  if (c->rank_off) (void)hipFree(c->rank_off);
   delete c;
   return GRPIC_OK;
 }
@@ -780,6 +819,7 @@ grpic_status grpic_get_params(const grpic_ctx* c, grpic_params* out) {
 
 grpic_status grpic_particles_init(grpic_ctx* c, const grpic_particles* P, int64_t n_pairs,
                                   int32_t ppc, double T, int64_t n_geo, uint64_t seed, void* stream) {
+  drop_ranks(c);
   grpic_status st;
   if ((st = check_ctx(c)) || (st = check_particles(P))) return st;
   const Grid& g = c->g;
@@ -810,6 +850,7 @@ grpic_status grpic_fields_init_wald(grpic_ctx* c, const grpic_fields* F, double 
 }
 
 grpic_status grpic_push(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, void* stream) {
+  drop_ranks(c);
   grpic_status st;
   if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
   if (P->n == 0) return GRPIC_OK;
@@ -827,8 +868,34 @@ grpic_status grpic_push_deposit(grpic_ctx* c, const grpic_fields* F, const grpic
                                 void* stream) {
   grpic_status st;
   if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
+  c->ranked = false;
   if (P->n == 0) return GRPIC_OK;
-  return push_deposit_impl(c, F, P, S(stream));
+  return push_deposit_impl(c, F, P, nullptr, S(stream));
+}
+
+grpic_status grpic_push_deposit_ranked(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P,
+                                       void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
+  if (P->n > 0x7FFFFFFFll) return fail(GRPIC_EINVAL, "more than 2^31 - 1 slots");
+  c->ranked = false;
+  const int64_t nkeys = (int64_t)c->g.n_r * c->g.n_th + 1;
+  const int64_t nb = (nkeys + kScanBlock - 1) / kScanBlock;
+  if (!c->rank_off) {
+    const hipError_t e = hipMalloc(&c->rank_off, (nkeys + nb + 1) * sizeof(int));
+    if (e != hipSuccess) {
+      c->rank_off = nullptr;
+      return fail(GRPIC_ENOMEM, "rank scratch allocation: %s", hipGetErrorString(e));
+    }
+  }
+  hipStream_t s = S(stream);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks(nkeys)), dim3(kB), 0, s, nkeys, c->rank_off, 0);
+  LAUNCH_CHECK("fill_int");
+  if (P->n > 0 && (st = push_deposit_impl(c, F, P, c->rank_off, s))) return st;
+  c->ranked = true;
+  c->ranked_i1p = P->i1p;
+  c->ranked_n = P->n;
+  return GRPIC_OK;
 }
 
 grpic_status grpic_push_adjoint(grpic_ctx* c, const grpic_fields* F, double B0, const grpic_particles* P,
@@ -852,6 +919,7 @@ grpic_status grpic_push_adjoint(grpic_ctx* c, const grpic_fields* F, double B0, 
 
 grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst,
                         int64_t* n_live, void* stream) {
+  drop_ranks(c);
   grpic_status st;
   hipStream_t s = S(stream);
   if (!c) return fail(GRPIC_EINVAL, "null context");
@@ -865,8 +933,30 @@ grpic_status grpic_sort(grpic_ctx* c, const grpic_particles* src, const grpic_pa
   return GRPIC_OK;
 }
 
+grpic_status grpic_sort_ranked(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst,
+                               int64_t* n_live, void* stream) {
+  grpic_status st;
+  if ((st = check_ctx(c)) || (st = check_particles(src))) return st;
+  if (!c->rank_off || !c->ranked || c->ranked_i1p != src->i1p || c->ranked_n != src->n)
+    return fail(GRPIC_ESTATE, "no grpic_push_deposit_ranked of this particle set since its last change");
+  const int64_t nkeys = (int64_t)c->g.n_r * c->g.n_th + 1;
+  const int64_t nb = (nkeys + kScanBlock - 1) / kScanBlock;
+  hipStream_t s = S(stream);
+  const SortScratch w{c->rank_off, c->rank_off + nkeys, c->rank_off + nkeys + nb};
+  if ((st = sort_run(c, src, dst, w, s, true))) return st;
+  c->ranked = false;
+  if (n_live) {
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, w.live, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_live = h;
+  }
+  return GRPIC_OK;
+}
+
 grpic_status grpic_sort_noalloc(grpic_ctx* c, const grpic_particles* src, const grpic_particles* dst,
                                 int32_t* n_live_device, void* stream) {
+  drop_ranks(c);
   grpic_status st;
   if (!c) return fail(GRPIC_EINVAL, "null context");
   const int64_t ncell = (int64_t)c->g.n_r * c->g.n_th;
@@ -888,6 +978,7 @@ grpic_status grpic_sort_noalloc(grpic_ctx* c, const grpic_particles* src, const 
 grpic_status grpic_inject_pairs(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P,
                                 const grpic_inject_params* ip, int64_t first_free, int64_t* n_injected,
                                 void* stream) {
+  drop_ranks(c);
   grpic_status st;
   if ((st = check_ctx(c)) || (st = check_fields(c, F)) || (st = check_particles(P))) return st;
   if (!ip) return fail(GRPIC_EINVAL, "null injection parameters");

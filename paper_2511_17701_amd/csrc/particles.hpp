@@ -405,6 +405,13 @@ __device__ inline RSCT<float> rsc_near_f(const Grid& g, const Tables& t, int i1,
   return p;
 }
 
+// Sort key of a slot's state: its cell i1 * n_th + i2, or n_cells for a slot
+// that the cell sort drops (empty, invalid, leaving, outside the grid).
+__device__ inline int cell_key(const Grid& g, uint8_t t, int i1, int i2) {
+  if (!is_live(t) || (t & kLeaving) || i1 < 0 || i1 >= g.n_r || i2 < 0 || i2 >= g.n_th) return g.n_r * g.n_th;
+  return i1 * g.n_th + i2;
+}
+
 // What the deposit needs from one particle's move (Sec. 3.2).
 template <class T>
 struct Move {
@@ -415,6 +422,7 @@ struct Move {
   T q;                 // species sign x charge_scale x weight
   T vphi;
   T u1, u2, u3;        // u^{n+1/2}, for vphi when !mid
+  int cell;            // sort key of the state after the push (cell_key)
 };
 
 // FP64 particle update (Sec. 3.1 steps 1-11) of slot k; writes the new state
@@ -424,6 +432,7 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
                                         const ParticleArrays& P, int64_t k) {
   Move<double> mv;
   mv.dep = false;
+  mv.cell = g.n_r * g.n_th;
   if (k >= P.n) return mv;
   uint8_t t = P.tag[k];
   if (!is_live(t)) return mv;
@@ -549,6 +558,7 @@ __device__ inline Move<double> push_one(const Grid& g, const Tables& tab, const 
   mv.u1 = u1;
   mv.u2 = u2;
   mv.u3 = u3;
+  mv.cell = cell_key(g, t, i1, i2);
   return mv;
 }
 
@@ -558,6 +568,7 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
                                            const ParticleArraysT<float>& P, int64_t k) {
   Move<float> mv;
   mv.dep = false;
+  mv.cell = g.n_r * g.n_th;
   if (k >= P.n) return mv;
   uint8_t t = P.tag[k];
   if (!is_live(t)) return mv;
@@ -693,6 +704,7 @@ __device__ inline Move<float> push_one_f32(const Grid& g, const Tables& tab, con
   mv.u1 = u1;
   mv.u2 = u2;
   mv.u3 = u3;
+  mv.cell = cell_key(g, t, i1, i2);
   return mv;
 }
 
@@ -702,6 +714,7 @@ __device__ inline Move<T> load_move(const Grid& g, const ParticleArraysT<T>& P, 
   Move<T> mv;
   mv.dep = false;
   mv.mid = false;
+  mv.cell = g.n_r * g.n_th;
   if (k >= P.n) return mv;
   const uint8_t t = P.tag[k];
   if (!is_live(t)) return mv;
@@ -1019,7 +1032,8 @@ __device__ inline void add_lane_folded(const Grid& g, bool act, const ContribT<T
 // atomic per touched node.  A block whose footprint does not
 // fit the tile (its cells wrap from the end of one theta row to the next, or
 // its particles have spread) adds wavefront run sums straight to the planes.
-// Every lane of the block must call this.
+// Every lane of the block must call this; on every path it passes a block
+// barrier before returning.
 template <class T>
 __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp, bool act,
                                      const ContribT<T>& c) {
@@ -1075,6 +1089,86 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
   }
 }
 
+// ------------------------------------------------------------------ cell ranks
+// The counting sort by cell (cell_key) needs each live slot's rank among the
+// slots of its cell and each cell's count.  A block counts its slots per cell
+// in an LDS hash table of 2^kBits cells (open addressing, linear probing; at
+// most 2^(kBits-1) slots per block, so a free cell is always found): a slot's
+// rank inside the block is its cell's count when it was added.  Then one
+// returning atomic per cell present in the block claims the block's ranks of
+// that cell on the cell's global counter, and every slot takes its cell's
+// base plus its rank inside the block.  Slots with key n_cells claim nothing.
+template <int kBits>
+struct RankTable {
+  int key[1 << kBits];
+  int n[1 << kBits];  // count in the block, then the cell's base
+};
+
+// The block's table (one LDS object per block, whichever function asks).
+template <int kBits>
+__device__ inline RankTable<kBits>& block_rank_table() {
+  __shared__ RankTable<kBits> rt;
+  return rt;
+}
+
+template <int kBits>
+__device__ inline void rank_clear(RankTable<kBits>& rt) {
+  for (int e = (int)threadIdx.x; e < (1 << kBits); e += (int)blockDim.x) {
+    rt.key[e] = -1;
+    rt.n[e] = 0;
+  }
+}
+
+// Adds a slot of cell `key` (< n_cells) to the table; returns its entry, and
+// in `local` the number of the block's slots of that cell added before it.
+template <int kBits>
+__device__ inline int rank_insert(RankTable<kBits>& rt, int key, int& local) {
+  int h = (int)(((uint32_t)key * 0x9E3779B1u) >> (32 - kBits));  // multiplicative hash
+  for (;;) {
+    const int old = atomicCAS(&rt.key[h], -1, key);
+    if (old == -1 || old == key) break;
+    h = (h + 1) & ((1 << kBits) - 1);
+  }
+  local = atomicAdd(&rt.n[h], 1);
+  return h;
+}
+
+// The claims: afterwards rt.n holds each present cell's base.  Every thread
+// of the block calls this after a barrier that follows the last insert (all
+// of a thread's claims are in flight before the first is waited for).
+template <int kBits, int kThreads>
+__device__ inline void rank_claim(RankTable<kBits>& rt, int* __restrict__ counts) {
+  constexpr int kE = (1 << kBits) / kThreads;
+  int base[kE];
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int h = e * kThreads + (int)threadIdx.x;
+    const int key = rt.key[h];
+    base[e] = key >= 0 ? atomicAdd(counts + key, rt.n[h]) : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kE; ++e) rt.n[e * kThreads + (int)threadIdx.x] = base[e];
+  __syncthreads();
+}
+
+// The rank pass of the sort inside a fused push + deposit block: slot k's key
+// after the push is `cell`; its rank goes to i1p (the previous position is not
+// stored by the fused pass).  The table was cleared at the start of the
+// kernel and a block barrier (the deposit's) has passed since.
+constexpr int kPushRankBits = 9;  // 512 cells for the kDepBlock slots of a block
+static_assert((1 << (kPushRankBits - 1)) >= kDepBlock, "rank table too small for a block");
+
+__device__ inline void rank_fused(const Grid& g, int* __restrict__ i1p, int64_t k, int cell,
+                                  int* __restrict__ counts) {
+  RankTable<kPushRankBits>& rt = block_rank_table<kPushRankBits>();
+  int local = 0, entry = -1;
+  if (cell < g.n_r * g.n_th) entry = rank_insert(rt, cell, local);
+  __syncthreads();
+  rank_claim<kPushRankBits, kDepBlock>(rt, counts);
+  if (entry >= 0) i1p[k] = rt.n[entry] + local;
+}
+
 // ------------------------------------------------------------------ kernels
 // The FP64 push kernels are held to 128 VGPRs (4 wavefronts per SIMD; no
 // spills on the series paths): on gfx950 the push is latency- and issue-bound,
@@ -1106,51 +1200,66 @@ __global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, 
 
 // Push and deposit in one pass: the deposit takes the move from registers and
 // J^3 from the push's own midpoint metric; the previous position is not
-// stored.
-template <int SER>
+// stored.  kRank: the pass also ranks the slots by their cell after the push
+// for the cell sort (rank_fused; counts: the sort's zeroed cell counters).
+template <int SER, bool kRank>
 __global__ void __launch_bounds__(kDepBlock) GRPIC_FP64_PUSH_OCCUPANCY
-push_deposit_kernel(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp) {
-  const Move<double> mv = push_one<SER, false>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+push_deposit_kernel(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp, int* counts) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if constexpr (kRank) rank_clear(block_rank_table<kPushRankBits>());
+  const Move<double> mv = push_one<SER, false>(g, tab, fp, P, k);
   ContribT<double> c;
   const bool act = make_contrib<double, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
+  if constexpr (kRank) rank_fused(g, P.i1p, k, mv.cell, counts);
 }
 
 // library path in FP64 (coarse grids and the general quasi-spherical map):
 // the library exp and sincos and the map factors need more registers than the
 // series paths; three wavefronts per SIMD leave room for them without spills
+template <bool kRank>
 __global__ void __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(3)))
-push_deposit_kernel_lib(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp) {
-  const Move<double> mv = push_one<0, false>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+push_deposit_kernel_lib(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp,
+                        int* counts) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if constexpr (kRank) rank_clear(block_rank_table<kPushRankBits>());
+  const Move<double> mv = push_one<0, false>(g, tab, fp, P, k);
   ContribT<double> c;
   const bool act = make_contrib<double, 0>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
+  if constexpr (kRank) rank_fused(g, P.i1p, k, mv.cell, counts);
 }
 
-template <int SER>
+template <int SER, bool kRank>
 __device__ inline void push_deposit_f32(const Grid& g, const Tables& tab, const GatherPlanesT<float>& fp,
-                                        const ParticleArraysT<float>& P, const CurrentPlanesT<float>& cp) {
-  const Move<float> mv = push_one_f32<SER, false>(g, tab, fp, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                                        const ParticleArraysT<float>& P, const CurrentPlanesT<float>& cp,
+                                        int* counts) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if constexpr (kRank) rank_clear(block_rank_table<kPushRankBits>());
+  const Move<float> mv = push_one_f32<SER, false>(g, tab, fp, P, k);
   ContribT<float> c;
   const bool act = make_contrib<float, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
+  if constexpr (kRank) rank_fused(g, P.i1p, k, mv.cell, counts);
 }
 
-// series paths: the compiler's own allocation (<= 96 VGPRs, 5 wavefronts)
-template <int SER>
-__global__ void __launch_bounds__(kDepBlock) push_deposit_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
+// series paths: 5 wavefronts per SIMD (96 VGPRs: the compiler's own
+// allocation without the rank pass; the rank pass would take it past 96)
+template <int SER, bool kRank>
+__global__ void __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(5))) push_deposit_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
                                                                      ParticleArraysT<float> P,
-                                                                     CurrentPlanesT<float> cp) {
-  push_deposit_f32<SER>(g, tab, fp, P, cp);
+                                                                     CurrentPlanesT<float> cp, int* counts) {
+  push_deposit_f32<SER, kRank>(g, tab, fp, P, cp, counts);
 }
 
 // library path (coarse grids and the general quasi-spherical map): held to 5
 // wavefronts per SIMD (a few spilled registers), 11 % faster than the 4 that
 // its 100 VGPRs would give
+template <bool kRank>
 __global__ void __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(5)))
 push_deposit_kernel_f32_lib(Grid g, Tables tab, GatherPlanesT<float> fp, ParticleArraysT<float> P,
-                            CurrentPlanesT<float> cp) {
-  push_deposit_f32<0>(g, tab, fp, P, cp);
+                            CurrentPlanesT<float> cp, int* counts) {
+  push_deposit_f32<0, kRank>(g, tab, fp, P, cp, counts);
 }
 
 }  // namespace grpic

@@ -14,11 +14,6 @@ namespace grpic {
 
 constexpr int kScanBlock = 1024;  // elements scanned per block (4 per thread)
 
-__device__ inline int cell_key(const Grid& g, uint8_t t, int i1, int i2) {
-  if (!is_live(t) || (t & kLeaving) || i1 < 0 || i1 >= g.n_r || i2 < 0 || i2 >= g.n_th) return g.n_r * g.n_th;
-  return i1 * g.n_th + i2;
-}
-
 template <class T>
 __device__ inline int sort_key(const Grid& g, const ParticleArraysT<T>& P, int64_t k) {
   const uint8_t t = P.tag[k];
@@ -27,37 +22,29 @@ __device__ inline int sort_key(const Grid& g, const ParticleArraysT<T>& P, int64
 }
 
 // The rank pass takes kRankBlock consecutive slots per block of 256 threads
-// (8 per thread) and counts them in an LDS hash table of kRankTable cells.
-constexpr int kRankBlock = 2048, kRankTable = 4096;
+// (8 per thread) and counts them in a RankTable of kRankTable cells.
+constexpr int kRankBits = 12;
+constexpr int kRankBlock = 2048, kRankTable = 1 << kRankBits;
+static_assert(kRankTable >= 2 * kRankBlock, "rank table too small for a block");
 
 // Counts the live slots of each cell and gives every live slot its rank among
-// the slots of its cell.  Ten steps after a sort, neighbouring slots mostly
-// hold particles of different (nearby) cells, so runs of equal cells are
-// short (about 2 slots at 16 particles per cell), while a block's slots fall
-// in a few hundred distinct cells (measured: 262 of 2048 on a 4096^2 grid at
-// 16 particles per cell, 83 on 2048^2 at 90).  So the block
-// counts its slots per cell in an LDS hash table (open addressing, linear
-// probing; a slot's rank inside the block is the count its cell had when it
-// was added), then claims each cell's ranks with one returning atomic on the
-// cell's global counter, and every slot takes its cell's base plus its rank
-// inside the block.  Empty and leaving slots (key n_cells) claim nothing.
-// The rank is written to the source's i1p (the previous position is scratch
-// between a push and its deposit, and the sort does not carry it), so the
-// scatter needs no atomics.
-__device__ inline int rank_hash(int key) { return (int)(((uint32_t)key * 0x9E3779B1u) >> 20); }  // 12 bits
-
+// the slots of its cell (block counting in an LDS hash table, one claim per
+// cell and block: RankTable).  Ten steps after a sort, neighbouring slots
+// mostly hold particles of different (nearby) cells, so runs of equal cells
+// are short (about 2 slots at 16 particles per cell), while a block's slots
+// fall in a few hundred distinct cells (measured: 262 of 2048 on a 4096^2
+// grid at 16 particles per cell, 83 on 2048^2 at 90).  The rank is written to
+// the source's i1p (the previous position is scratch between a push and its
+// deposit, and the sort does not carry it), so the scatter needs no atomics.
+// The fused push + deposit pass can do the same per block of its own
+// (rank_fused), which makes this pass unnecessary.
 template <class T>
 __global__ void __launch_bounds__(256) sort_rank_kernel(Grid g, ParticleArraysT<T> P, int* __restrict__ counts) {
-  static_assert(kRankTable == 4096, "rank_hash gives 12 bits");
-  __shared__ int tab_key[kRankTable];
-  __shared__ int tab_n[kRankTable];  // count in the block, then the cell's base
+  RankTable<kRankBits>& rt = block_rank_table<kRankBits>();
   const int ncell = g.n_r * g.n_th;
   const int64_t k0 = (int64_t)blockIdx.x * kRankBlock;
   const int t = threadIdx.x;
-  for (int e = t; e < kRankTable; e += 256) {
-    tab_key[e] = -1;
-    tab_n[e] = 0;
-  }
+  rank_clear(rt);
   __syncthreads();
   constexpr int kQ = kRankBlock / 256;
   int entry[kQ], local[kQ];
@@ -65,38 +52,13 @@ __global__ void __launch_bounds__(256) sort_rank_kernel(Grid g, ParticleArraysT<
   for (int q = 0; q < kQ; ++q) {
     const int64_t k = k0 + q * 256 + t;  // consecutive threads on consecutive slots
     const int key = k < P.n ? sort_key(g, P, k) : ncell;
-    entry[q] = -1;
-    if (key < ncell) {
-      // at most kRankBlock distinct keys in kRankTable cells: a free cell is
-      // always found
-      int h = rank_hash(key);
-      for (;;) {
-        const int old = atomicCAS(&tab_key[h], -1, key);
-        if (old == -1 || old == key) break;
-        h = (h + 1) & (kRankTable - 1);
-      }
-      entry[q] = h;
-      local[q] = atomicAdd(&tab_n[h], 1);
-    }
+    entry[q] = key < ncell ? rank_insert(rt, key, local[q]) : -1;
   }
   __syncthreads();
-  // one claim per cell present in the block (all of a thread's claims in
-  // flight before the first is waited for)
-  constexpr int kE = kRankTable / 256;
-  int base[kE];
-#pragma unroll
-  for (int e = 0; e < kE; ++e) {
-    const int h = e * 256 + t;
-    const int key = tab_key[h];
-    base[e] = key >= 0 ? atomicAdd(counts + key, tab_n[h]) : 0;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < kE; ++e) tab_n[e * 256 + t] = base[e];
-  __syncthreads();
+  rank_claim<kRankBits, 256>(rt, counts);
 #pragma unroll
   for (int q = 0; q < kQ; ++q)
-    if (entry[q] >= 0) P.i1p[k0 + q * 256 + t] = tab_n[entry[q]] + local[q];
+    if (entry[q] >= 0) P.i1p[k0 + q * 256 + t] = rt.n[entry[q]] + local[q];
 }
 
 // Exclusive scan of n ints in place, three phases: per-block scan (block sums
@@ -188,6 +150,7 @@ __global__ void __launch_bounds__(256) sort_scatter_kernel(Grid g, ParticleArray
   const int key = cell_key(g, t, i1, i2);
   if (key == g.n_r * g.n_th) return;
   const int64_t o = (int64_t)off[key] + scatter_load<T>(S.i1p + k);
+  if (o < 0 || o >= D.n) return;  // ranks that do not belong to these counts (a caller's error)
   D.i1[o] = i1;
   D.i2[o] = i2;
   D.dx1[o] = scatter_load<T>(S.dx1 + k);

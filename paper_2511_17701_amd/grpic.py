@@ -86,10 +86,12 @@ _sigs = {
     "grpic_push": ([c_void_p, _F, _PP, c_void_p], c_int32),
     "grpic_deposit": ([c_void_p, _PP, _F, c_void_p], c_int32),
     "grpic_push_deposit": ([c_void_p, _F, _PP, c_void_p], c_int32),
+    "grpic_push_deposit_ranked": ([c_void_p, _F, _PP, c_void_p], c_int32),
     "grpic_push_adjoint": ([c_void_p, _F, c_double, _PP, c_void_p, c_void_p, c_void_p, c_void_p],
                            c_int32),
     "grpic_field_advance": ([c_void_p, _F, c_int32, c_void_p], c_int32),
     "grpic_sort": ([c_void_p, _PP, _PP, POINTER(c_int64), c_void_p], c_int32),
+    "grpic_sort_ranked": ([c_void_p, _PP, _PP, POINTER(c_int64), c_void_p], c_int32),
     "grpic_sort_noalloc": ([c_void_p, _PP, _PP, c_void_p, c_void_p], c_int32),
     "grpic_inject_pairs": ([c_void_p, _F, _PP, POINTER(InjectParams), c_int64, POINTER(c_int64),
                             c_void_p], c_int32),
@@ -227,7 +229,14 @@ class Context:
         _check(_lib.grpic_deposit(self._h, ctypes.byref(self._particles(P)),
                                   ctypes.byref(self._fields(F)), _stream()), "grpic_deposit")
 
-    def push_deposit(self, F: torch.Tensor, P: dict):
+    def push_deposit(self, F: torch.Tensor, P: dict, ranked: bool = False):
+        """grpic_push_deposit; ranked: grpic_push_deposit_ranked (the pass
+        also ranks the slots for a following sort(P, Q, ranked=True))."""
+        if ranked:
+            _check(_lib.grpic_push_deposit_ranked(self._h, ctypes.byref(self._fields(F)),
+                                                  ctypes.byref(self._particles(P)), _stream()),
+                   "grpic_push_deposit_ranked")
+            return
         _check(_lib.grpic_push_deposit(self._h, ctypes.byref(self._fields(F)),
                                        ctypes.byref(self._particles(P)), _stream()),
                "grpic_push_deposit")
@@ -251,13 +260,15 @@ class Context:
         _check(_lib.grpic_field_advance(self._h, ctypes.byref(self._fields(F)), stage, _stream()),
                "grpic_field_advance")
 
-    def sort(self, P: dict, Q: dict, count: bool = False):
+    def sort(self, P: dict, Q: dict, count: bool = False, ranked: bool = False):
         """Cell-sort the slots of P into Q (same size); returns the number of
-        live slots when count is True (waits for the stream)."""
+        live slots when count is True (waits for the stream).  ranked:
+        grpic_sort_ranked, from the ranks of the preceding
+        push_deposit(F, P, ranked=True)."""
         n = c_int64(0)
-        _check(_lib.grpic_sort(self._h, ctypes.byref(self._particles(P)),
-                               ctypes.byref(self._particles(Q)),
-                               ctypes.byref(n) if count else None, _stream()), "grpic_sort")
+        fn, name = (_lib.grpic_sort_ranked, "grpic_sort_ranked") if ranked else (_lib.grpic_sort, "grpic_sort")
+        _check(fn(self._h, ctypes.byref(self._particles(P)), ctypes.byref(self._particles(Q)),
+                  ctypes.byref(n) if count else None, _stream()), name)
         return n.value if count else None
 
     def sort_noalloc(self, P: dict, Q: dict, n_live=None):
