@@ -8,7 +8,10 @@ and some are emptied.  Bars: the pushed states are the same bit for bit; the
 sorted sets have the same cell sequence and the same particle states in each
 cell bit for bit, and the same live count; the currents agree to the rounding
 of the atomic additions' order.  A ranked sort whose ranks were consumed or
-whose particle set changed since the ranked pass is refused."""
+whose particle set changed since the ranked pass is refused.  At full size in
+FP64 (C6 and C5, where the benchmark ranks inside the fused pass), the two
+routes give the same live count and the same particle states per cell
+(exact integer sums of the values' bit patterns)."""
 import numpy as np
 import pytest
 
@@ -108,3 +111,59 @@ def test_ranked_sort_of_an_empty_set(G):
     E = c.new_particles(0)
     c.push_deposit(F, E, ranked=True)
     assert c.sort(E, c.new_particles(0), count=True, ranked=True) == 0
+
+
+@pytest.mark.parametrize("name", ["c6_monopole", "c5_4096"])
+def test_ranked_sort_full_size_fp64(G, name):
+    """At full size in the form where the benchmark takes the ranked pass (FP64:
+    C6, 2048^2 at 90 particles per cell = 3.77e8 particles, the paper's shape;
+    C5, 4096^2 at 16), after 10 steps of motion: the ranked pass + ranked sort
+    and the fused pass + separate sort give the same live count, both outputs
+    are in cell order, and every cell holds the same particle states (per
+    cell and array, the count and the integer sum of the values' bit patterns
+    agree exactly)."""
+    import torch
+    from paper_2511_17701_amd.workloads import WORKLOADS
+    w = WORKLOADS[name]
+    c = G.Context(w.a, w.M, w.r_min, w.r_max, w.n_r, w.n_th, cfl=w.cfl, n_iter=w.n_iter,
+                  small_angle=w.small_angle, charge_scale=w.charge_scale, n_filter=w.n_filter,
+                  n_absorb=w.n_absorb, r0=w.r0, h0=w.h0, precision=G.GRPIC_FP64)
+    F = c.new_fields()
+    (c.fields_init_monopole if w.init == "monopole" else c.fields_init_wald)(F, w.B0)
+    P = c.new_particles(w.n_particles)
+    c.particles_init(P, w.n_pairs_total if w.ppc == 0 else 0, w.ppc, w.T, w.n_geo, w.seed)
+    for _ in range(10):
+        c.step(F, P, fused=True)
+    P2 = {k: v.clone() for k, v in P.items()}
+    F2 = F.clone()
+    QA = c.new_particles(w.n_particles)
+    c.push_deposit(F, P)
+    nA = c.sort(P, QA, count=True)
+    del P
+    QB = c.new_particles(w.n_particles)
+    c.push_deposit(F2, P2, ranked=True)
+    nB = c.sort(P2, QB, count=True, ranked=True)
+    del P2
+    assert nA == nB and nB > 0.99 * w.n_particles
+    ncell = w.n_r * w.n_th
+
+    def summary(Q, n):
+        cell = Q["i1"][:n].long() * w.n_th + Q["i2"][:n].long()
+        assert bool((cell[1:] >= cell[:-1]).all()), "cell order"
+        cnt = torch.zeros(ncell, dtype=torch.int64, device=cell.device).index_add_(
+            0, cell, torch.ones_like(cell))
+        sums = []
+        for k in COLS:
+            v = Q[k][:n]
+            bits = (v.view(torch.int64) if v.dtype == torch.float64 else v.to(torch.int64))
+            sums.append(torch.zeros(ncell, dtype=torch.int64, device=cell.device).index_add_(0, cell, bits))
+        return cnt, sums
+
+    ca, sa = summary(QA, nA)
+    cb, sb = summary(QB, nB)
+    assert torch.equal(ca, cb)
+    for k, x, y in zip(COLS, sa, sb):
+        assert torch.equal(x, y), k
+    assert bool((QB["tag"][nB:] == 0).all())
+    del QA, QB, F, F2
+    torch.cuda.empty_cache()
