@@ -37,7 +37,8 @@
  * u_1 = u_r dr/dx1, u_2 = u_theta dth/dx2, u_3 = u_phi; previous position
  * (i1p, i2p, dx1p, dx2p): written by grpic_push for grpic_deposit (Sec. 3.2)
  * and read by grpic_diagnostics (time-centred E, L); grpic_push_deposit does
- * not write it and grpic_sort does not carry it, so a step whose E, L are
+ * not write it (grpic_push_deposit_ranked writes the sort's ranks to i1p) and
+ * grpic_sort does not carry it, so a step whose E, L are
  * wanted is taken with grpic_push and grpic_deposit (same particle state bit
  * for bit, same currents to rounding order).
  * tag: 0 = empty slot, 1 = positron (q/m = +1), 2 = electron (q/m = -1),
