@@ -751,12 +751,13 @@ __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 // deposits J^1 and J^2 (normalised by 1/dt) on the edges of the cell it lies
 // in, with first-order weights at the segment midpoint; J^3 = q alpha u^3 /
 // gamma goes to the four nodes around the path midpoint.
-constexpr int kDepBlock = 256;
-// tile of kTI rows x kTJ columns; measured against 8 x 24, 8 x 40, 8 x 48 and
-// 6 x 32: 8 x 32 the fastest at 4096^2 and 16 per cell (fused pass -1.5 %
-// against 8 x 48) and at 2048^2 and 90 per cell (-0.6 %), the same at 512^2;
-// six rows often miss a block's footprint (+10 to +13 %)
-constexpr int kTI = 8, kTJ = 32;
+// blocks of 128 particles with a tile of kTI rows x kTJ columns: measured
+// against 256 particles with tiles of 8 x 24 to 8 x 48 and 6 x 32 and 128
+// with 8 x 32, the fastest at 4096^2 and 16 per cell (fused pass -3 % against
+// 256 with 8 x 48), at 2048^2 and 90 per cell (-1 %) and at 512^2 (-3 %); six
+// rows often miss a block's footprint (+10 to +13 %)
+constexpr int kDepBlock = 128;
+constexpr int kTI = 8, kTJ = 24;
 constexpr int kDepRep = 2;  // copies of the deposit tile
 // lane-folding levels before the LDS atomics: quads in FP32, pairs in FP64
 // (measured: FP32 LDS atomics are the costlier, FP64 gains nothing past pairs)
@@ -1160,7 +1161,7 @@ __device__ inline void rank_claim(RankTable<kBits>& rt, int* __restrict__ counts
 // after the push is `cell`; its rank goes to i1p (the previous position is not
 // stored by the fused pass).  The table was cleared at the start of the
 // kernel and a block barrier (the deposit's) has passed since.
-constexpr int kPushRankBits = 9;  // 512 cells for the kDepBlock slots of a block
+constexpr int kPushRankBits = 8;  // 256 cells for the kDepBlock slots of a block
 static_assert((1 << (kPushRankBits - 1)) >= kDepBlock, "rank table too small for a block");
 
 __device__ inline void rank_fused(const Grid& g, int* __restrict__ i1p, int64_t k, int cell,
