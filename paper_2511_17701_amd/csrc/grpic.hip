@@ -334,8 +334,9 @@ grpic_status push_impl(grpic_ctx* c, const grpic_fields* F, const grpic_particle
 template <bool kRank>
 void launch_push_deposit(grpic_ctx* c, const grpic_fields* F, const grpic_particles* P, int* counts,
                          hipStream_t s) {
-  const dim3 grid((unsigned)((P->n + kDepBlock - 1) / kDepBlock));
   if (c->f32) {
+    constexpr int kBk = dep_block<float>();
+    const dim3 grid((unsigned)((P->n + kBk - 1) / kBk));
     GatherPlanesT<float> gp;
     for (int k = 0; k < 3; ++k) {
       gp.D[k] = (const float*)F->D[k];
@@ -344,11 +345,13 @@ void launch_push_deposit(grpic_ctx* c, const grpic_fields* F, const grpic_partic
     CurrentPlanesT<float> cp{{(float*)F->J[0], (float*)F->J[1], (float*)F->J[2]}};
     const ParticleArraysT<float> a = arrays<float>(P);
     switch (c->g.ser) {
-      case 2: hipLaunchKernelGGL((push_deposit_kernel_f32<2, kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
-      case 1: hipLaunchKernelGGL((push_deposit_kernel_f32<1, kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
-      default: hipLaunchKernelGGL((push_deposit_kernel_f32_lib<kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      case 2: hipLaunchKernelGGL((push_deposit_kernel_f32<2, kRank>), grid, dim3(kBk), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      case 1: hipLaunchKernelGGL((push_deposit_kernel_f32<1, kRank>), grid, dim3(kBk), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      default: hipLaunchKernelGGL((push_deposit_kernel_f32_lib<kRank>), grid, dim3(kBk), 0, s, c->g, c->tab, gp, a, cp, counts); break;
     }
   } else {
+    constexpr int kBk = dep_block<double>();
+    const dim3 grid((unsigned)((P->n + kBk - 1) / kBk));
     GatherPlanesT<double> gp;
     for (int k = 0; k < 3; ++k) {
       gp.D[k] = (const double*)F->D[k];
@@ -357,9 +360,9 @@ void launch_push_deposit(grpic_ctx* c, const grpic_fields* F, const grpic_partic
     CurrentPlanesT<double> cp{{(double*)F->J[0], (double*)F->J[1], (double*)F->J[2]}};
     const ParticleArraysT<double> a = arrays<double>(P);
     switch (c->g.ser) {
-      case 2: hipLaunchKernelGGL((push_deposit_kernel<2, kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
-      case 1: hipLaunchKernelGGL((push_deposit_kernel<1, kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
-      default: hipLaunchKernelGGL((push_deposit_kernel_lib<kRank>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      case 2: hipLaunchKernelGGL((push_deposit_kernel<2, kRank>), grid, dim3(kBk), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      case 1: hipLaunchKernelGGL((push_deposit_kernel<1, kRank>), grid, dim3(kBk), 0, s, c->g, c->tab, gp, a, cp, counts); break;
+      default: hipLaunchKernelGGL((push_deposit_kernel_lib<kRank>), grid, dim3(kBk), 0, s, c->g, c->tab, gp, a, cp, counts); break;
     }
   }
 }
@@ -375,11 +378,12 @@ grpic_status push_deposit_impl(grpic_ctx* c, const grpic_fields* F, const grpic_
 template <class T>
 grpic_status deposit_impl(grpic_ctx* c, const grpic_particles* P, const grpic_fields* F, hipStream_t s) {
   CurrentPlanesT<T> cp{{(T*)F->J[0], (T*)F->J[1], (T*)F->J[2]}};
-  const dim3 grid((unsigned)((P->n + kDepBlock - 1) / kDepBlock));
+  constexpr int kBk = dep_block<T>();
+  const dim3 grid((unsigned)((P->n + kBk - 1) / kBk));
   switch (c->g.ser) {
-    case 2: hipLaunchKernelGGL((deposit_kernel<T, 2>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
-    case 1: hipLaunchKernelGGL((deposit_kernel<T, 1>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
-    default: hipLaunchKernelGGL((deposit_kernel<T, 0>), grid, dim3(kDepBlock), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
+    case 2: hipLaunchKernelGGL((deposit_kernel<T, 2>), grid, dim3(kBk), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
+    case 1: hipLaunchKernelGGL((deposit_kernel<T, 1>), grid, dim3(kBk), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
+    default: hipLaunchKernelGGL((deposit_kernel<T, 0>), grid, dim3(kBk), 0, s, c->g, c->tab, arrays<T>(P), cp); break;
   }
   LAUNCH_CHECK("deposit");
   return GRPIC_OK;

@@ -751,13 +751,18 @@ __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 // deposits J^1 and J^2 (normalised by 1/dt) on the edges of the cell it lies
 // in, with first-order weights at the segment midpoint; J^3 = q alpha u^3 /
 // gamma goes to the four nodes around the path midpoint.
-// blocks of 128 particles with a tile of kTI rows x kTJ columns: measured
-// against 256 particles with tiles of 8 x 24 to 8 x 48 and 6 x 32 and 128
-// with 8 x 32, the fastest at 4096^2 and 16 per cell (fused pass -3 % against
-// 256 with 8 x 48), at 2048^2 and 90 per cell (-1 %) and at 512^2 (-3 %); six
-// rows often miss a block's footprint (+10 to +13 %)
-constexpr int kDepBlock = 128;
-constexpr int kTI = 8, kTJ = 24;
+// Particles per block of the deposit passes and the LDS tile of kTI rows x
+// dep_tj<T>() columns, measured on the fused pass (blocks of 64, 128 and 256,
+// tiles of 6 or 8 rows and 16 to 48 columns): in single precision 64 with
+// 8 x 16 (at 4096^2 and 16 per cell -4.5 % against 256 with 8 x 48; 128 with
+// 8 x 24 -3 %), in double precision 128 with 8 x 24 (at 2048^2 and 90 per cell
+// -1 %, 64 with 8 x 16 +0.3 % there; at 512^2 64 and 128 within 2 %); six rows
+// often miss a block's footprint (+7 to +13 %)
+template <class T>
+constexpr int dep_block() { return sizeof(T) == 4 ? 64 : 128; }
+template <class T>
+constexpr int dep_tj() { return sizeof(T) == 4 ? 16 : 24; }
+constexpr int kTI = 8;
 constexpr int kDepRep = 2;  // copies of the deposit tile
 // lane-folding levels before the LDS atomics: quads in FP32, pairs in FP64
 // (measured: FP32 LDS atomics are the costlier, FP64 gains nothing past pairs)
@@ -1045,8 +1050,9 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
   // kRep copies of the tile: the adding lanes alternate between copies, which
   // divides the same-address conflicts of a cell's run of lanes by kRep
   constexpr int kRep = kDepRep;
+  constexpr int kBlk = dep_block<T>(), kTJ = dep_tj<T>();
   __shared__ __align__(16) T tile[kRep][3][kTI][kTJ];
-  __shared__ int bound[4][kDepBlock / 64];
+  __shared__ int bound[4][kBlk / 64];
   // block footprint: union of [ia-1, ia+2] x [ja-1, ja+2]
   int v[4] = {act ? c.ia - 1 : INT_MAX, act ? -(c.ia + 2) : INT_MAX, act ? c.ja - 1 : INT_MAX,
               act ? -(c.ja + 2) : INT_MAX};
@@ -1061,14 +1067,14 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
     constexpr int kVec = 16 / sizeof(T);
     using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
     V* fv = reinterpret_cast<V*>(&tile[0][0][0][0]);
-    for (int e = threadIdx.x; e < kRep * 3 * kTI * kTJ / kVec; e += kDepBlock) fv[e] = V{};
+    for (int e = threadIdx.x; e < kRep * 3 * kTI * kTJ / kVec; e += kBlk) fv[e] = V{};
   }
   __syncthreads();
   int b[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     b[q] = bound[q][0];
-    for (int w = 1; w < kDepBlock / 64; ++w) b[q] = min(b[q], bound[q][w]);
+    for (int w = 1; w < kBlk / 64; ++w) b[q] = min(b[q], bound[q][w]);
   }
   const int i0 = b[0], i1 = -b[1], j0 = b[2], j1 = -b[3];
   if (i0 == INT_MAX) return;  // no live charged particle in this block (uniform)
@@ -1085,7 +1091,7 @@ __device__ inline void deposit_block(const Grid& g, const CurrentPlanesT<T>& cp,
   const int rows = (i1 - i0 + 1) * kTJ;
 #pragma unroll
   for (int comp = 0; comp < 3; ++comp) {
-    for (int e = threadIdx.x; e < rows; e += kDepBlock) {
+    for (int e = threadIdx.x; e < rows; e += kBlk) {
       T val = (&tile[0][comp][0][0])[e];
 #pragma unroll
       for (int r = 1; r < kRep; ++r) val += (&tile[r][comp][0][0])[e];
@@ -1161,16 +1167,21 @@ __device__ inline void rank_claim(RankTable<kBits>& rt, int* __restrict__ counts
 // after the push is `cell`; its rank goes to i1p (the previous position is not
 // stored by the fused pass).  The table was cleared at the start of the
 // kernel and a block barrier (the deposit's) has passed since.
-constexpr int kPushRankBits = 8;  // 256 cells for the kDepBlock slots of a block
-static_assert((1 << (kPushRankBits - 1)) >= kDepBlock, "rank table too small for a block");
+// table bits for the dep_block<T>() slots of a block: twice as many cells
+template <class T>
+constexpr int push_rank_bits() { return sizeof(T) == 4 ? 7 : 8; }
+static_assert((1 << (push_rank_bits<float>() - 1)) >= dep_block<float>(), "rank table too small");
+static_assert((1 << (push_rank_bits<double>() - 1)) >= dep_block<double>(), "rank table too small");
 
+template <class T>
 __device__ inline void rank_fused(const Grid& g, int* __restrict__ i1p, int64_t k, int cell,
                                   int* __restrict__ counts) {
-  RankTable<kPushRankBits>& rt = block_rank_table<kPushRankBits>();
+  constexpr int kBits = push_rank_bits<T>();
+  RankTable<kBits>& rt = block_rank_table<kBits>();
   int local = 0, entry = -1;
   if (cell < g.n_r * g.n_th) entry = rank_insert(rt, cell, local);
   __syncthreads();
-  rank_claim<kPushRankBits, kDepBlock>(rt, counts);
+  rank_claim<kBits, dep_block<T>()>(rt, counts);
   if (entry >= 0) i1p[k] = rt.n[entry] + local;
 }
 
@@ -1195,7 +1206,7 @@ __global__ void __launch_bounds__(256) push_kernel_f32(Grid g, Tables tab, Gathe
 }
 
 template <class T, int SER>
-__global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, ParticleArraysT<T> P,
+__global__ void __launch_bounds__(dep_block<T>()) deposit_kernel(Grid g, Tables tab, ParticleArraysT<T> P,
                                                             CurrentPlanesT<T> cp) {
   const Move<T> mv = load_move(g, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   ContribT<T> c;
@@ -1208,31 +1219,31 @@ __global__ void __launch_bounds__(kDepBlock) deposit_kernel(Grid g, Tables tab, 
 // stored.  kRank: the pass also ranks the slots by their cell after the push
 // for the cell sort (rank_fused; counts: the sort's zeroed cell counters).
 template <int SER, bool kRank>
-__global__ void __launch_bounds__(kDepBlock) GRPIC_FP64_PUSH_OCCUPANCY
+__global__ void __launch_bounds__(dep_block<double>()) GRPIC_FP64_PUSH_OCCUPANCY
 push_deposit_kernel(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp, int* counts) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if constexpr (kRank) rank_clear(block_rank_table<kPushRankBits>());
+  if constexpr (kRank) rank_clear(block_rank_table<push_rank_bits<double>()>());
   const Move<double> mv = push_one<SER, false>(g, tab, fp, P, k);
   ContribT<double> c;
   const bool act = make_contrib<double, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
-  if constexpr (kRank) rank_fused(g, P.i1p, k, mv.cell, counts);
+  if constexpr (kRank) rank_fused<decltype(mv.u1)>(g, P.i1p, k, mv.cell, counts);
 }
 
 // library path in FP64 (coarse grids and the general quasi-spherical map):
 // the library exp and sincos and the map factors need more registers than the
 // series paths; three wavefronts per SIMD leave room for them without spills
 template <bool kRank>
-__global__ void __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(dep_block<double>()) __attribute__((amdgpu_waves_per_eu(3)))
 push_deposit_kernel_lib(Grid g, Tables tab, GatherPlanesT<double> fp, ParticleArrays P, CurrentPlanes cp,
                         int* counts) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if constexpr (kRank) rank_clear(block_rank_table<kPushRankBits>());
+  if constexpr (kRank) rank_clear(block_rank_table<push_rank_bits<double>()>());
   const Move<double> mv = push_one<0, false>(g, tab, fp, P, k);
   ContribT<double> c;
   const bool act = make_contrib<double, 0>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
-  if constexpr (kRank) rank_fused(g, P.i1p, k, mv.cell, counts);
+  if constexpr (kRank) rank_fused<decltype(mv.u1)>(g, P.i1p, k, mv.cell, counts);
 }
 
 template <int SER, bool kRank>
@@ -1240,18 +1251,18 @@ __device__ inline void push_deposit_f32(const Grid& g, const Tables& tab, const 
                                         const ParticleArraysT<float>& P, const CurrentPlanesT<float>& cp,
                                         int* counts) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if constexpr (kRank) rank_clear(block_rank_table<kPushRankBits>());
+  if constexpr (kRank) rank_clear(block_rank_table<push_rank_bits<float>()>());
   const Move<float> mv = push_one_f32<SER, false>(g, tab, fp, P, k);
   ContribT<float> c;
   const bool act = make_contrib<float, SER>(g, tab, mv, c);
   deposit_block(g, cp, act, c);
-  if constexpr (kRank) rank_fused(g, P.i1p, k, mv.cell, counts);
+  if constexpr (kRank) rank_fused<decltype(mv.u1)>(g, P.i1p, k, mv.cell, counts);
 }
 
 // series paths: 5 wavefronts per SIMD (96 VGPRs: the compiler's own
 // allocation without the rank pass; the rank pass would take it past 96)
 template <int SER, bool kRank>
-__global__ void __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(5))) push_deposit_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
+__global__ void __launch_bounds__(dep_block<float>()) __attribute__((amdgpu_waves_per_eu(5))) push_deposit_kernel_f32(Grid g, Tables tab, GatherPlanesT<float> fp,
                                                                      ParticleArraysT<float> P,
                                                                      CurrentPlanesT<float> cp, int* counts) {
   push_deposit_f32<SER, kRank>(g, tab, fp, P, cp, counts);
@@ -1261,7 +1272,7 @@ __global__ void __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(
 // wavefronts per SIMD (a few spilled registers), 11 % faster than the 4 that
 // its 100 VGPRs would give
 template <bool kRank>
-__global__ void __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(dep_block<float>()) __attribute__((amdgpu_waves_per_eu(5)))
 push_deposit_kernel_f32_lib(Grid g, Tables tab, GatherPlanesT<float> fp, ParticleArraysT<float> P,
                             CurrentPlanesT<float> cp, int* counts) {
   push_deposit_f32<0, kRank>(g, tab, fp, P, cp, counts);
