@@ -764,10 +764,11 @@ template <class T>
 constexpr int dep_tj() { return sizeof(T) == 4 ? 16 : 24; }
 constexpr int kTI = 8;
 constexpr int kDepRep = 2;  // copies of the deposit tile
-// lane-folding levels before the LDS atomics: quads in FP32, pairs in FP64
-// (measured: FP32 LDS atomics are the costlier, FP64 gains nothing past pairs)
+// lane-folding levels before the LDS atomics: pairs (measured: quads gave
+// nothing in FP64 and, once the FP32 blocks were 64 particles, cost 0.4 % of
+// the FP32 fused pass at 4096^2 and 16 per cell)
 template <class T>
-constexpr int dep_fold() { return sizeof(T) == 4 ? 2 : 1; }
+constexpr int dep_fold() { return 1; }
 
 template <class T>
 struct ContribT {
