@@ -753,15 +753,15 @@ __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 // gamma goes to the four nodes around the path midpoint.
 // Particles per block of the deposit passes and the LDS tile of kTI rows x
 // dep_tj<T>() columns, measured on the fused pass (blocks of 64, 128 and 256,
-// tiles of 6 or 8 rows and 16 to 48 columns): in single precision 64 with
-// 8 x 16 (at 4096^2 and 16 per cell -4.5 % against 256 with 8 x 48; 128 with
-// 8 x 24 -3 %), in double precision 128 with 8 x 24 (at 2048^2 and 90 per cell
-// -1 %, 64 with 8 x 16 +0.3 % there; at 512^2 64 and 128 within 2 %); six rows
-// often miss a block's footprint (+7 to +13 %)
+// tiles of 6 or 8 rows and 12 to 48 columns): in single precision 64 with
+// 8 x 16 (at 4096^2 and 16 per cell -4.5 % against 256 with 8 x 48), in double
+// precision 128 with 8 x 16 (at 2048^2 and 90 per cell -2 % against 256 with
+// 8 x 48, 64 with 8 x 16 +1 % there; at 512^2 64 and 128 within 2 %); six
+// rows often miss a block's footprint (+5 to +13 %)
 template <class T>
 constexpr int dep_block() { return sizeof(T) == 4 ? 64 : 128; }
 template <class T>
-constexpr int dep_tj() { return sizeof(T) == 4 ? 16 : 24; }
+constexpr int dep_tj() { return 16; }
 constexpr int kTI = 8;
 constexpr int kDepRep = 2;  // copies of the deposit tile
 // lane-folding levels before the LDS atomics: pairs (measured: quads gave
