@@ -1164,16 +1164,17 @@ __device__ inline void rank_claim(RankTable<kBits>& rt, int* __restrict__ counts
   __syncthreads();
 }
 
-// The rank pass of the sort inside a fused push + deposit block: slot k's key
-// after the push is `cell`; its rank goes to i1p (the previous position is not
-// stored by the fused pass).  The table was cleared at the start of the
-// kernel and a block barrier (the deposit's) has passed since.
-// table bits for the dep_block<T>() slots of a block: twice as many cells
+// Table bits for the dep_block<T>() slots of a fused block: twice as many
+// cells as slots.
 template <class T>
 constexpr int push_rank_bits() { return sizeof(T) == 4 ? 7 : 8; }
 static_assert((1 << (push_rank_bits<float>() - 1)) >= dep_block<float>(), "rank table too small");
 static_assert((1 << (push_rank_bits<double>() - 1)) >= dep_block<double>(), "rank table too small");
 
+// The rank pass of the sort inside a fused push + deposit block: slot k's key
+// after the push is `cell`; its rank goes to i1p (the previous position is not
+// stored by the fused pass).  The table was cleared at the start of the
+// kernel and a block barrier (the deposit's) has passed since.
 template <class T>
 __device__ inline void rank_fused(const Grid& g, int* __restrict__ i1p, int64_t k, int cell,
                                   int* __restrict__ counts) {
