@@ -2,7 +2,8 @@
 
 The oracle starts from the GPU's FP32 state and fields widened to FP64 (the
 same numbers), so the comparison measures what one FP32 step adds:
-  - one fused push + deposit pass (C3 recipe, a = 0.99, 32 ppc, 256^2):
+  - one fused push + deposit pass (C3 recipe, a = 0.99, 32 ppc, 256^2 and
+    512^2, the latter on the short-series kernel the benchmark times):
     per-particle momenta within 1e-5 of max(|u_i|, gamma c_i) (median within
     1e-6), positions within 3e-6 of a cell, currents per plane within 1e-5 of
     the plane's largest value;
@@ -93,14 +94,17 @@ def report(what, x_err, u_err, planes=None):
     print(msg)
 
 
-def test_fp32_fused_pass_against_oracle(O, G):
-    w, prm, c, Pg, Fg, Po, Fo = setup(O, G, "c3_2048", 256, charge_scale=1e-3)
+@pytest.mark.parametrize("n", [256, 512])
+def test_fp32_fused_pass_against_oracle(O, G, n):
+    """At 512^2 (dtheta small enough) the pass runs the short-series kernel
+    that the benchmark times, currents included."""
+    w, prm, c, Pg, Fg, Po, Fo = setup(O, G, "c3_2048", n, charge_scale=1e-3)
     c.push_deposit(Fg, Pg)
     O.push(prm, Fo, Po)
     O.deposit(prm, Fo, Po)
     x_err, u_err = particle_errors(w, Pg, Po)
     jerr = plane_errors(Fg, Fo, [18, 19, 20])
-    report("fused pass", x_err, u_err, jerr)
+    report(f"fused pass {n}^2", x_err, u_err, jerr)
     assert x_err.max() <= 3e-6
     assert u_err.max() <= 1e-5 and np.median(u_err) <= 1e-6
     assert max(jerr) <= 1e-5
