@@ -127,11 +127,12 @@ def test_fp32_push_against_oracle(O, G, iter_tol):
     assert u_err.max() <= 1e-5 and np.median(u_err) <= 1e-6
 
 
-@pytest.mark.parametrize("n", [128, 32])
+@pytest.mark.parametrize("n", [128, 32, 512])
 def test_fp32_full_step_against_oracle(O, G, n):
     """One full PIC step with 4 filter passes and an 8-cell absorbing layer
     (C5 recipe, kappa = 1e-3): fields and particles.  At 32^2 the current
-    filter takes its path for planes with fewer rows than a strip stages."""
+    filter takes its path for planes with fewer rows than a strip stages; at
+    512^2 the push runs the short-series kernel the benchmark times."""
     w, prm, c, Pg, Fg, Po, Fo = setup(O, G, "c5_4096", n, charge_scale=1e-3, n_absorb=8)
     c.step(Fg, Pg)
     O.step(prm, Fo, Po)
